@@ -1,0 +1,192 @@
+/*
+ * msp.h -- C ABI of the MI355X (gfx950) sparse general matrix-matrix product.
+ *
+ * The library computes C = A * B for sparse A (m x k) and B (k x n) stored in
+ * CSR (FSpGEMM Sec. II-A: values, column indices and row pointers), by the
+ * row-wise Gustavson method (FSpGEMM Sec. II-B, Fig. 1):
+ *
+ *     C(i,:) = sum over stored A(i,k) of  A(i,k) * B(k,:)
+ *
+ * where adding sparse rows merges equal column indices by adding their values
+ * (Sec. II-B, "sort and merge"; Algorithm 1).  The merge never tests a sum
+ * for zero, so C's structure is the structural union of the B rows that
+ * A(i,:) selects: an entry whose terms cancel to 0.0 is still stored.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers inside msp_csr / msp_csr_out are DEVICE pointers on the
+ *    handle's device.  Scalar sizes are host values.
+ *  - row_ptr is int64 with nrows + 1 entries (row_ptr[0] == 0); col is int32
+ *    (so ncols <= 2^31 - 1); values are FP32 or FP64, the same type for A, B
+ *    and C.
+ *  - Inputs must be canonical CSR: row_ptr non-decreasing, columns strictly
+ *    increasing inside each row and in [0, ncols).  With opts->validate = 1
+ *    the library checks this on the device and returns
+ *    MSP_ERR_UNSORTED_OR_DUP (or MSP_ERR_INVALID_ARG for out-of-range
+ *    indices) instead of computing.
+ *  - The output is canonical CSR with strictly increasing columns in a row.
+ *  - Inputs are borrowed: they must stay valid until the work queued on the
+ *    handle's stream has completed.  The handle owns its workspace and frees
+ *    it in msp_destroy.  Output arrays obtained through the allocator belong
+ *    to the caller.
+ *  - Every call is asynchronous on the handle's stream except for the points
+ *    named per entry point where the host must read a size back.
+ *  - No entry point throws, aborts or exits.  On error the return value says
+ *    what failed and msp_last_error() gives a message (thread-local); output
+ *    arrays already obtained from the allocator are released through its
+ *    free function.
+ *  - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSP_OK = 0,
+    MSP_ERR_INVALID_ARG = 1,     /* null pointer, negative size, bad option   */
+    MSP_ERR_SHAPE = 2,           /* A.ncols != B.nrows, or C shape mismatch    */
+    MSP_ERR_DTYPE = 3,           /* value types differ or are not FP32/FP64    */
+    MSP_ERR_UNSORTED_OR_DUP = 4, /* input rows not strictly increasing         */
+    MSP_ERR_OOM = 5,             /* allocator or workspace allocation failed   */
+    MSP_ERR_HIP = 6,             /* a HIP runtime call failed                  */
+    MSP_ERR_INDEX_OVERFLOW = 7,  /* a size does not fit the index types        */
+    MSP_ERR_UNSUPPORTED = 8      /* a feature not built for this device        */
+} msp_status;
+
+typedef enum { MSP_F32 = 0, MSP_F64 = 1 } msp_dtype;
+
+/* A read-only CSR operand (device pointers). */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    const int64_t* row_ptr;      /* nrows + 1 */
+    const int32_t* col;          /* nnz       */
+    const void* val;             /* nnz values of type dtype */
+    msp_dtype dtype;
+} msp_csr;
+
+/* The CSR result.  On input the caller sets row_ptr to a device buffer of
+ * nrows + 1 int64 (nrows = A.nrows) or leaves it NULL to have it allocated;
+ * col and val are always allocated by the library through the handle's
+ * allocator once nnz(C) is known.  On return all fields are filled in. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int64_t* row_ptr;
+    int32_t* col;
+    void* val;
+    msp_dtype dtype;
+} msp_csr_out;
+
+/* Device allocator used for outputs.  alloc returns a device pointer of at
+ * least `bytes` bytes usable on `stream` (NULL on failure); free releases
+ * it.  Python passes callbacks that create and drop torch tensors.  With no
+ * allocator set the library uses hipMalloc / hipFree. */
+typedef void* (*msp_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*msp_free_fn)(void* ctx, void* ptr, void* stream);
+
+/* Tuning of the per-bin accumulators.  Zero-initialised fields mean "use the
+ * library default".  See msp_autotune. */
+typedef struct {
+    int32_t hash_scale;     /* table slots = nextpow2(bound) << hash_scale (1..2) */
+    int32_t group_scale;    /* lanes per row = default << group_scale (0..2)      */
+    int32_t spill_nnz;      /* numeric rows with more nnz use the global path     */
+    int32_t block_rows;     /* symbolic rows with bound above this use block kernels */
+} msp_tuning;
+
+typedef struct {
+    int32_t validate;       /* 1: check inputs on the device first            */
+    int32_t force_spill;    /* 1: every nonempty row takes the global path    */
+    msp_tuning tuning;      /* zero: defaults (or the handle's tuned values)  */
+} msp_opts;
+
+typedef struct msp_handle msp_handle;
+
+/* ---- handle -------------------------------------------------------------- */
+
+/* Create a handle on `device` that queues all work on `hip_stream` (a
+ * hipStream_t; NULL means the device's null stream).  Selects the device,
+ * checks that it is gfx950 (MSP_ERR_UNSUPPORTED otherwise). */
+msp_status msp_create(msp_handle** h, int device, void* hip_stream);
+msp_status msp_destroy(msp_handle* h);
+msp_status msp_set_stream(msp_handle* h, void* hip_stream);
+msp_status msp_set_allocator(msp_handle* h, msp_alloc_fn alloc, msp_free_fn free_fn, void* ctx);
+/* Tuning used when a call's opts->tuning is all zero. */
+msp_status msp_set_tuning(msp_handle* h, const msp_tuning* t);
+msp_status msp_get_tuning(const msp_handle* h, msp_tuning* t);
+
+/* ---- the plain two-phase product ---------------------------------------- */
+
+/*
+ * C = A * B by row-wise Gustavson (FSpGEMM Sec. II-B), two phases:
+ *   1. per-row statistics: intermediate products prod_i = sum over A(i,k)
+ *      of nnz(B(k,:)), bound u_i = min(prod_i, n);
+ *   2. binning of rows by u_i;
+ *   3. symbolic pass: per-row structural union size row_nnz_i, with a
+ *      per-bin LDS hash of keys, an LDS bitmap, or a global bitmap;
+ *   4. device prefix sum -> C.row_ptr, nnz(C);
+ *   5. re-binning by row_nnz_i and the numeric pass: LDS hash accumulators
+ *      (FP64 sums for both value types) with an in-row column sort, or a
+ *      global dense accumulator with an ordered bitmap scan for rows too
+ *      large for LDS.
+ * Host synchronisation: two small device-to-host reads (bin counts, then
+ * nnz(C) with the numeric bin counts).  Values of C are rounded once from
+ * FP64 sums; they satisfy |c - exact| <= k * eps64 * sum|a||b| for a row
+ * with k terms.
+ */
+msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B,
+                      msp_csr_out* C, const msp_opts* opts);
+
+/* Only the symbolic part: row_nnz (device, A.nrows int32) and the total.
+ * Used to produce training targets for the predictor. */
+msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const msp_csr* B,
+                               int32_t* row_nnz, int64_t* nnz_total,
+                               const msp_opts* opts);
+
+/* Per-row features of A*B (device outputs, A.nrows rows each; any pointer
+ * may be NULL): prod (int64), and the 8 FP32 predictor features per row
+ * (row-major m x 8): log2(1+x) of nnz(A(i,:)), prod_i, min/mean/max
+ * nnz(B(k,:)) and ncols(B), then min(1, prod_i/n) and span_i/n, where
+ * span_i is the largest minus the smallest column index over the B rows
+ * A(i,:) selects. */
+msp_status msp_row_features(msp_handle* h, const msp_csr* A, const msp_csr* B,
+                            int64_t* prod, float* features);
+
+/* ---- timing ------------------------------------------------------------- */
+
+/* Phases timed with HIP events on the handle's stream when profiling is on. */
+enum {
+    MSP_PHASE_ROW_STATS = 0,   /* statistics + binning histogram          */
+    MSP_PHASE_SYMBOLIC = 1,    /* scatter + symbolic kernels              */
+    MSP_PHASE_SCAN = 2,        /* prefix sum + numeric binning histogram  */
+    MSP_PHASE_NUMERIC = 3,     /* scatter + numeric kernels               */
+    MSP_PHASE_PREDICT = 4,     /* predictor inference (learned form)      */
+    MSP_PHASE_FALLBACK = 5,    /* exact fallback rows (learned form)      */
+    MSP_PHASE_COMPACT = 6,     /* compaction (learned form)               */
+    MSP_PHASE_BATCH = 7,       /* one batched graph launch                */
+    MSP_NUM_PHASES = 8
+};
+
+typedef struct {
+    double ms[MSP_NUM_PHASES];       /* accumulated event time per phase     */
+    int64_t count[MSP_NUM_PHASES];   /* number of timed intervals per phase  */
+} msp_profile;
+
+/* Turn per-phase event timing on (1) or off (0); either way the
+ * accumulators are reset.  Timing adds two event records per phase. */
+msp_status msp_profile_enable(msp_handle* h, int on);
+/* Accumulated times of the intervals that have completed so far. */
+msp_status msp_profile_get(msp_handle* h, msp_profile* out);
+
+const char* msp_status_string(msp_status s);
+const char* msp_last_error(void);
+int msp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSP_H */

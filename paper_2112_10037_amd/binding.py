@@ -1,0 +1,266 @@
+"""Thin ctypes binding of libmsp.so (the C ABI in include/msp.h).
+
+Argument marshalling only: every step of the product runs in the library's
+HIP kernels.  PyTorch provides device memory (input copies and the output
+arrays, through the allocator callback) and the stream.  If the library is
+missing or cannot be loaded, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsp.so")
+
+MSP_F32, MSP_F64 = 0, 1
+STATUS = {0: "MSP_OK", 1: "MSP_ERR_INVALID_ARG", 2: "MSP_ERR_SHAPE", 3: "MSP_ERR_DTYPE",
+          4: "MSP_ERR_UNSORTED_OR_DUP", 5: "MSP_ERR_OOM", 6: "MSP_ERR_HIP",
+          7: "MSP_ERR_INDEX_OVERFLOW", 8: "MSP_ERR_UNSUPPORTED"}
+
+
+class MspError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class c_csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("dtype", ctypes.c_int)]
+
+
+class c_csr_out(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("dtype", ctypes.c_int)]
+
+
+class c_tuning(ctypes.Structure):
+    _fields_ = [("hash_scale", ctypes.c_int32), ("group_scale", ctypes.c_int32),
+                ("spill_nnz", ctypes.c_int32), ("block_rows", ctypes.c_int32)]
+
+
+class c_opts(ctypes.Structure):
+    _fields_ = [("validate", ctypes.c_int32), ("force_spill", ctypes.c_int32),
+                ("tuning", c_tuning)]
+
+
+NUM_PHASES = 8
+PHASES = ["row_stats", "symbolic", "scan", "numeric", "predict", "fallback", "compact", "batch"]
+
+
+class c_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NUM_PHASES), ("count", ctypes.c_int64 * NUM_PHASES)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+# (name, restype, argtypes) of every symbol include/msp.h declares
+SIGNATURES = [
+    ("msp_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    ("msp_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("msp_set_stream", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("msp_set_allocator", ctypes.c_int, [ctypes.c_void_p, ALLOC_FN, FREE_FN, ctypes.c_void_p]),
+    ("msp_set_tuning", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_tuning)]),
+    ("msp_get_tuning", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_tuning)]),
+    ("msp_spgemm", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
+                                  ctypes.POINTER(c_csr_out), ctypes.POINTER(c_opts)]),
+    ("msp_spgemm_symbolic", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
+                                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(c_opts)]),
+    ("msp_row_features", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    ("msp_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("msp_profile_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_profile)]),
+    ("msp_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("msp_last_error", ctypes.c_char_p, []),
+    ("msp_version", ctypes.c_int, []),
+]
+
+
+def load():
+    """Load libmsp.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2112_10037_amd/build.py "
+                              "(or __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise MspError(rc, load().msp_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# device matrices
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DeviceCSR:
+    """CSR on the GPU: int64 row_ptr, int32 col, f32/f64 val torch tensors."""
+    nrows: int
+    ncols: int
+    row_ptr: "object"
+    col: "object"
+    val: "object"
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @property
+    def dtype_code(self) -> int:
+        import torch
+        return MSP_F64 if self.val.dtype == torch.float64 else MSP_F32
+
+    @classmethod
+    def from_host(cls, m, device="cuda") -> "DeviceCSR":
+        import torch
+        return cls(int(m.nrows), int(m.ncols),
+                   torch.from_numpy(np.ascontiguousarray(m.row_ptr, np.int64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(m.col, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(m.val)).to(device))
+
+    def to_host(self):
+        from .gen import CSR
+        return CSR(self.nrows, self.ncols, self.row_ptr.cpu().numpy(), self.col.cpu().numpy(),
+                   self.val.cpu().numpy())
+
+    def c(self) -> c_csr:
+        return c_csr(self.nrows, self.ncols, self.nnz, self.row_ptr.data_ptr(),
+                     self.col.data_ptr() if self.nnz else None,
+                     self.val.data_ptr() if self.nnz else None, self.dtype_code)
+
+
+def _opts(validate=False, force_spill=False, tuning=None) -> c_opts:
+    t = c_tuning(*(tuning or (0, 0, 0, 0)))
+    return c_opts(int(bool(validate)), int(bool(force_spill)), t)
+
+
+class Handle:
+    """One library handle on one device, queueing work on torch's current
+    stream (or the stream given)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._lib = load()
+        self.device = device
+        self._torch = torch
+        self._h = ctypes.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = s
+        _check(self._lib.msp_create(ctypes.byref(self._h), device, ctypes.c_void_p(s.cuda_stream)))
+        self._live = {}
+        self._alloc_cb = ALLOC_FN(self._alloc)
+        self._free_cb = FREE_FN(self._free)
+        _check(self._lib.msp_set_allocator(self._h, self._alloc_cb, self._free_cb, None))
+
+    # allocator callbacks: torch tensors kept alive until handed out or freed
+    def _alloc(self, ctx, nbytes, stream):
+        try:
+            t = self._torch.empty(max(int(nbytes), 1), dtype=self._torch.uint8,
+                                  device=f"cuda:{self.device}")
+        except RuntimeError:
+            return None
+        p = t.data_ptr()
+        self._live[p] = t
+        return p
+
+    def _free(self, ctx, ptr, stream):
+        self._live.pop(ptr, None)
+
+    def _take(self, ptr, n, dtype):
+        t = self._live.pop(ptr)
+        return t[: n * self._torch.empty(0, dtype=dtype).element_size()].view(dtype)
+
+    def close(self):
+        if self._h:
+            self._lib.msp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, on: bool = True):
+        """Enable (and reset) per-phase HIP-event timing."""
+        _check(self._lib.msp_profile_enable(self._h, int(bool(on))))
+
+    def profile_get(self) -> dict:
+        """{phase: (total ms, intervals)} for every phase timed so far."""
+        p = c_profile()
+        _check(self._lib.msp_profile_get(self._h, ctypes.byref(p)))
+        return {name: (p.ms[i], int(p.count[i])) for i, name in enumerate(PHASES)}
+
+    def set_tuning(self, tuning):
+        _check(self._lib.msp_set_tuning(self._h, ctypes.byref(c_tuning(*tuning))))
+
+    def get_tuning(self):
+        t = c_tuning()
+        _check(self._lib.msp_get_tuning(self._h, ctypes.byref(t)))
+        return (t.hash_scale, t.group_scale, t.spill_nnz, t.block_rows)
+
+    def spgemm(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False,
+               tuning=None, row_ptr=None) -> DeviceCSR:
+        """C = A * B (plain two-phase path)."""
+        torch = self._torch
+        a, b = A.c(), B.c()
+        out = c_csr_out()
+        rp = row_ptr if row_ptr is not None else torch.empty(A.nrows + 1, dtype=torch.int64,
+                                                              device=f"cuda:{self.device}")
+        out.row_ptr = rp.data_ptr()
+        o = _opts(validate, force_spill, tuning)
+        _check(self._lib.msp_spgemm(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(out),
+                                    ctypes.byref(o)))
+        nnz = int(out.nnz)
+        vdt = torch.float64 if out.dtype == MSP_F64 else torch.float32
+        if nnz > 0:
+            col = self._take(out.col, nnz, torch.int32)
+            val = self._take(out.val, nnz, vdt)
+        else:
+            col = torch.empty(0, dtype=torch.int32, device=rp.device)
+            val = torch.empty(0, dtype=vdt, device=rp.device)
+        return DeviceCSR(A.nrows, B.ncols, rp, col, val)
+
+    def symbolic(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False, tuning=None):
+        """(row_nnz int32 tensor, nnz(C)) from the symbolic pass alone."""
+        torch = self._torch
+        a, b = A.c(), B.c()
+        rn = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        tot = ctypes.c_int64()
+        o = _opts(validate, force_spill, tuning)
+        _check(self._lib.msp_spgemm_symbolic(self._h, ctypes.byref(a), ctypes.byref(b),
+                                             ctypes.c_void_p(rn.data_ptr()), ctypes.byref(tot),
+                                             ctypes.byref(o)))
+        return rn[: A.nrows], int(tot.value)
+
+    def row_features(self, A: DeviceCSR, B: DeviceCSR):
+        """(prod int64 [m], features float32 [m, 8])."""
+        torch = self._torch
+        m = A.nrows
+        prod = torch.empty(max(m, 1), dtype=torch.int64, device=f"cuda:{self.device}")
+        feat = torch.empty((max(m, 1), 8), dtype=torch.float32, device=f"cuda:{self.device}")
+        a, b = A.c(), B.c()
+        _check(self._lib.msp_row_features(self._h, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.c_void_p(prod.data_ptr()),
+                                          ctypes.c_void_p(feat.data_ptr())))
+        return prod[:m], feat[:m]

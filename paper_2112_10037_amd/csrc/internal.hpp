@@ -1,0 +1,103 @@
+// Internal host-side declarations shared by the translation units of the
+// library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "msp.h"
+#include "types.hpp"
+
+namespace msp {
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    msp_status ensure(size_t need);
+    void release();
+    template <typename T> T* as() const { return (T*)ptr; }
+};
+
+// One accumulator class of a bin: the kernel family and its shape.
+enum class Kind { None, Group, Block, Bitmap, Dense };
+
+struct BinSpec {
+    Kind kind = Kind::None;
+    int lanes = 0;      // G for Group, BS for Block/Bitmap/Dense
+    int slots = 0;      // T (hash slots) for Group/Block
+};
+
+struct BinPlan {
+    BinTable table;                 // thresholds, consumed by the kernels
+    BinSpec spec[kMaxBins + 1];     // spec[b] for b in 1..nb (nb = the global path)
+};
+
+struct ExtraState;                  // learned / batched state (other units)
+
+// Per-phase event timing: intervals are recorded on the handle's stream and
+// folded into the accumulators once they have completed.
+struct Profiler {
+    bool on = false;
+    double ms[MSP_NUM_PHASES] = {};
+    int64_t count[MSP_NUM_PHASES] = {};
+    struct Pending { int phase; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int open_phase = -1;
+    hipEvent_t open_ev = nullptr;
+    hipEvent_t get();
+    void begin(int phase, hipStream_t s);
+    void end(hipStream_t s);
+    void collect();          // fold completed intervals (after a sync)
+    void reset();
+    void release();
+};
+
+}  // namespace msp
+
+struct msp_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    msp_alloc_fn alloc = nullptr;
+    msp_free_fn free_fn = nullptr;
+    void* alloc_ctx = nullptr;
+    int num_cu = 256;
+    int lds_per_block = 65536;
+    msp_tuning tuning{};
+    msp::DevBuf info, u, rnnz, perm, tiles, dslab, gbm, sbm, prod;
+    size_t dslab_cols = 0;          // ncols the dense slabs were zeroed for
+    int dslab_count = 0;
+    msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
+    msp::ExtraState* extra = nullptr;
+    msp::Profiler prof;
+};
+
+namespace msp {
+
+msp_status fail(msp_status s, const char* fmt, ...);
+msp_status hip_fail(hipError_t e, const char* what);
+msp_status check_csr(const msp_csr* M, const char* name);
+msp_tuning default_tuning();
+msp_status check_tuning(msp_tuning* t);
+msp_tuning effective_tuning(const msp_handle* h, const msp_opts* o);
+msp_status configure_kernels(msp_handle* h);
+void release_extra(msp_handle* h);
+
+BinPlan symbolic_plan(const msp_tuning& t, bool force_spill);
+BinPlan numeric_plan(const msp_tuning& t, bool force_spill);
+
+// The plain pipeline pieces, reused by the learned and batched forms.
+msp_status read_info(msp_handle* h);
+msp_status zero_info(msp_handle* h);
+msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                         int64_t* prod_out, float* feat);
+msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                             const int* counts_host, int32_t* row_nnz);
+msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan);
+msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                            const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
+                            int32_t* ccol, void* cval, const int32_t* perm_override, int perm_rows);
+
+}  // namespace msp

@@ -1,0 +1,326 @@
+// Host side of the C ABI declared in include/msp.h: handle, workspace,
+// bin tables and the dispatch of the per-bin kernels of kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "msp.h"
+#include "internal.hpp"
+
+using namespace msp;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace msp {
+thread_local char g_last_error[512] = "";
+
+msp_status fail(msp_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+msp_status hip_fail(hipError_t e, const char* what) {
+    return fail(MSP_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+}  // namespace msp
+
+extern "C" const char* msp_last_error(void) { return g_last_error; }
+
+extern "C" const char* msp_status_string(msp_status s) {
+    switch (s) {
+        case MSP_OK: return "ok";
+        case MSP_ERR_INVALID_ARG: return "invalid argument";
+        case MSP_ERR_SHAPE: return "shape mismatch";
+        case MSP_ERR_DTYPE: return "value type mismatch";
+        case MSP_ERR_UNSORTED_OR_DUP: return "input columns not strictly increasing";
+        case MSP_ERR_OOM: return "out of memory";
+        case MSP_ERR_HIP: return "HIP runtime error";
+        case MSP_ERR_INDEX_OVERFLOW: return "size exceeds index types";
+        case MSP_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+extern "C" int msp_version(void) { return 1; }
+
+// ---------------------------------------------------------------------------
+// handle and workspace
+// ---------------------------------------------------------------------------
+namespace msp {
+
+msp_status DevBuf::ensure(size_t need) {
+    if (need <= bytes) return MSP_OK;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+    }
+    size_t want = std::max(need, (size_t)256);
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(MSP_ERR_OOM, "workspace allocation of %zu bytes failed", want);
+    }
+    bytes = want;
+    return MSP_OK;
+}
+
+void __attribute__((weak)) release_extra(msp_handle*) {}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+}  // namespace msp
+
+static void* default_alloc(void*, size_t bytes, void*) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+static void default_free(void*, void* p, void*) {
+    if (p) (void)hipFree(p);
+}
+
+extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
+    if (!out) return fail(MSP_ERR_INVALID_ARG, "msp_create: null handle pointer");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(MSP_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, ndev);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MSP_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+    msp_handle* h = new (std::nothrow) msp_handle();
+    if (!h) return fail(MSP_ERR_OOM, "msp_create: host allocation failed");
+    h->device = device;
+    h->stream = (hipStream_t)stream;
+    h->alloc = default_alloc;
+    h->free_fn = default_free;
+    h->alloc_ctx = nullptr;
+    h->num_cu = prop.multiProcessorCount;
+    h->lds_per_block = (int)prop.sharedMemPerBlock;
+    h->tuning = default_tuning();
+    msp_status s = h->info.ensure(sizeof(DevInfo));
+    if (s != MSP_OK) { delete h; return s; }
+    if ((e = hipHostMalloc((void**)&h->hinfo, sizeof(DevInfo), hipHostMallocDefault)) != hipSuccess) {
+        h->info.release();
+        delete h;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    if ((s = configure_kernels(h)) != MSP_OK) {
+        (void)hipHostFree(h->hinfo);
+        h->info.release();
+        delete h;
+        return s;
+    }
+    *out = h;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_destroy(msp_handle* h) {
+    if (!h) return MSP_OK;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
+    for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->dslab, &h->gbm, &h->sbm, &h->prod})
+        b->release();
+    release_extra(h);
+    h->prof.release();
+    if (h->hinfo) (void)hipHostFree(h->hinfo);
+    delete h;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_set_stream(msp_handle* h, void* stream) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    h->stream = (hipStream_t)stream;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_set_allocator(msp_handle* h, msp_alloc_fn a, msp_free_fn f, void* ctx) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    if ((a == nullptr) != (f == nullptr)) return fail(MSP_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+    h->alloc = a ? a : default_alloc;
+    h->free_fn = f ? f : default_free;
+    h->alloc_ctx = a ? ctx : nullptr;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_set_tuning(msp_handle* h, const msp_tuning* t) {
+    if (!h || !t) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    msp_tuning c = *t;
+    msp_status s = check_tuning(&c);
+    if (s != MSP_OK) return s;
+    h->tuning = c;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_get_tuning(const msp_handle* h, msp_tuning* t) {
+    if (!h || !t) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    *t = h->tuning;
+    return MSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+namespace msp {
+
+msp_status check_csr(const msp_csr* M, const char* name) {
+    if (!M) return fail(MSP_ERR_INVALID_ARG, "%s is NULL", name);
+    if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0) return fail(MSP_ERR_INVALID_ARG, "%s has a negative size", name);
+    if (M->nrows >= INT32_MAX || M->ncols > INT32_MAX)
+        return fail(MSP_ERR_INDEX_OVERFLOW, "%s: rows and columns must fit int32 (%lld x %lld)", name,
+                    (long long)M->nrows, (long long)M->ncols);
+    if (M->dtype != MSP_F32 && M->dtype != MSP_F64) return fail(MSP_ERR_DTYPE, "%s: dtype must be MSP_F32 or MSP_F64", name);
+    if (!M->row_ptr) return fail(MSP_ERR_INVALID_ARG, "%s.row_ptr is NULL", name);
+    if (M->nnz > 0 && (!M->col || !M->val)) return fail(MSP_ERR_INVALID_ARG, "%s.col/val is NULL with nnz > 0", name);
+    return MSP_OK;
+}
+
+msp_tuning default_tuning() {
+    msp_tuning t;
+    t.hash_scale = 1;
+    t.group_scale = 0;
+    t.spill_nnz = 4096;
+    t.block_rows = 128;
+    return t;
+}
+
+msp_status check_tuning(msp_tuning* t) {
+    const msp_tuning d = default_tuning();
+    if (t->hash_scale == 0) t->hash_scale = d.hash_scale;
+    if (t->spill_nnz == 0) t->spill_nnz = d.spill_nnz;
+    if (t->block_rows == 0) t->block_rows = d.block_rows;
+    if (t->hash_scale < 1 || t->hash_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.hash_scale must be 1 or 2");
+    if (t->group_scale < 0 || t->group_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.group_scale must be 0..2");
+    if (t->spill_nnz < 64 || t->spill_nnz > 4096) return fail(MSP_ERR_INVALID_ARG, "tuning.spill_nnz must be in 64..4096");
+    if (t->block_rows != 32 && t->block_rows != 64 && t->block_rows != 128)
+        return fail(MSP_ERR_INVALID_ARG, "tuning.block_rows must be 32, 64 or 128");
+    return MSP_OK;
+}
+
+msp_tuning effective_tuning(const msp_handle* h, const msp_opts* o) {
+    if (!o) return h->tuning;
+    const msp_tuning& t = o->tuning;
+    if (t.hash_scale == 0 && t.group_scale == 0 && t.spill_nnz == 0 && t.block_rows == 0) return h->tuning;
+    msp_tuning c = t;
+    if (check_tuning(&c) != MSP_OK) return h->tuning;
+    return c;
+}
+
+}  // namespace msp
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+namespace msp {
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void Profiler::begin(int phase, hipStream_t s) {
+    if (!on) return;
+    if (open_phase >= 0) end(s);
+    open_ev = get();
+    if (!open_ev) return;
+    open_phase = phase;
+    (void)hipEventRecord(open_ev, s);
+}
+
+void Profiler::end(hipStream_t s) {
+    if (!on || open_phase < 0) return;
+    hipEvent_t b = get();
+    if (b) {
+        (void)hipEventRecord(b, s);
+        pending.push_back({open_phase, open_ev, b});
+    } else {
+        pool.push_back(open_ev);
+    }
+    open_phase = -1;
+    open_ev = nullptr;
+}
+
+void Profiler::collect() {
+    std::vector<Pending> keep;
+    for (const Pending& p : pending) {
+        if (hipEventQuery(p.b) != hipSuccess) {
+            (void)hipGetLastError();
+            keep.push_back(p);
+            continue;
+        }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+            ms[p.phase] += t;
+            count[p.phase] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        pool.push_back(p.a);
+        pool.push_back(p.b);
+    }
+    pending.swap(keep);
+}
+
+void Profiler::reset() {
+    for (int i = 0; i < MSP_NUM_PHASES; ++i) { ms[i] = 0; count[i] = 0; }
+}
+
+void Profiler::release() {
+    for (const Pending& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    if (open_ev) (void)hipEventDestroy(open_ev);
+    pending.clear();
+    pool.clear();
+    open_ev = nullptr;
+    open_phase = -1;
+}
+
+}  // namespace msp
+
+extern "C" msp_status msp_profile_enable(msp_handle* h, int on) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
+    h->prof.collect();
+    h->prof.reset();
+    h->prof.on = on != 0;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_profile_get(msp_handle* h, msp_profile* out) {
+    if (!h || !out) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    h->prof.collect();
+    for (int i = 0; i < MSP_NUM_PHASES; ++i) { out->ms[i] = h->prof.ms[i]; out->count[i] = h->prof.count[i]; }
+    return MSP_OK;
+}

@@ -1,0 +1,519 @@
+// The plain two-phase product: bin plans, per-bin kernel dispatch and the
+// msp_spgemm / msp_spgemm_symbolic / msp_row_features entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "msp.h"
+
+using namespace msp;
+
+namespace msp {
+
+static int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// bin plans
+// ---------------------------------------------------------------------------
+// Sub-wave lane groups cover bounds up to block_rows (16, 32, 64, 128 with
+// 8, 16, 32, 64 lanes, scaled by group_scale); workgroup kernels cover the
+// middle; the last bin is the global path.  Hash tables get
+// nextpow2(bound) << hash_scale slots, so they are at most half full.
+
+static void add_bin(BinPlan& p, int umax, BinSpec s) {
+    const int b = p.table.nb;          // bins are appended after bin 0
+    p.table.umax[b] = umax;
+    p.spec[b] = s;
+    p.table.nb = b + 1;
+}
+
+static void add_group_bins(BinPlan& p, const msp_tuning& t, int limit) {
+    static const int umax[4] = {16, 32, 64, 128};
+    static const int g0[4] = {8, 16, 32, 64};
+    for (int i = 0; i < 4; ++i) {
+        if (umax[i] > limit) break;
+        const int T = next_pow2(umax[i]) << t.hash_scale;
+        int G = std::min(64, g0[i] << t.group_scale);
+        G = std::min(G, T / 2);
+        add_bin(p, umax[i], BinSpec{Kind::Group, G, T});
+    }
+}
+
+BinPlan symbolic_plan(const msp_tuning& t, bool force_spill) {
+    BinPlan p;
+    memset(&p.table, 0, sizeof(p.table));
+    p.table.nb = 1;                    // bin 0: u == 0
+    if (!force_spill) {
+        add_group_bins(p, t, t.block_rows);
+        static const int umax[4] = {512, 2048, 8192, 16384};
+        static const int bs[4] = {256, 512, 1024, 1024};
+        int last = p.table.umax[p.table.nb - 1];
+        for (int i = 0; i < 4; ++i) {
+            int T = std::min(32768, next_pow2(umax[i]) << t.hash_scale);
+            int u = std::min(umax[i], T / 2);
+            if (u <= last) continue;
+            add_bin(p, u, BinSpec{Kind::Block, bs[i], T});
+            last = u;
+        }
+    }
+    p.spec[p.table.nb] = BinSpec{Kind::Bitmap, 1024, 0};
+    return p;
+}
+
+BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
+    BinPlan p;
+    memset(&p.table, 0, sizeof(p.table));
+    p.table.nb = 1;
+    if (!force_spill) {
+        add_group_bins(p, t, std::min(t.block_rows, t.spill_nnz));
+        int last = p.table.umax[p.table.nb - 1];
+        int list[4] = {512, 2048, 4096, t.spill_nnz};
+        std::sort(list, list + 4);
+        for (int i = 0; i < 4; ++i) {
+            const int u0 = list[i];
+            if (u0 > t.spill_nnz || u0 <= last) continue;
+            const int bs = u0 <= 512 ? 256 : (u0 <= 2048 ? 512 : 1024);
+            const int T = std::min(8192, next_pow2(u0) << t.hash_scale);
+            const int u = std::min(u0, T / 2);
+            if (u <= last) continue;
+            add_bin(p, u, BinSpec{Kind::Block, bs, T});
+            last = u;
+        }
+    }
+    p.spec[p.table.nb] = BinSpec{Kind::Dense, 1024, 0};
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// kernel tables
+// ---------------------------------------------------------------------------
+constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense kernels
+
+#define MSP_GROUP_SHAPES(X) \
+    X(8, 32) X(16, 32) X(8, 64) X(16, 64) X(32, 64) X(16, 128) X(32, 128) X(64, 128) \
+    X(32, 256) X(64, 256) X(64, 512)
+#define MSP_SYM_BLOCK_SHAPES(X) \
+    X(256, 1024) X(256, 2048) X(512, 4096) X(512, 8192) X(1024, 16384) X(1024, 32768)
+#define MSP_NUM_BLOCK_SHAPES(X) \
+    X(256, 512) X(256, 1024) X(256, 2048) X(512, 2048) X(512, 4096) X(512, 8192) X(1024, 8192)
+
+template <typename VT>
+static void* dense_kernel(bool lds) {
+    return lds ? (void*)k_num_dense<1024, true, VT> : (void*)k_num_dense<1024, false, VT>;
+}
+
+msp_status configure_kernels(msp_handle* h) {
+    // allow the bitmap kernels the device's full LDS for their dynamic part
+    const int dyn = std::max(0, h->lds_per_block - kLdsReserve);
+    void* fns[] = {(void*)k_sym_bitmap<1024, true>, dense_kernel<float>(true), dense_kernel<double>(true)};
+    for (void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
+        }
+    }
+    return MSP_OK;
+}
+
+static int group_grid(int rows, int G) {
+    const int ng = 256 / G;
+    int blocks = (rows + ng - 1) / ng;
+    return (blocks + 7) & ~7;           // multiple of 8 for the XCD-aware order
+}
+
+static msp_status launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return MSP_OK;
+}
+
+// symbolic kernel of one bin over `rows` rows listed in perm (or all rows)
+static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
+                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz) {
+    if (rows <= 0) return MSP_OK;
+    DevInfo* info = h->info.as<DevInfo>();
+    const int m = (int)A->nrows;
+    hipStream_t st = h->stream;
+    if (s.kind == Kind::Group) {
+        const int grid = group_grid(rows, s.lanes);
+#define X(G, T)                                                                                 \
+    if (s.lanes == G && s.slots == T) {                                                         \
+        k_sym_group<G, T><<<grid, 256, 0, st>>>(rows, perm, m, A->row_ptr, A->col, B->row_ptr, \
+                                                B->col, rnnz, info);                           \
+        return launch_check("k_sym_group");                                                     \
+    }
+        MSP_GROUP_SHAPES(X)
+#undef X
+    } else if (s.kind == Kind::Block) {
+        const int grid = std::min(rows, 4 * h->num_cu);
+#define X(BS, T)                                                                                  \
+    if (s.lanes == BS && s.slots == T) {                                                          \
+        k_sym_block<BS, T><<<grid, BS, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, \
+                                                rnnz, info);                                      \
+        return launch_check("k_sym_block");                                                       \
+    }
+        MSP_SYM_BLOCK_SHAPES(X)
+#undef X
+    } else if (s.kind == Kind::Bitmap) {
+        const long long n = B->ncols;
+        const long long words = (n + 31) / 32;
+        const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
+        const int grid = std::min(rows, (lds ? 1 : 2) * h->num_cu);
+        uint32_t* slab = nullptr;
+        if (!lds) {
+            msp_status r = h->sbm.ensure((size_t)grid * words * 4);
+            if (r != MSP_OK) return r;
+            slab = h->sbm.as<uint32_t>();
+        }
+        if (lds)
+            k_sym_bitmap<1024, true><<<grid, 1024, words * 4, st>>>(rows, perm, n, A->row_ptr, A->col,
+                                                                    B->row_ptr, B->col, rnnz, slab, info);
+        else
+            k_sym_bitmap<1024, false><<<grid, 1024, 0, st>>>(rows, perm, n, A->row_ptr, A->col,
+                                                             B->row_ptr, B->col, rnnz, slab, info);
+        return launch_check("k_sym_bitmap");
+    }
+    return fail(MSP_ERR_UNSUPPORTED, "no symbolic kernel for bin shape (%d, %d)", s.lanes, s.slots);
+}
+
+template <typename VT>
+static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
+                                   const msp_csr* A, const msp_csr* B, const int64_t* crp,
+                                   int32_t* ccol, VT* cval) {
+    DevInfo* info = h->info.as<DevInfo>();
+    hipStream_t st = h->stream;
+    const VT* av = (const VT*)A->val;
+    const VT* bv = (const VT*)B->val;
+    if (s.kind == Kind::Group) {
+        const int grid = group_grid(rows, s.lanes);
+#define X(G, T)                                                                                   \
+    if (s.lanes == G && s.slots == T) {                                                           \
+        k_num_group<G, T, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
+                                                    B->col, bv, crp, ccol, cval, info);          \
+        return launch_check("k_num_group");                                                       \
+    }
+        MSP_GROUP_SHAPES(X)
+#undef X
+    } else if (s.kind == Kind::Block) {
+        const int grid = std::min(rows, 4 * h->num_cu);
+#define X(BS, T)                                                                                  \
+    if (s.lanes == BS && s.slots == T) {                                                          \
+        k_num_block<BS, T, VT><<<grid, BS, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
+                                                    B->col, bv, crp, ccol, cval, info);          \
+        return launch_check("k_num_block");                                                       \
+    }
+        MSP_NUM_BLOCK_SHAPES(X)
+#undef X
+    } else if (s.kind == Kind::Dense) {
+        const long long n = B->ncols;
+        const long long words = (n + 31) / 32;
+        const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
+        // one slab per resident workgroup; keep the arena under 16 GiB
+        long long cap = (16LL << 30) / std::max(1LL, n * 8);
+        int nslab = (int)std::max(1LL, std::min<long long>(h->num_cu, cap));
+        if (h->dslab_cols != (size_t)n || h->dslab_count < nslab) {
+            msp_status r = h->dslab.ensure((size_t)nslab * (size_t)n * 8);
+            if (r != MSP_OK) return r;
+            hipError_t e = hipMemsetAsync(h->dslab.ptr, 0, (size_t)nslab * (size_t)n * 8, st);
+            if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(dense slab)");
+            if (!lds) {
+                r = h->gbm.ensure((size_t)nslab * words * 4);
+                if (r != MSP_OK) return r;
+                e = hipMemsetAsync(h->gbm.ptr, 0, (size_t)nslab * words * 4, st);
+                if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(bitmap slab)");
+            }
+            h->dslab_cols = (size_t)n;
+            h->dslab_count = nslab;
+        }
+        const int grid = std::min(rows, nslab);
+        if (lds)
+            k_num_dense<1024, true, VT><<<grid, 1024, words * 4, st>>>(
+                rows, perm, n, A->row_ptr, A->col, av, B->row_ptr, B->col, bv, crp, ccol, cval,
+                h->dslab.as<double>(), nullptr, info);
+        else
+            k_num_dense<1024, false, VT><<<grid, 1024, 0, st>>>(
+                rows, perm, n, A->row_ptr, A->col, av, B->row_ptr, B->col, bv, crp, ccol, cval,
+                h->dslab.as<double>(), h->gbm.as<uint32_t>(), info);
+        return launch_check("k_num_dense");
+    }
+    return fail(MSP_ERR_UNSUPPORTED, "no numeric kernel for bin shape (%d, %d)", s.lanes, s.slots);
+}
+
+static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
+                                 const msp_csr* A, const msp_csr* B, const int64_t* crp,
+                                 int32_t* ccol, void* cval) {
+    if (rows <= 0) return MSP_OK;
+    if (A->dtype == MSP_F64) return launch_numeric_t<double>(h, s, rows, perm, A, B, crp, ccol, (double*)cval);
+    return launch_numeric_t<float>(h, s, rows, perm, A, B, crp, ccol, (float*)cval);
+}
+
+// ---------------------------------------------------------------------------
+// pipeline pieces
+// ---------------------------------------------------------------------------
+msp_status zero_info(msp_handle* h) {
+    const int words = (int)(sizeof(DevInfo) / 4);
+    k_zero_words<<<1, 256, 0, h->stream>>>((int*)h->info.ptr, words);
+    return launch_check("k_zero_words");
+}
+
+msp_status read_info(msp_handle* h) {
+    hipError_t e = hipMemcpyAsync(h->hinfo, h->info.ptr, sizeof(DevInfo), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(info)");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (h->prof.on) h->prof.collect();
+    return MSP_OK;
+}
+
+msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                         int64_t* prod_out, float* feat) {
+    const int m = (int)A->nrows;
+    msp_status s = h->u.ensure((size_t)std::max(m, 1) * 4);
+    if (s != MSP_OK) return s;
+    if (m == 0) return MSP_OK;
+    const int grid = (m + 255) / 256;
+    if (feat)
+        k_row_stats<true><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
+                                                      h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
+                                                      plan.table, h->info.as<DevInfo>(), feat);
+    else
+        k_row_stats<false><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
+                                                       h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
+                                                       plan.table, h->info.as<DevInfo>(), nullptr);
+    return launch_check("k_row_stats");
+}
+
+// Launch the kernels of every nonempty bin.  With a single nonempty bin the
+// rows are taken in their natural order (no scatter, and every kernel also
+// handles the rows of bin 0); otherwise row ids are scattered into per-bin
+// lists first.
+static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                           const int* counts, const int32_t* key, int* cursor, bool numeric,
+                           const int64_t* crp, int32_t* ccol, void* cval, int32_t* rnnz) {
+    const int m = (int)A->nrows;
+    const int nb = plan.table.nb;
+    int nonempty = 0, only = -1;
+    for (int b = 1; b <= nb; ++b)
+        if (counts[b] > 0) { ++nonempty; only = b; }
+    if (nonempty == 0) return MSP_OK;
+    if (nonempty == 1) {
+        return numeric ? launch_numeric(h, plan.spec[only], m, nullptr, A, B, crp, ccol, cval)
+                       : launch_symbolic(h, plan.spec[only], m, nullptr, A, B, rnnz);
+    }
+    msp_status s = h->perm.ensure((size_t)m * 4);
+    if (s != MSP_OK) return s;
+    int32_t* perm = h->perm.as<int32_t>();
+    DevInfo* info = h->info.as<DevInfo>();
+    k_scatter<<<(m + 255) / 256, 256, 0, h->stream>>>(m, key, plan.table,
+                                                     numeric ? info->num_count : info->sym_count, cursor, perm);
+    if ((s = launch_check("k_scatter")) != MSP_OK) return s;
+    int start = counts[0];
+    for (int b = 1; b <= nb; ++b) {
+        if (counts[b] > 0) {
+            s = numeric ? launch_numeric(h, plan.spec[b], counts[b], perm + start, A, B, crp, ccol, cval)
+                        : launch_symbolic(h, plan.spec[b], counts[b], perm + start, A, B, rnnz);
+            if (s != MSP_OK) return s;
+        }
+        start += counts[b];
+    }
+    return MSP_OK;
+}
+
+msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                             const int* counts_host, int32_t* row_nnz) {
+    return run_bins(h, A, B, plan, counts_host, h->u.as<int32_t>(), h->info.as<DevInfo>()->cursor, false,
+                    nullptr, nullptr, nullptr, row_nnz);
+}
+
+msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan) {
+    const int tiles = (m + kScanTile - 1) / kScanTile;
+    msp_status s = h->tiles.ensure((size_t)std::max(tiles, 1) * 8);
+    if (s != MSP_OK) return s;
+    BinTable bt;
+    memset(&bt, 0, sizeof(bt));
+    if (plan) bt = plan->table;
+    if (tiles > 0) {
+        k_scan_tiles<<<tiles, kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<long long>());
+        if ((s = launch_check("k_scan_tiles")) != MSP_OK) return s;
+    }
+    k_scan_tile_sums<<<1, kScanBS, 0, h->stream>>>(tiles, h->tiles.as<long long>(), h->info.as<DevInfo>());
+    if ((s = launch_check("k_scan_tile_sums")) != MSP_OK) return s;
+    k_scan_apply<<<std::max(tiles, 1), kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<long long>(), row_ptr,
+                                                               bt, h->info.as<DevInfo>());
+    return launch_check("k_scan_apply");
+}
+
+msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
+                            const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
+                            int32_t* ccol, void* cval, const int32_t*, int) {
+    return run_bins(h, A, B, plan, counts_host, row_nnz, h->info.as<DevInfo>()->cursor, true, crp, ccol,
+                    cval, nullptr);
+}
+
+static msp_status check_pair(const msp_csr* A, const msp_csr* B) {
+    msp_status s;
+    if ((s = check_csr(A, "A")) != MSP_OK) return s;
+    if ((s = check_csr(B, "B")) != MSP_OK) return s;
+    if (A->ncols != B->nrows)
+        return fail(MSP_ERR_SHAPE, "A is %lld x %lld but B is %lld x %lld", (long long)A->nrows,
+                    (long long)A->ncols, (long long)B->nrows, (long long)B->ncols);
+    if (A->dtype != B->dtype) return fail(MSP_ERR_DTYPE, "A and B value types differ");
+    return MSP_OK;
+}
+
+static msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B) {
+    msp_status s;
+    if ((s = zero_info(h)) != MSP_OK) return s;
+    for (const msp_csr* M : {A, B}) {
+        if (M->nrows == 0) continue;
+        k_validate<<<(int)((M->nrows + 255) / 256), 256, 0, h->stream>>>(M->nrows, M->ncols, M->nnz, M->row_ptr,
+                                                                         M->col, h->info.as<DevInfo>());
+        if ((s = launch_check("k_validate")) != MSP_OK) return s;
+    }
+    if ((s = read_info(h)) != MSP_OK) return s;
+    const int err = h->hinfo->err;
+    if (err & kErrRange) return fail(MSP_ERR_INVALID_ARG, "input CSR has an index out of range or a non-monotone row_ptr");
+    if (err & kErrUnsorted) return fail(MSP_ERR_UNSORTED_OR_DUP, "input CSR has unsorted or duplicate columns");
+    return MSP_OK;
+}
+
+static msp_status device_error(int err) {
+    if (err & kErrProbe) return fail(MSP_ERR_HIP, "internal: hash probe bound exceeded");
+    if (err & kErrCount) return fail(MSP_ERR_HIP, "internal: numeric row count differs from symbolic count");
+    return MSP_OK;
+}
+
+// symbolic phase up to row_nnz (shared by msp_spgemm and msp_spgemm_symbolic)
+static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr* B, const msp_opts* opts,
+                                 const msp_tuning& t) {
+    const int m = (int)A->nrows;
+    msp_status s;
+    if ((s = h->rnnz.ensure((size_t)std::max(m, 1) * 4)) != MSP_OK) return s;
+    const BinPlan sp = symbolic_plan(t, opts && opts->force_spill);
+    if ((s = zero_info(h)) != MSP_OK) return s;
+    h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
+    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr)) != MSP_OK) return s;
+    h->prof.end(h->stream);
+    if ((s = read_info(h)) != MSP_OK) return s;
+    int counts[kMaxBins + 1];
+    memcpy(counts, h->hinfo->sym_count, sizeof(counts));
+    h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
+    s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>());
+    h->prof.end(h->stream);
+    return s;
+}
+
+}  // namespace msp
+
+extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C,
+                                 const msp_opts* opts) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    if (!C) return fail(MSP_ERR_INVALID_ARG, "C is NULL");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const msp_tuning t = effective_tuning(h, opts);
+    const int m = (int)A->nrows;
+    if (opts && opts->validate && (s = validate_inputs(h, A, B)) != MSP_OK) return s;
+
+    bool own_rp = false;
+    if (!C->row_ptr) {
+        C->row_ptr = (int64_t*)h->alloc(h->alloc_ctx, (size_t)(m + 1) * 8, h->stream);
+        if (!C->row_ptr) return fail(MSP_ERR_OOM, "allocation of C.row_ptr failed");
+        own_rp = true;
+    }
+    C->col = nullptr;
+    C->val = nullptr;
+    auto cleanup = [&](msp_status st) {
+        if (C->col) h->free_fn(h->alloc_ctx, C->col, h->stream);
+        if (C->val) h->free_fn(h->alloc_ctx, C->val, h->stream);
+        C->col = nullptr;
+        C->val = nullptr;
+        if (own_rp) { h->free_fn(h->alloc_ctx, C->row_ptr, h->stream); C->row_ptr = nullptr; }
+        return st;
+    };
+
+    if ((s = symbolic_phase(h, A, B, opts, t)) != MSP_OK) return cleanup(s);
+    const BinPlan np = numeric_plan(t, opts && opts->force_spill);
+    h->prof.begin(MSP_PHASE_SCAN, h->stream);
+    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), C->row_ptr, &np)) != MSP_OK) return cleanup(s);
+    h->prof.end(h->stream);
+    if ((s = read_info(h)) != MSP_OK) return cleanup(s);
+    if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
+    const long long nnz = h->hinfo->nnz;
+    int counts[kMaxBins + 1];
+    memcpy(counts, h->hinfo->num_count, sizeof(counts));
+    const size_t vsz = A->dtype == MSP_F64 ? 8 : 4;
+    C->nrows = m;
+    C->ncols = B->ncols;
+    C->nnz = nnz;
+    C->dtype = A->dtype;
+    if (nnz > 0) {
+        C->col = (int32_t*)h->alloc(h->alloc_ctx, (size_t)nnz * 4, h->stream);
+        C->val = h->alloc(h->alloc_ctx, (size_t)nnz * vsz, h->stream);
+        if (!C->col || !C->val) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
+        // the scatter cursors are reused by the numeric binning
+        k_zero_words<<<1, 64, 0, h->stream>>>(h->info.as<DevInfo>()->cursor, kMaxBins + 1);
+        if ((s = launch_check("k_zero_words")) != MSP_OK) return cleanup(s);
+        h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
+        if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col, C->val,
+                                  nullptr, 0)) != MSP_OK)
+            return cleanup(s);
+        h->prof.end(h->stream);
+        if ((s = read_info(h)) != MSP_OK) return cleanup(s);
+        if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
+    }
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const msp_csr* B, int32_t* row_nnz,
+                                          int64_t* nnz_total, const msp_opts* opts) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    if (!row_nnz && A->nrows > 0) return fail(MSP_ERR_INVALID_ARG, "row_nnz is NULL");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const msp_tuning t = effective_tuning(h, opts);
+    if (opts && opts->validate && (s = validate_inputs(h, A, B)) != MSP_OK) return s;
+    if ((s = symbolic_phase(h, A, B, opts, t)) != MSP_OK) return s;
+    const int m = (int)A->nrows;
+    if (m > 0) {
+        e = hipMemcpyAsync(row_nnz, h->rnnz.ptr, (size_t)m * 4, hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(row_nnz)");
+    }
+    // total via the scan's tile sums (no row_ptr output needed)
+    const int tiles = (m + kScanTile - 1) / kScanTile;
+    if ((s = h->tiles.ensure((size_t)std::max(tiles, 1) * 8)) != MSP_OK) return s;
+    if (tiles > 0) k_scan_tiles<<<tiles, kScanBS, 0, h->stream>>>(m, h->rnnz.as<int32_t>(), h->tiles.as<long long>());
+    k_scan_tile_sums<<<1, kScanBS, 0, h->stream>>>(tiles, h->tiles.as<long long>(), h->info.as<DevInfo>());
+    if ((s = launch_check("k_scan")) != MSP_OK) return s;
+    if ((s = read_info(h)) != MSP_OK) return s;
+    if ((s = device_error(h->hinfo->err)) != MSP_OK) return s;
+    if (nnz_total) *nnz_total = h->hinfo->nnz;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_row_features(msp_handle* h, const msp_csr* A, const msp_csr* B, int64_t* prod,
+                                       float* features) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int m = (int)A->nrows;
+    if ((s = h->rnnz.ensure((size_t)std::max(m, 1) * 4)) != MSP_OK) return s;
+    BinPlan none;
+    memset(&none, 0, sizeof(none));
+    if ((s = zero_info(h)) != MSP_OK) return s;
+    return run_row_stats(h, A, B, none, prod, features ? features : nullptr);
+}

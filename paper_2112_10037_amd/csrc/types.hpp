@@ -1,0 +1,43 @@
+// Types and constants shared by the device kernels and the host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msp {
+
+constexpr int kWave = 64;
+constexpr int kMaxBins = 16;
+constexpr int32_t kEmpty = -1;
+
+// error bits reported in DevInfo::err
+constexpr int kErrProbe = 1;      // a hash probe sequence exceeded the table (bug guard)
+constexpr int kErrUnsorted = 2;   // input columns not strictly increasing
+constexpr int kErrRange = 4;      // input index out of range / row_ptr not monotone
+constexpr int kErrCount = 8;      // numeric count disagrees with the symbolic count
+
+struct DevInfo {
+    long long nnz;                 // nnz(C) after the scan
+    long long total_prod;          // sum of intermediate products
+    int err;
+    int pad;
+    int sym_count[kMaxBins + 1];   // rows per symbolic bin
+    int num_count[kMaxBins + 1];   // rows per numeric bin
+    int cursor[kMaxBins + 1];      // scatter cursors
+};
+
+// Bin b (1 <= b < nb) holds rows with umax[b-1] < u <= umax[b]; bin 0 holds
+// u == 0; bin nb holds everything above umax[nb-1] (the global path).
+struct BinTable {
+    int nb;
+    int umax[kMaxBins];
+};
+
+__device__ __forceinline__ int bin_of(const BinTable& t, long long u) {
+    if (u <= 0) return 0;
+    for (int b = 1; b < t.nb; ++b)
+        if (u <= t.umax[b]) return b;
+    return t.nb;
+}
+
+}  // namespace msp

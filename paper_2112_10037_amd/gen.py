@@ -107,9 +107,10 @@ def empty(nrows: int, ncols: int, dtype=np.float64) -> CSR:
 def erdos_renyi(nrows: int, ncols: int, k, seed: int, dtype=np.float64) -> CSR:
     """Each row gets exactly k[i] distinct columns, uniform without replacement.
 
-    ``k`` is an int or a length-nrows array.  Rows are drawn as kmax uniform
-    columns, redrawn while any column repeats; row i keeps the first k[i] in
-    draw order (a uniform k[i]-subset), then sorts them.  Values U[-1, 1].
+    ``k`` is an int or a length-nrows array.  Each row draws kmax uniform
+    columns; a row in which a column repeats is redrawn without replacement
+    (``Generator.choice``).  Row i keeps the first k[i] in draw order (a
+    uniform k[i]-subset), then sorts them.  Values U[-1, 1].
     """
     rng = np.random.default_rng(seed)
     kk = np.full(nrows, int(k), dtype=np.int64) if np.isscalar(k) else np.asarray(k, np.int64)
@@ -119,12 +120,11 @@ def erdos_renyi(nrows: int, ncols: int, k, seed: int, dtype=np.float64) -> CSR:
     if nrows == 0 or kmax == 0:
         return empty(nrows, ncols, dtype)
     draw = rng.integers(0, ncols, size=(nrows, kmax), dtype=np.int64)
-    while True:
+    if kmax > 1:
         s = np.sort(draw, axis=1)
-        bad = np.nonzero(np.any(s[:, 1:] == s[:, :-1], axis=1))[0] if kmax > 1 else np.zeros(0, np.int64)
-        if bad.size == 0:
-            break
-        draw[bad] = rng.integers(0, ncols, size=(bad.size, kmax), dtype=np.int64)
+        bad = np.nonzero(np.any(s[:, 1:] == s[:, :-1], axis=1))[0]
+        for r in bad:               # rows with a repeat: an exact draw without replacement
+            draw[r] = rng.choice(ncols, size=kmax, replace=False)
     keep = np.arange(kmax)[None, :] < kk[:, None]
     draw = np.where(keep, draw, np.iinfo(np.int64).max)
     draw.sort(axis=1)          # kept columns sorted first, sentinels last

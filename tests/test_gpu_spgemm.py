@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Structure (row_ptr, col) must be identical; values must satisfy
+|c - o| <= tol * sum_k |a_ik||b_kj| with tol 1e-12 (FP64) or 1e-5 (FP32).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_10037_amd import binding, gen
+
+from gpu_util import check_full, check_rows, run, to_dev
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hh = binding.Handle(0)
+    yield hh
+    hh.close()
+
+
+def _rand(rng, m, k, density, dtype=np.float64):
+    pat = rng.random((m, k)) < density
+    return gen.from_dense(np.where(pat, rng.uniform(-1, 1, (m, k)), 0.0).astype(dtype), pattern=pat)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_hand_products(h, dtype):
+    cases = json.load(open(os.path.join(GOLDEN, "hand_products.json")))["cases"]
+    for c in cases:
+        d = c["A"]
+        A = gen.CSR(d["nrows"], d["ncols"], np.array(d["row_ptr"], np.int64),
+                    np.array(d["col"], np.int32), np.array(d["val"], dtype))
+        if c["B"] == "A":
+            B = A
+        else:
+            d = c["B"]
+            B = gen.CSR(d["nrows"], d["ncols"], np.array(d["row_ptr"], np.int64),
+                        np.array(d["col"], np.int32), np.array(d["val"], dtype))
+        C = run(h, A, B).to_host()
+        assert C.row_ptr.tolist() == c["C"]["row_ptr"], c["name"]
+        assert C.col.tolist() == c["C"]["col"], c["name"]
+        assert C.val.tolist() == [float(v) for v in c["C"]["val"]], c["name"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_dense_tiny(h, seed, dtype):
+    rng = np.random.default_rng(seed)
+    m, k, n = (int(x) for x in rng.integers(1, 49, 3))
+    A = _rand(rng, m, k, rng.uniform(0, 0.6), dtype)
+    B = _rand(rng, k, n, rng.uniform(0, 0.6), dtype)
+    check_full(h, A, B)
+
+
+def test_er_4096_exact8(h):
+    """ER 4096 x 4096, exactly 8 nonzeros per row, FP64, seed 0 (C = A*A)."""
+    A = gen.erdos_renyi(4096, 4096, 8, seed=0)
+    err = check_full(h, A, A)
+    print(f"max |c-o|/bound = {err:.3e}")
+
+
+def test_laplacian_2d_1024_exact(h):
+    """2D 5-point Laplacian on 1024^2, FP64: every value is a small integer, so
+    the GPU sums must equal the oracle's bit for bit."""
+    A = gen.laplacian_2d(1024)
+    C = run(h, A, A).to_host()
+    rp, col, val, bnd = oracle.spgemm(A, A)
+    assert np.array_equal(C.row_ptr, rp) and np.array_equal(C.col, col)
+    assert np.array_equal(C.val, val)
+    assert C.nnz == 13_611_012
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("scale", [10, 13])
+def test_rmat_skewed(h, scale, dtype):
+    A = gen.rmat(scale, 16 << scale, seed=3, dtype=dtype)
+    check_full(h, A, A)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_forced_spill(h, dtype):
+    A = gen.rmat(11, 16 << 11, seed=5, dtype=dtype)
+    check_full(h, A, A, force_spill=True)
+    B = gen.erdos_renyi(3000, 3000, 7, seed=2, dtype=dtype)
+    check_full(h, B, B, force_spill=True)
+
+
+def test_hub_rows_lds_bitmap_and_dense(h):
+    """A few rows whose union exceeds every LDS table: symbolic bitmap (LDS)
+    and numeric global dense accumulator."""
+    rng = np.random.default_rng(8)
+    n = 20000
+    B = gen.erdos_renyi(n, n, 8, seed=9)
+    k = np.full(40, 3, dtype=np.int64)
+    k[[0, 7, 39]] = [3000, 6000, 1500]
+    A = gen.erdos_renyi(40, n, k, seed=10)
+    check_full(h, A, B)
+
+
+def test_wide_matrix_global_bitmap(h):
+    """ncols = 2^21: the n-bit bitmap no longer fits LDS (global slabs)."""
+    n = 1 << 21
+    B = gen.erdos_renyi(4000, n, 60, seed=11)
+    k = np.full(16, 5, dtype=np.int64)
+    k[[1, 9]] = [900, 2500]
+    A = gen.erdos_renyi(16, 4000, k, seed=12)
+    check_full(h, A, B)
+
+
+def test_degenerate_shapes(h):
+    import torch
+    for (m, k, n) in [(0, 0, 0), (0, 5, 3), (4, 0, 3), (4, 5, 0), (3, 3, 3)]:
+        A = gen.empty(m, k)
+        B = gen.empty(k, n)
+        C = run(h, A, B)
+        assert C.nnz == 0 and C.row_ptr.cpu().tolist() == [0] * (m + 1)
+    # one column, one row, empty rows mixed in
+    A = gen.from_dense(np.ones((5, 1)))
+    B = gen.from_dense(np.full((1, 1), 2.0))
+    check_full(h, A, B)
+    A = gen.from_dense(np.array([[0, 0, 0], [1.0, 0, 2], [0, 0, 0]]))
+    check_full(h, A, A)
+
+
+def test_all_zero_values_keep_structure(h):
+    A = gen.erdos_renyi(500, 500, 6, seed=4)
+    A.val[:] = 0.0
+    C = run(h, A, A).to_host()
+    rp, col, _, _ = oracle.spgemm(A, A)
+    assert np.array_equal(C.row_ptr, rp) and np.array_equal(C.col, col)
+    assert np.all(C.val == 0.0)
+
+
+def test_hash_hostile_columns(h):
+    """Columns that are all multiples of 4096 (congruent mod every table size)."""
+    n = 1 << 22
+    rng = np.random.default_rng(6)
+    rows = 300
+    k = rng.integers(1, 60, rows)
+    cols = [np.sort(rng.choice(n // 4096, size=int(x), replace=False)) * 4096 for x in k]
+    rp = np.zeros(rows + 1, np.int64)
+    np.cumsum(k, out=rp[1:])
+    B = gen.CSR(rows, n, rp, np.concatenate(cols).astype(np.int32), rng.uniform(-1, 1, int(rp[-1])))
+    A = gen.erdos_renyi(200, rows, 12, seed=7)
+    check_full(h, A, B)
+
+
+def test_rectangular_chain(h):
+    rng = np.random.default_rng(21)
+    A = _rand(rng, 300, 700, 0.02)
+    B = _rand(rng, 700, 90, 0.05)
+    check_full(h, A, B)
+
+
+def test_transpose_identity_structure(h):
+    import scipy.sparse as sp
+    A = gen.rmat(10, 8 << 10, seed=13, dtype=np.float64)
+    B = gen.erdos_renyi(1024, 1024, 5, seed=14)
+
+    def T(M):
+        s = sp.csr_matrix((M.val, M.col, M.row_ptr), shape=(M.nrows, M.ncols)).T.tocsr()
+        s.sort_indices()
+        return gen.CSR(M.ncols, M.nrows, s.indptr.astype(np.int64), s.indices.astype(np.int32), s.data)
+
+    C = run(h, A, B).to_host()
+    Ct = run(h, T(B), T(A)).to_host()
+    CT = T(C)
+    assert np.array_equal(CT.row_ptr, Ct.row_ptr) and np.array_equal(CT.col, Ct.col)
+    ref = oracle.spgemm(T(B), T(A))
+    oracle.compare(Ct.row_ptr, Ct.col, Ct.val, ref, 1e-12)
+
+
+@pytest.mark.parametrize("tuning", [(1, 0, 4096, 128), (2, 0, 4096, 128), (1, 1, 1024, 64),
+                                    (2, 2, 256, 32), (1, 2, 512, 128)])
+def test_tuning_variants_same_result(h, tuning):
+    A = gen.rmat(12, 12 << 12, seed=15, dtype=np.float64)
+    check_full(h, A, A, tuning=tuning)
+
+
+def test_validation_errors(h):
+    A = gen.erdos_renyi(50, 50, 4, seed=1)
+    bad = gen.CSR(A.nrows, A.ncols, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    bad.col[1], bad.col[2] = bad.col[2], bad.col[1]       # unsorted row 0
+    with pytest.raises(binding.MspError) as e:
+        h.spgemm(to_dev(bad), to_dev(A), validate=True)
+    assert e.value.name == "MSP_ERR_UNSORTED_OR_DUP"
+    oor = gen.CSR(A.nrows, A.ncols, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    oor.col[-1] = 50                                      # out of range
+    with pytest.raises(binding.MspError) as e:
+        h.spgemm(to_dev(oor), to_dev(A), validate=True)
+    assert e.value.name == "MSP_ERR_INVALID_ARG"
+    B = gen.erdos_renyi(40, 40, 4, seed=2)
+    with pytest.raises(binding.MspError) as e:
+        h.spgemm(to_dev(A), to_dev(B))
+    assert e.value.name == "MSP_ERR_SHAPE"
+    with pytest.raises(binding.MspError) as e:
+        h.spgemm(to_dev(A), to_dev(A.astype(np.float32)))
+    assert e.value.name == "MSP_ERR_DTYPE"
+    check_full(h, A, A, validate=True)
+
+
+def test_symbolic_and_features(h):
+    A = gen.rmat(12, 16 << 12, seed=17, dtype=np.float64)
+    dA = to_dev(A)
+    rn, tot = h.symbolic(dA, dA)
+    ref = oracle.row_nnz(A, A)
+    assert np.array_equal(rn.cpu().numpy(), ref) and tot == ref.sum()
+    prod, feat = h.row_features(dA, dA)
+    st = oracle.row_stats(A, A)
+    assert np.array_equal(prod.cpu().numpy(), st["prod"])
+    f_ref = oracle.features(A, A)
+    assert np.allclose(feat.cpu().numpy(), f_ref, rtol=2e-6, atol=2e-6)
+
+
+def test_repeat_calls_deterministic_structure(h):
+    A = gen.rmat(12, 16 << 12, seed=19, dtype=np.float32)
+    dA = to_dev(A)
+    C1 = h.spgemm(dA, dA)
+    C2 = h.spgemm(dA, dA)
+    import torch
+    assert torch.equal(C1.row_ptr, C2.row_ptr) and torch.equal(C1.col, C2.col)
+
+
+@pytest.mark.slow
+def test_rmat_2p20_fp32_sampled(h):
+    """R-MAT 2^20 vertices, 16 x 2^20 edges, (0.57, 0.19, 0.19, 0.05), FP32
+    (0, 1], seed 1: full-size run, parity on sampled rows (the heaviest rows,
+    random rows, rows straddling the bins) and sortedness of every row."""
+    import torch
+    A = gen.rmat(20, 16 << 20, seed=1, dtype=np.float32)
+    dA = to_dev(A)
+    C = h.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    st = oracle.row_stats(A, A)
+    rng = np.random.default_rng(0)
+    heavy = np.argsort(st["prod"])[-12:]
+    rows = np.concatenate([heavy, rng.integers(0, A.nrows, 300),
+                           np.nonzero(st["prod"] == 0)[0][:5]])
+    worst = check_rows(C, A, A, rows)
+    print(f"nnz(C) = {C.nnz}, max |c-o|/bound on sampled rows = {worst:.3e}")
+    # every row strictly increasing, checked in chunks on the device
+    rp = C.row_ptr
+    nnz = C.nnz
+    step = 1 << 28
+    starts = torch.zeros(nnz, dtype=torch.bool, device=rp.device) if nnz < (1 << 31) else None
+    for s in range(0, nnz - 1, step):
+        e = min(nnz - 1, s + step)
+        d = C.col[s + 1:e + 1].to(torch.int64) - C.col[s:e].to(torch.int64)
+        bad = torch.nonzero(d <= 0).flatten() + s + 1      # positions where col does not increase
+        if bad.numel():
+            # all such positions must be row starts
+            idx = torch.searchsorted(rp, bad, right=False)
+            assert torch.all(rp[idx] == bad), "a row is not strictly increasing"
+    del starts
