@@ -80,6 +80,10 @@ def main():
     ap.add_argument("--workload", default="laplacian2d_1024")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="hash_scale,group_scale,spill_nnz,block_rows,merge_k (default: library's)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -95,7 +99,8 @@ def main():
     products = int(st["prod"].sum())
     dA = binding.DeviceCSR.from_host(A, "cuda:0")
     h = binding.Handle(0)
-    stream = torch.cuda.current_stream()
+    if args.tuning:
+        h.set_tuning(tuple(int(x) for x in args.tuning.split(",")))
 
     for _ in range(args.warmup):
         C = h.spgemm(dA, dA)
@@ -136,7 +141,8 @@ def main():
         "dtype": "f64" if A.val.dtype == np.float64 else "f32",
         "data": "synthetic",
         "config": {"workload": desc, "rows": A.nrows, "nnz_a": A.nnz, "products": products,
-                   "nnz_c": nnz_c, "path": "plain two-phase"},
+                   "nnz_c": nnz_c, "path": "plain two-phase",
+                   "tuning": list(h.get_tuning())},
         "roofline": {"bound": "hbm", "kernel": "numeric pass",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -147,6 +153,14 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, products, args.cpu_seconds)
+    if args.calibrate_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 8
     h.close()
     print(json.dumps(out))
 

@@ -94,8 +94,12 @@ typedef void (*msp_free_fn)(void* ctx, void* ptr, void* stream);
 typedef struct {
     int32_t hash_scale;     /* table slots = nextpow2(bound) << hash_scale (1..2) */
     int32_t group_scale;    /* lanes per row = default << group_scale (0..2)      */
-    int32_t spill_nnz;      /* numeric rows with more nnz use the global path     */
-    int32_t block_rows;     /* symbolic rows with bound above this use block kernels */
+    int32_t spill_nnz;      /* numeric rows with more nnz use the global path
+                               (a power of two, 256..4096)                       */
+    int32_t block_rows;     /* rows with bound above this (32, 64 or 128) use
+                               one workgroup per row                            */
+    int32_t merge_k;        /* rows with bound <= 32 and at most merge_k A
+                               entries use the per-lane merge (4 or 8; -1: off) */
 } msp_tuning;
 
 typedef struct {

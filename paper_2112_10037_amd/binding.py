@@ -43,7 +43,8 @@ class c_csr_out(ctypes.Structure):
 
 class c_tuning(ctypes.Structure):
     _fields_ = [("hash_scale", ctypes.c_int32), ("group_scale", ctypes.c_int32),
-                ("spill_nnz", ctypes.c_int32), ("block_rows", ctypes.c_int32)]
+                ("spill_nnz", ctypes.c_int32), ("block_rows", ctypes.c_int32),
+                ("merge_k", ctypes.c_int32)]
 
 
 class c_opts(ctypes.Structure):
@@ -150,7 +151,7 @@ class DeviceCSR:
 
 
 def _opts(validate=False, force_spill=False, tuning=None) -> c_opts:
-    t = c_tuning(*(tuning or (0, 0, 0, 0)))
+    t = c_tuning(*(tuning or (0, 0, 0, 0, 0)))
     return c_opts(int(bool(validate)), int(bool(force_spill)), t)
 
 
@@ -217,7 +218,7 @@ class Handle:
     def get_tuning(self):
         t = c_tuning()
         _check(self._lib.msp_get_tuning(self._h, ctypes.byref(t)))
-        return (t.hash_scale, t.group_scale, t.spill_nnz, t.block_rows)
+        return (t.hash_scale, t.group_scale, t.spill_nnz, t.block_rows, t.merge_k)
 
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False,
                tuning=None, row_ptr=None) -> DeviceCSR:

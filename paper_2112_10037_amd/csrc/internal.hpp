@@ -21,11 +21,12 @@ struct DevBuf {
 };
 
 // One accumulator class of a bin: the kernel family and its shape.
-enum class Kind { None, Group, Block, Bitmap, Dense };
+enum class Kind { None, Merge, Batch, Group, Block, Bitmap, Dense };
 
 struct BinSpec {
     Kind kind = Kind::None;
-    int lanes = 0;      // G for Group, BS for Block/Bitmap/Dense
+    int lanes = 0;      // K lists for Merge, rows per batch R for Batch, G for Group,
+                        // BS for Block/Bitmap/Dense
     int slots = 0;      // T (hash slots) for Group/Block
 };
 
@@ -85,6 +86,8 @@ msp_tuning effective_tuning(const msp_handle* h, const msp_opts* o);
 msp_status configure_kernels(msp_handle* h);
 void release_extra(msp_handle* h);
 
+int count_unsupported_plans(int verbose);
+void sum_parts(const int (*part)[kPartStride], int out[kNB]);
 BinPlan symbolic_plan(const msp_tuning& t, bool force_spill);
 BinPlan numeric_plan(const msp_tuning& t, bool force_spill);
 

@@ -150,15 +150,33 @@ static __global__ void k_zero_words(int* p, int n) {
 // Per-row statistics and symbolic binning
 // ===========================================================================
 //
-// One wave per 64 consecutive rows.  Rows with at most kShortRow entries are
-// summed by their own lane; longer rows are summed by the whole wave, one
-// after another, so hub rows of power-law matrices do not serialise a lane.
-// Outputs: u_i = min(prod_i, ncols(B)) (int32), optional int64 prod_i,
-// optional min/max B-row length and column span, the per-bin histogram of
-// u_i, the total product count, and row_nnz_i = 0 for rows with u_i = 0.
+// Add the wave's rows to an LDS histogram with one atomic per distinct bin
+// present in the wave; returns the lane's rank among the workgroup's rows of
+// its bin (b < 0: no row).  Wave-uniform control flow required.
+__device__ __forceinline__ int wave_hist_add(int* hist, int b) {
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(b >= 0);
+    int rank = 0;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int bl = __shfl(b, leader);
+        const uint64_t same = __ballot(b == bl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&hist[bl], __builtin_popcountll(same));
+        base = __shfl(base, leader);
+        if (b == bl) rank = base + __builtin_popcountll(same & ((1ull << lane) - 1));
+        todo &= ~same;
+    }
+    return rank;
+}
 
-constexpr int kShortRow = 32;
-
+// One wave per 64 consecutive rows.  The wave walks the A entries of its
+// rows flattened (lane = entry), so a row's B-row lengths are gathered in
+// parallel; each entry finds its row by binary search in the 65 row
+// pointers held in LDS and adds into the row's LDS accumulator.
+// Outputs: u_i = min(prod_i, ncols(B)) (int32), optional int64 prod_i and
+// FP32 features, row_nnz_i = 0 for rows with u_i = 0, and the bin
+// histogram of u_i (partitioned global counters).
 template <bool FEAT>
 __global__ void __launch_bounds__(256)
 k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
@@ -166,129 +184,110 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
             int32_t* __restrict__ u_out, int64_t* __restrict__ prod_out,
             int32_t* __restrict__ row_nnz, BinTable bins, DevInfo* info,
             float* __restrict__ feat) {
-    __shared__ int hist[kMaxBins + 1];
-    __shared__ long long prod_acc;
-    if (threadIdx.x <= kMaxBins) hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) prod_acc = 0;
-    __syncthreads();
-
+    __shared__ int hist[kNB];
+    __shared__ long long s_rp[4][65];
+    __shared__ unsigned long long s_prod[4][64];
+    __shared__ int s_mn[FEAT ? 4 : 1][64], s_mx[FEAT ? 4 : 1][64];
+    __shared__ int s_lo[FEAT ? 4 : 1][64], s_hi[FEAT ? 4 : 1][64];
     const int lane = threadIdx.x & 63;
-    const long long row = (long long)blockIdx.x * 256 + threadIdx.x;
-    const bool valid = row < m;
-    long long a0 = 0, a1 = 0;
-    if (valid) { a0 = arp[row]; a1 = arp[row + 1]; }
-    const long long len = a1 - a0;
-
-    long long s = 0, mn = -1, mx = 0, lo = -1, hi = -1;
-    if (valid && len <= kShortRow) {
-        for (long long p = a0; p < a1; ++p) {
+    const int w = threadIdx.x >> 6;
+    if (threadIdx.x < kNB) hist[threadIdx.x] = 0;
+    const long long r0 = ((long long)blockIdx.x * 4 + w) * 64;
+    const int nr = r0 < m ? (int)(m - r0 < 64 ? m - r0 : 64) : 0;
+    // row pointers of the wave's rows: entries 0..nr (nr + 1 <= 65 values)
+    if (lane < nr) s_rp[w][lane] = arp[r0 + lane];
+    if (lane == 0 && nr > 0) s_rp[w][nr] = arp[r0 + nr];
+    s_prod[w][lane] = 0;
+    if constexpr (FEAT) {
+        s_mn[w][lane] = 0x7fffffff; s_mx[w][lane] = 0; s_lo[w][lane] = 0x7fffffff; s_hi[w][lane] = -1;
+    }
+    __syncthreads();
+    if (nr > 0) {
+        const long long e0 = s_rp[w][0], e1 = s_rp[w][nr];
+        for (long long p = e0 + lane; p < e1; p += 64) {
             const int32_t k = acol[p];
             const long long b0 = brp[k], b1 = brp[k + 1];
             const long long l = b1 - b0;
-            s += l;
-            if (FEAT) {
-                mn = (mn < 0 || l < mn) ? l : mn;
-                mx = l > mx ? l : mx;
+            // last row r with s_rp[r] <= p (skips empty rows)
+            int lo = 0, hi = nr;           // s_rp[lo] <= p < s_rp[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_rp[w][mid] <= p) lo = mid; else hi = mid;
+            }
+            atomicAdd(&s_prod[w][lo], (unsigned long long)l);
+            if constexpr (FEAT) {
+                atomicMin(&s_mn[w][lo], (int)l);
+                atomicMax(&s_mx[w][lo], (int)l);
                 if (l > 0) {
-                    const long long f = bcol[b0], e = bcol[b1 - 1];
-                    lo = (lo < 0 || f < lo) ? f : lo;
-                    hi = (hi < 0 || e > hi) ? e : hi;
+                    atomicMin(&s_lo[w][lo], bcol[b0]);
+                    atomicMax(&s_hi[w][lo], bcol[b1 - 1]);
                 }
             }
         }
     }
-    uint64_t longmask = __ballot(valid && len > kShortRow);
-    while (longmask) {
-        const int r = __builtin_ctzll(longmask);
-        longmask &= longmask - 1;
-        const long long ra0 = __shfl(a0, r), ra1 = __shfl(a1, r);
-        long long ls = 0, lmn = -1, lmx = 0, llo = -1, lhi = -1;
-        for (long long p = ra0 + lane; p < ra1; p += 64) {
-            const int32_t k = acol[p];
-            const long long b0 = brp[k], b1 = brp[k + 1];
-            const long long l = b1 - b0;
-            ls += l;
-            if (FEAT) {
-                lmn = (lmn < 0 || l < lmn) ? l : lmn;
-                lmx = l > lmx ? l : lmx;
-                if (l > 0) {
-                    const long long f = bcol[b0], e = bcol[b1 - 1];
-                    llo = (llo < 0 || f < llo) ? f : llo;
-                    lhi = (lhi < 0 || e > lhi) ? e : lhi;
-                }
-            }
-        }
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) {
-            ls += __shfl_xor(ls, d);
-            if (FEAT) {
-                long long o;
-                o = __shfl_xor(lmn, d); lmn = (lmn < 0) ? o : ((o < 0) ? lmn : (o < lmn ? o : lmn));
-                o = __shfl_xor(lmx, d); lmx = o > lmx ? o : lmx;
-                o = __shfl_xor(llo, d); llo = (llo < 0) ? o : ((o < 0) ? llo : (o < llo ? o : llo));
-                o = __shfl_xor(lhi, d); lhi = o > lhi ? o : lhi;
-            }
-        }
-        if (lane == r) { s = ls; mn = lmn; mx = lmx; lo = llo; hi = lhi; }
-    }
-
+    __syncthreads();
+    const long long row = r0 + lane;
+    const bool valid = lane < nr;
+    int bin = -1;
     if (valid) {
+        const long long s = (long long)s_prod[w][lane];
         const long long u = s < ncols ? s : ncols;
         u_out[row] = (int32_t)u;
         if (prod_out) prod_out[row] = s;
         if (u == 0 && row_nnz) row_nnz[row] = 0;
-        atomicAdd(&hist[bin_of(bins, u)], 1);
-        if (FEAT && feat) {
-            const float n = (float)(ncols > 0 ? ncols : 1);
-            const float fl = (float)len, fs = (float)s;
+        bin = bin_of(bins, u);
+        if constexpr (FEAT) {
+            const long long len = s_rp[w][lane + 1] - s_rp[w][lane];
+            const int mn = len > 0 ? s_mn[w][lane] : 0, mx = s_mx[w][lane];
+            const int lo = s_lo[w][lane], hi = s_hi[w][lane];
+            const double n = (double)(ncols > 0 ? ncols : 1);
             const float mean = len > 0 ? (float)((double)s / (double)len) : 0.f;
             float* f = feat + row * 8;
-            f[0] = log2f(1.f + fl);
-            f[1] = log2f(1.f + fs);
-            f[2] = log2f(1.f + (float)(mn < 0 ? 0 : mn));
+            f[0] = log2f(1.f + (float)len);
+            f[1] = log2f(1.f + (float)s);
+            f[2] = log2f(1.f + (float)mn);
             f[3] = log2f(1.f + mean);
             f[4] = log2f(1.f + (float)mx);
             f[5] = log2f(1.f + (float)ncols);
-            f[6] = fminf(1.f, (float)((double)s / (double)n));
-            f[7] = (float)((double)(lo < 0 ? 0 : hi - lo) / (double)n);
+            f[6] = fminf(1.f, (float)((double)s / n));
+            f[7] = (float)((double)(hi < 0 ? 0 : hi - lo) / n);
         }
     }
-    // block total of products
-    long long ws = s;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) ws += __shfl_xor(ws, d);
-    if (lane == 0) atomicAdd((unsigned long long*)&prod_acc, (unsigned long long)ws);
+    if (bins.nb > 0) wave_hist_add(hist, bin);
     __syncthreads();
-    if (threadIdx.x <= kMaxBins && hist[threadIdx.x]) {
-        if (bins.nb > 0) atomicAdd(&info->sym_count[threadIdx.x], hist[threadIdx.x]);
-    }
-    if (threadIdx.x == 0 && prod_acc) atomicAdd((unsigned long long*)&info->total_prod, (unsigned long long)prod_acc);
+    if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
+        atomicAdd(&info->sym_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
 }
 
 // ===========================================================================
 // Scatter row ids into per-bin lists
 // ===========================================================================
-// Bin b's rows go to perm[start_b ...], start_b = sum of the counts of the
-// bins before it.  Rows of one workgroup reserve one range per bin with a
-// single global atomic.
+// Bin b's rows occupy perm[start_b ...) with start_b the total of the bins
+// before it; inside a bin, partition p's rows follow those of partitions
+// < p, and each workgroup reserves its range from partition p's cursor.
+// part_counts are the per-partition counts of the pass that binned the
+// rows, which counted rows in workgroups of count_rows rows.
 static __global__ void __launch_bounds__(256)
-k_scatter(int m, const int32_t* __restrict__ key, BinTable bins, const int* __restrict__ counts,
-          int* cursor, int32_t* __restrict__ perm) {
-    __shared__ int cnt[kMaxBins + 1];
-    __shared__ int base[kMaxBins + 1];
-    if (threadIdx.x <= kMaxBins) cnt[threadIdx.x] = 0;
+k_scatter(int m, const int32_t* __restrict__ key, BinTable bins, const int* __restrict__ part_counts,
+          int count_rows, int* cursor, int32_t* __restrict__ perm) {
+    __shared__ int cnt[kNB];
+    __shared__ int base[kNB];
+    if (threadIdx.x < kNB) cnt[threadIdx.x] = 0;
     __syncthreads();
     const long long row = (long long)blockIdx.x * 256 + threadIdx.x;
-    int b = -1, r = 0;
-    if (row < m) {
-        b = bin_of(bins, key[row]);
-        r = atomicAdd(&cnt[b], 1);
-    }
+    const int b = row < m ? bin_of(bins, key[row]) : -1;
+    const int r = wave_hist_add(cnt, b);
     __syncthreads();
+    const int part = (int)(((long long)blockIdx.x * 256 / count_rows) % kParts);
     if (threadIdx.x <= bins.nb && cnt[threadIdx.x]) {
+        const int me = threadIdx.x;
         int start = 0;
-        for (int i = 0; i < (int)threadIdx.x; ++i) start += counts[i];
-        base[threadIdx.x] = start + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        for (int p = 0; p < kParts; ++p) {
+            const int* pc = part_counts + p * kPartStride;
+            for (int i = 0; i < me; ++i) start += pc[i];
+            if (p < part) start += pc[me];
+        }
+        base[me] = start + atomicAdd(&cursor[part * kPartStride + me], cnt[me]);
     }
     __syncthreads();
     if (b >= 0) perm[base[b] + r] = (int32_t)row;
@@ -314,7 +313,7 @@ __device__ __forceinline__ int hash_insert_key(int32_t* keys, int32_t j, int* er
         }
         h = (h + 1) & (T - 1);
     }
-    *err = 1;
+    *err |= 1;
     return 0;
 }
 
@@ -331,7 +330,7 @@ __device__ __forceinline__ int hash_slot_of(int32_t* keys, int32_t j, int* err) 
         }
         h = (h + 1) & (T - 1);
     }
-    *err = 1;
+    *err |= 1;
     return -1;
 }
 
@@ -343,7 +342,9 @@ struct GroupCfg {
 };
 
 // Symbolic, sub-wave lane groups: G lanes per row, T key slots per row.
-// rows = perm (bin list) or identity when perm == nullptr.
+// rows = perm (bin list) or identity when perm == nullptr.  Every per-group
+// LDS row is padded by one word so that the groups of a wave start on
+// different banks.
 template <int G, int T>
 __global__ void __launch_bounds__(256)
 k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
@@ -351,18 +352,20 @@ k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             int32_t* __restrict__ row_nnz, DevInfo* info) {
     constexpr int NG = GroupCfg<G>::NG;
-    __shared__ int32_t keys[NG][T];
-    __shared__ long long s_off[NG][G];
-    __shared__ long long s_bst[NG][G];
-    const int lane = threadIdx.x & 63;
+    __shared__ int32_t keys[NG][T + 1];
+    __shared__ long long s_off[NG][G + 1];
+    __shared__ long long s_bst[NG][G + 1];
     const int gl = threadIdx.x & (G - 1);
     const int g = threadIdx.x / G;
-    const long long slot = (long long)xcd_block() * NG + g;
-    if (slot >= nrows_bin) return;               // group-uniform
-    const int row = perm ? perm[slot] : (int)slot;
-    (void)lane;
+    (void)m;
     int err = 0;
     int32_t* kt = keys[g];
+    // persistent: workgroup lb owns the contiguous slot range [lo, hi)
+    const long long per = (nrows_bin + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)xcd_block() * per;
+    const long long hi = lo + per < nrows_bin ? lo + per : nrows_bin;
+    for (long long slot = lo + g; slot < hi; slot += NG) {      // group-uniform
+    const int row = perm ? perm[slot] : (int)slot;
 #pragma unroll
     for (int s = gl; s < T; s += G) kt[s] = kEmpty;
     lds_fence();
@@ -391,6 +394,8 @@ k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
     }
     cnt = group_sum<G>(cnt);
     if (gl == 0) row_nnz[row] = cnt;
+    lds_fence();
+    }
     if (err) atomicOr(&info->err, kErrProbe);
 }
 
@@ -494,6 +499,446 @@ k_sym_bitmap(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
 }
 
 // ===========================================================================
+// Small-row kernels: wave-local row batches, one A entry per lane
+// ===========================================================================
+// Each wave owns a contiguous range of slots of the bin list and walks it in
+// batches: it takes the longest run of consecutive rows (at most RM) whose
+// A entries fit in the 64 lanes (always at least one row), so every lane
+// holds one A entry and streams that entry's B row, four independent loads
+// at a time, into its row's LDS hash table.  Waves never wait for each
+// other (no workgroup barriers).  In the bins these kernels serve every B
+// row has at most umax <= T/2 entries, so the per-lane loop is short.
+
+template <int RM>
+struct WaveRows {
+    long long off[RM + 1];    // exclusive prefix of the rows' A-entry counts
+    long long a0[RM];         // first A entry of each row
+    long long c0[RM];         // C row start (numeric)
+    long long c1[RM];         // C row end (numeric)
+    int row[RM];
+    int cnt[RM];
+};
+
+// Take the next batch starting at slot pos (< hi); returns the number of
+// rows nb >= 1 and leaves E = wr.off[nb].  Whole wave.
+template <int RM, bool NUMERIC>
+__device__ __forceinline__ int wave_rows_take(WaveRows<RM>& wr, long long pos, long long hi,
+                                              const int32_t* __restrict__ perm,
+                                              const int64_t* __restrict__ arp,
+                                              const int64_t* __restrict__ crp) {
+    const int lane = threadIdx.x & 63;
+    const int ncand = (int)(hi - pos < RM ? hi - pos : RM);
+    long long a0 = 0, len = 0;
+    int r = -1;
+    if (lane < ncand) {
+        r = perm ? perm[pos + lane] : (int)(pos + lane);
+        a0 = arp[r];
+        len = arp[r + 1] - a0;
+    }
+    const long long incl = group_incl_scan<64>(len, lane);
+    const uint64_t fits = __ballot(lane < ncand && incl <= 64);
+    int nb = __builtin_ctzll(~fits);          // leading run of rows that fit
+    if (nb == 0) nb = 1;
+    if (lane < nb) {
+        wr.off[lane] = incl - len;
+        wr.a0[lane] = a0;
+        wr.row[lane] = r;
+        wr.cnt[lane] = 0;
+        if (NUMERIC) { wr.c0[lane] = crp[r]; wr.c1[lane] = crp[r + 1]; }
+    }
+    if (lane == nb - 1) wr.off[nb] = incl;
+    return nb;
+}
+
+template <int RM>
+__device__ __forceinline__ int wave_row_of(const WaveRows<RM>& wr, int nb, long long e) {
+    int lo = 0, hi = nb;                    // wr.off[lo] <= e < wr.off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wr.off[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// contiguous slot range of this wave (4 waves per workgroup)
+__device__ __forceinline__ void wave_range(long long n, long long* lo, long long* hi) {
+    const long long nw = (long long)gridDim.x * 4;
+    const long long wid = (long long)xcd_block() * 4 + (threadIdx.x >> 6);
+    const long long per = (n + nw - 1) / nw;
+    *lo = wid * per;
+    *hi = *lo + per < n ? *lo + per : n;
+}
+
+template <int T, int RM>
+__global__ void __launch_bounds__(256)
+k_sym_wave(int nrows_bin, const int32_t* __restrict__ perm,
+           const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
+           const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
+           int32_t* __restrict__ row_nnz, DevInfo* info) {
+    __shared__ int32_t keys_all[4][RM][T + 1];
+    __shared__ WaveRows<RM> wr_all[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    auto& keys = keys_all[w];
+    WaveRows<RM>& wr = wr_all[w];
+    int err = 0;
+    long long lo, hi;
+    wave_range(nrows_bin, &lo, &hi);
+    for (long long pos = lo; pos < hi;) {
+        const int nb = wave_rows_take<RM, false>(wr, pos, hi, perm, arp, nullptr);
+        for (int i = lane; i < nb * T; i += 64) keys[i / T][i % T] = kEmpty;
+        lds_fence();
+        const long long E = wr.off[nb];
+        for (long long e = lane; e < E; e += 64) {
+            const int r = wave_row_of<RM>(wr, nb, e);
+            const long long p = wr.a0[r] + (e - wr.off[r]);
+            const int32_t k = acol[p];
+            const long long q0 = brp[k], q1 = brp[k + 1];
+            int added = 0;
+            for (long long q = q0; q < q1; q += 4) {
+                int32_t j[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) j[u] = q + u < q1 ? bcol[q + u] : kEmpty;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j[u] != kEmpty) added += hash_insert_key<T>(keys[r], j[u], &err);
+            }
+            if (added) atomicAdd(&wr.cnt[r], added);
+        }
+        lds_fence();
+        if (lane < nb) row_nnz[wr.row[lane]] = wr.cnt[lane];
+        lds_fence();
+        pos += nb;
+    }
+    if (err) atomicOr(&info->err, kErrProbe);
+}
+
+// Numeric counterpart: (key, FP64 value) tables.  Extraction: L = min(T, 64)
+// lanes per row; each occupied slot's output position is the number of
+// smaller keys in its row's table (unsigned compare, so empty slots count
+// as larger than every key), read 16 bytes at a time and broadcast to the
+// row's lanes.  Writes are guarded by the row's symbolic size.
+template <int T, int RM, typename VT>
+__global__ void __launch_bounds__(256)
+k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
+           const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
+           const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
+           const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
+           DevInfo* info) {
+    constexpr int KS = T + 4;                 // 16-byte aligned key rows, shifted banks
+    constexpr int L = T < 64 ? T : 64;        // extraction lanes per row
+    __shared__ __align__(16) int32_t keys_all[4][RM][KS];
+    __shared__ double vals_all[4][RM][T + 1];
+    __shared__ WaveRows<RM> wr_all[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    auto& keys = keys_all[w];
+    auto& vals = vals_all[w];
+    WaveRows<RM>& wr = wr_all[w];
+    int err = 0;
+    long long lo, hi;
+    wave_range(nrows_bin, &lo, &hi);
+    for (long long pos = lo; pos < hi;) {
+        const int nb = wave_rows_take<RM, true>(wr, pos, hi, perm, arp, crp);
+        for (int i = lane; i < nb * T; i += 64) { keys[i / T][i % T] = kEmpty; vals[i / T][i % T] = 0.0; }
+        lds_fence();
+        const long long E = wr.off[nb];
+        for (long long e = lane; e < E; e += 64) {
+            const int r = wave_row_of<RM>(wr, nb, e);
+            const long long p = wr.a0[r] + (e - wr.off[r]);
+            const int32_t k = acol[p];
+            const double a = to_f64(aval[p]);
+            const long long q0 = brp[k], q1 = brp[k + 1];
+            for (long long q = q0; q < q1; q += 4) {
+                int32_t j[4];
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = q + u < q1;
+                    j[u] = in ? bcol[q + u] : kEmpty;
+                    v[u] = in ? to_f64(bval[q + u]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j[u] != kEmpty) {
+                        const int h = hash_slot_of<T>(keys[r], j[u], &err);
+                        if (h >= 0) atomicAdd(&vals[r][h], a * v[u]);
+                    }
+            }
+        }
+        lds_fence();
+        for (int rr = lane / L; rr < nb; rr += 64 / L) {
+            for (int sl = lane % L; sl < T; sl += L) {
+                const uint32_t key = (uint32_t)keys[rr][sl];
+                if (key == (uint32_t)kEmpty) continue;
+                int rank = 0;
+#pragma unroll 4
+                for (int f = 0; f < T; f += 4) {
+                    const int4 q = *reinterpret_cast<const int4*>(&keys[rr][f]);
+                    rank += ((uint32_t)q.x < key) + ((uint32_t)q.y < key) + ((uint32_t)q.z < key) +
+                            ((uint32_t)q.w < key);
+                }
+                const long long c0 = wr.c0[rr];
+                if (rank < wr.c1[rr] - c0) {
+                    ccol[c0 + rank] = (int32_t)key;
+                    cval[c0 + rank] = (VT)vals[rr][sl];
+                }
+                atomicAdd(&wr.cnt[rr], 1);
+            }
+        }
+        lds_fence();
+        if (lane < nb && wr.cnt[lane] != (int)(wr.c1[lane] - wr.c0[lane])) err |= 2;
+        lds_fence();
+        pos += nb;
+    }
+    if (err & 1) atomicOr(&info->err, kErrProbe);
+    if (err & 2) atomicOr(&info->err, kErrCount);
+}
+
+// ===========================================================================
+// Merge accumulator for short rows (FSpGEMM Alg. 1, one row per lane)
+// ===========================================================================
+// The paper's sort-and-merge unit adds sparse partial rows by merging them
+// in column order.  Here one lane owns one output row and merges the (at
+// most K) sorted B rows its A entries select: every step takes the smallest
+// head column, adds a_ik * b_kj over the heads equal to it, and advances
+// those heads.  The row comes out in column order (no hash table, no sort)
+// in exactly row_nnz steps.  Rows with more than K A entries are taken by
+// the whole wave afterwards, one at a time, with an LDS hash of FT slots
+// (the bins served here bound the row's distinct columns by FT/2).
+
+constexpr int kMergeFT = 64;     // fallback table: the merge bins bound rows by 32
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
+            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
+            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
+            int32_t* __restrict__ row_nnz, DevInfo* info) {
+    __shared__ int32_t fb_keys[4][kMergeFT + 1];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int err = 0;
+    long long lo, hi;
+    wave_range(nrows_bin, &lo, &hi);
+    for (long long base = lo; base < hi; base += 64) {
+        const long long slot = base + lane;
+        const bool valid = slot < hi;
+        int row = -1;
+        long long a0 = 0, a1 = 0;
+        if (valid) {
+            row = perm ? perm[slot] : (int)slot;
+            a0 = arp[row];
+            a1 = arp[row + 1];
+        }
+        const bool mine = valid && a1 - a0 <= K;
+        if (mine) {
+            const int len = (int)(a1 - a0);
+            int hk[K];
+            long long hp[K], he[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                hk[k] = 0x7fffffff;
+                hp[k] = 0;
+                he[k] = 0;
+                if (k < len) {
+                    const int32_t kk = acol[a0 + k];
+                    hp[k] = brp[kk];
+                    he[k] = brp[kk + 1];
+                    if (hp[k] < he[k]) hk[k] = bcol[hp[k]];
+                }
+            }
+            int cnt = 0;
+            while (true) {
+                int m = hk[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k) m = hk[k] < m ? hk[k] : m;
+                if (m == 0x7fffffff) break;
+                ++cnt;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (hk[k] == m) {
+                        ++hp[k];
+                        hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                    }
+            }
+            row_nnz[row] = cnt;
+        }
+        uint64_t fb = __ballot(valid && !mine);
+        while (fb) {                                   // wave-uniform
+            const int r = __builtin_ctzll(fb);
+            fb &= fb - 1;
+            const int frow = __shfl(row, r);
+            const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
+            for (int i = lane; i < kMergeFT; i += 64) fb_keys[w][i] = kEmpty;
+            lds_fence();
+            int c = 0;
+            for (long long p = fa0; p < fa1; ++p) {
+                const int32_t kk = acol[p];
+                const long long q1 = brp[kk + 1];
+                for (long long q = brp[kk] + lane; q < q1; q += 64)
+                    c += hash_insert_key<kMergeFT>(fb_keys[w], bcol[q], &err);
+            }
+            c = group_sum<64>(c);
+            if (lane == 0) row_nnz[frow] = c;
+            lds_fence();
+        }
+    }
+    if (err) atomicOr(&info->err, kErrProbe);
+}
+
+// Numeric merge.  A wave takes the longest run of its rows (at most 64)
+// whose outputs fit an LDS staging area of kMergeStage entries; every row's
+// output is merged into its own staging segment (its size is known from the
+// symbolic pass) and the whole batch is then copied to C with coalesced
+// stores, so each cache line of C is written once and completely.
+constexpr int kMergeStage = 512;
+
+template <int K, typename VT, typename IT>
+__global__ void __launch_bounds__(256)
+k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
+            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
+            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
+            const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
+            DevInfo* info) {
+    constexpr int FT = kMergeFT;
+    constexpr int SN = kMergeStage;
+    static_assert(SN >= FT / 2, "a fallback row must fit the staging area");
+    __shared__ int32_t st_k[4][SN];             // staged output columns
+    __shared__ double st_v[4][SN];              // staged output values
+    __shared__ __align__(16) int32_t fb_keys[4][FT + 4];
+    __shared__ double fb_vals[4][FT + 1];
+    __shared__ int st_off[4][65];               // staging offset of each row of the batch
+    __shared__ long long st_c0[4][64];          // C row start of each row of the batch
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int err = 0;
+    long long lo, hi;
+    wave_range(nrows_bin, &lo, &hi);
+    for (long long pos = lo; pos < hi;) {
+        const int ncand = (int)(hi - pos < 64 ? hi - pos : 64);
+        int row = -1;
+        long long a0 = 0, a1 = 0, c0 = 0, c1 = 0;
+        if (lane < ncand) {
+            row = perm ? perm[pos + lane] : (int)(pos + lane);
+            a0 = arp[row];
+            a1 = arp[row + 1];
+            c0 = crp[row];
+            c1 = crp[row + 1];
+        }
+        const long long nn = c1 - c0;           // row's output size (symbolic)
+        const long long incl = group_incl_scan<64>(nn, lane);
+        const uint64_t fits = __ballot(lane < ncand && incl <= SN);
+        int nb = __builtin_ctzll(~fits);
+        if (nb == 0) nb = 1;                    // never happens in bins with nnz <= SN
+        const bool in = lane < nb;
+        if (in) { st_off[w][lane] = (int)(incl - nn); st_c0[w][lane] = c0; }
+        if (lane == nb - 1) st_off[w][nb] = (int)incl;
+        lds_fence();
+        const bool mine = in && a1 - a0 <= K && nn <= SN;
+        if (mine) {
+            // heads: column hk at position hp (end he) in B, scale ha; the
+            // head's value is loaded when it is consumed.  IT is int32 when
+            // nnz(B) fits.
+            int hk[K];
+            double ha[K];
+            IT hp[K], he[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                hk[k] = 0x7fffffff;
+                ha[k] = 0.0;
+                hp[k] = 0;
+                he[k] = 0;
+                if (k < (int)(a1 - a0)) {
+                    const int32_t kk = acol[a0 + k];
+                    ha[k] = to_f64(aval[a0 + k]);
+                    hp[k] = (IT)brp[kk];
+                    he[k] = (IT)brp[kk + 1];
+                    if (hp[k] < he[k]) hk[k] = bcol[hp[k]];
+                }
+            }
+            const int so = (int)(incl - nn);
+            int t = 0;
+            while (true) {
+                int m = hk[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k) m = hk[k] < m ? hk[k] : m;
+                if (m == 0x7fffffff) break;
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (hk[k] == m) {
+                        acc += ha[k] * to_f64(bval[hp[k]]);
+                        ++hp[k];
+                        hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                    }
+                if (t < nn) { st_k[w][so + t] = m; st_v[w][so + t] = acc; }
+                ++t;
+            }
+            if (t != nn) err |= 2;
+        }
+        // rows with more than K A entries: the whole wave, one row at a time
+        uint64_t fb = __ballot(in && !mine);
+        while (fb) {                                   // wave-uniform
+            const int r = __builtin_ctzll(fb);
+            fb &= fb - 1;
+            const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
+            const long long fnn = __shfl(nn, r);
+            const int fso = st_off[w][r];
+            for (int i = lane; i < FT; i += 64) { fb_keys[w][i] = kEmpty; fb_vals[w][i] = 0.0; }
+            lds_fence();
+            for (long long p = fa0; p < fa1; ++p) {
+                const int32_t kk = acol[p];
+                const double a = to_f64(aval[p]);
+                const long long q1 = brp[kk + 1];
+                for (long long q = brp[kk] + lane; q < q1; q += 64) {
+                    const int h = hash_slot_of<FT>(fb_keys[w], bcol[q], &err);
+                    if (h >= 0) atomicAdd(&fb_vals[w][h], a * to_f64(bval[q]));
+                }
+            }
+            lds_fence();
+            int c = 0;
+            for (int sl = lane; sl < FT; sl += 64) {
+                const uint32_t key = (uint32_t)fb_keys[w][sl];
+                if (key == (uint32_t)kEmpty) continue;
+                int rank = 0;
+                for (int f = 0; f < FT; f += 4) {
+                    const int4 q = *reinterpret_cast<const int4*>(&fb_keys[w][f]);
+                    rank += ((uint32_t)q.x < key) + ((uint32_t)q.y < key) + ((uint32_t)q.z < key) +
+                            ((uint32_t)q.w < key);
+                }
+                if (rank < fnn) { st_k[w][fso + rank] = (int32_t)key; st_v[w][fso + rank] = fb_vals[w][sl]; }
+                ++c;
+            }
+            c = group_sum<64>(c);
+            if (c != fnn) err |= 2;
+            lds_fence();
+        }
+        lds_fence();
+        // copy the batch's staged rows to C
+        const int total = st_off[w][nb];
+        if (!perm) {
+            const long long cb = st_c0[w][0];       // consecutive rows: one contiguous range
+            for (int i = lane; i < total; i += 64) {
+                ccol[cb + i] = st_k[w][i];
+                cval[cb + i] = (VT)st_v[w][i];
+            }
+        } else {
+            for (int i = lane; i < total; i += 64) {
+                int lo2 = 0, hi2 = nb;                  // row r with st_off[r] <= i < st_off[r+1]
+                while (hi2 - lo2 > 1) {
+                    const int mid = (lo2 + hi2) >> 1;
+                    if (st_off[w][mid] <= i) lo2 = mid; else hi2 = mid;
+                }
+                const long long dst = st_c0[w][lo2] + (i - st_off[w][lo2]);
+                ccol[dst] = st_k[w][i];
+                cval[dst] = (VT)st_v[w][i];
+            }
+        }
+        lds_fence();
+        pos += nb;
+    }
+    if (err & 1) atomicOr(&info->err, kErrProbe);
+    if (err & 2) atomicOr(&info->err, kErrCount);
+}
+
+// ===========================================================================
 // Exclusive prefix sum of row_nnz -> row_ptr (int64), fused with the
 // numeric binning histogram.  Three kernels: tile sums, a scan of the tile
 // sums in one workgroup, and the tile scans with their offsets.
@@ -535,8 +980,8 @@ static __global__ void __launch_bounds__(kScanBS)
 k_scan_apply(int m, const int32_t* __restrict__ cnt, const long long* __restrict__ tile_off,
              int64_t* __restrict__ row_ptr, BinTable bins, DevInfo* info) {
     __shared__ BlockScanSmem<kScanBS> sm;
-    __shared__ int hist[kMaxBins + 1];
-    if (threadIdx.x <= kMaxBins) hist[threadIdx.x] = 0;
+    __shared__ int hist[kNB];
+    if (threadIdx.x < kNB) hist[threadIdx.x] = 0;
     const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
     int v[kScanPer];
     long long s = 0;
@@ -552,11 +997,9 @@ k_scan_apply(int m, const int32_t* __restrict__ cnt, const long long* __restrict
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
         const long long r = base + i;
-        if (r < m) {
-            row_ptr[r] = run;
-            if (bins.nb > 0) atomicAdd(&hist[bin_of(bins, v[i])], 1);
-        }
+        if (r < m) row_ptr[r] = run;
         run += v[i];
+        if (bins.nb > 0) wave_hist_add(hist, r < m ? bin_of(bins, v[i]) : -1);
     }
     if (m == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) row_ptr[0] = 0;
@@ -564,8 +1007,8 @@ k_scan_apply(int m, const int32_t* __restrict__ cnt, const long long* __restrict
         row_ptr[m] = run;      // the thread holding row m-1 closes row_ptr
     }
     __syncthreads();
-    if (bins.nb > 0 && threadIdx.x <= kMaxBins && hist[threadIdx.x])
-        atomicAdd(&info->num_count[threadIdx.x], hist[threadIdx.x]);
+    if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
+        atomicAdd(&info->num_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
 }
 
 // ===========================================================================
@@ -575,7 +1018,8 @@ k_scan_apply(int m, const int32_t* __restrict__ cnt, const long long* __restrict
 // Numeric, sub-wave lane groups.  T slots of (int32 key, FP64 value); a row
 // with r = row_nnz_i <= T/2 entries.  After accumulation the occupied slots
 // are compacted (group ballot) and each entry's output position is its
-// rank among the row's keys (keys are distinct).
+// rank among the row's keys (keys are distinct), counted with 16-byte LDS
+// reads.  Per-group LDS rows are padded so groups start on different banks.
 template <int G, int T, typename VT>
 __global__ void __launch_bounds__(256)
 k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
@@ -584,22 +1028,26 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
             DevInfo* info) {
     constexpr int NG = GroupCfg<G>::NG;
-    __shared__ int32_t keys[NG][T];
-    __shared__ double vals[NG][T];
-    __shared__ int32_t ck[NG][T / 2];
-    __shared__ double cv[NG][T / 2];
-    __shared__ long long s_off[NG][G];
-    __shared__ long long s_bst[NG][G];
-    __shared__ double s_a[NG][G];
+    constexpr int CK = T / 2 + 4;                 // compacted keys, 16-byte rows
+    __shared__ int32_t keys[NG][T + 1];
+    __shared__ double vals[NG][T + 1];
+    __shared__ __align__(16) int32_t ck[NG][CK];
+    __shared__ double cv[NG][T / 2 + 1];
+    __shared__ long long s_off[NG][G + 1];
+    __shared__ long long s_bst[NG][G + 1];
+    __shared__ double s_a[NG][G + 1];
     const int lane = threadIdx.x & 63;
     const int gl = threadIdx.x & (G - 1);
     const int g = threadIdx.x / G;
-    const long long slot = (long long)xcd_block() * NG + g;
-    if (slot >= nrows_bin) return;
-    const int row = perm ? perm[slot] : (int)slot;
     int err = 0;
     int32_t* kt = keys[g];
     double* vt = vals[g];
+    // persistent: workgroup lb owns the contiguous slot range [lo, hi)
+    const long long per = (nrows_bin + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)xcd_block() * per;
+    const long long hi = lo + per < nrows_bin ? lo + per : nrows_bin;
+    for (long long slot = lo + g; slot < hi; slot += NG) {      // group-uniform
+    const int row = perm ? perm[slot] : (int)slot;
 #pragma unroll
     for (int s = gl; s < T; s += G) { kt[s] = kEmpty; vt[s] = 0.0; }
     lds_fence();
@@ -633,6 +1081,7 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
     }
     // compact the occupied slots
     int n = 0;
+#pragma unroll
     for (int s0 = 0; s0 < T; s0 += G) {
         const int s = s0 + gl;
         const int32_t k = kt[s];
@@ -644,19 +1093,27 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
         }
         n += __builtin_popcountll(mask);
     }
-    lds_fence();
     const long long rp = crp[row];
     const int expect = (int)(crp[row + 1] - rp);
     if (n != expect || n > T / 2) {
         if (gl == 0) atomicOr(&info->err, kErrCount);
-        return;
+        lds_fence();
+        continue;
     }
+    const int n4 = (n + 3) & ~3;
+    if (gl < n4 - n) ck[g][n + gl] = 0x7fffffff;      // pads sort after every key
+    lds_fence();
     for (int e = gl; e < n; e += G) {
         const int32_t k = ck[g][e];
         int rank = 0;
-        for (int f = 0; f < n; ++f) rank += (ck[g][f] < k) ? 1 : 0;
+        for (int f = 0; f < n4; f += 4) {
+            const int4 q = *reinterpret_cast<const int4*>(&ck[g][f]);
+            rank += (q.x < k) + (q.y < k) + (q.z < k) + (q.w < k);
+        }
         ccol[rp + rank] = k;
         cval[rp + rank] = (VT)cv[g][e];
+    }
+    lds_fence();
     }
     if (err) atomicOr(&info->err, kErrProbe);
 }

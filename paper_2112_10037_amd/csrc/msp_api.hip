@@ -203,6 +203,7 @@ msp_tuning default_tuning() {
     t.group_scale = 0;
     t.spill_nnz = 4096;
     t.block_rows = 128;
+    t.merge_k = 8;
     return t;
 }
 
@@ -211,9 +212,13 @@ msp_status check_tuning(msp_tuning* t) {
     if (t->hash_scale == 0) t->hash_scale = d.hash_scale;
     if (t->spill_nnz == 0) t->spill_nnz = d.spill_nnz;
     if (t->block_rows == 0) t->block_rows = d.block_rows;
+    if (t->merge_k == 0) t->merge_k = d.merge_k;
+    if (t->merge_k != 4 && t->merge_k != 8 && t->merge_k != -1)
+        return fail(MSP_ERR_INVALID_ARG, "tuning.merge_k must be 4, 8 or -1");
     if (t->hash_scale < 1 || t->hash_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.hash_scale must be 1 or 2");
     if (t->group_scale < 0 || t->group_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.group_scale must be 0..2");
-    if (t->spill_nnz < 64 || t->spill_nnz > 4096) return fail(MSP_ERR_INVALID_ARG, "tuning.spill_nnz must be in 64..4096");
+    if (t->spill_nnz < 256 || t->spill_nnz > 4096 || (t->spill_nnz & (t->spill_nnz - 1)))
+        return fail(MSP_ERR_INVALID_ARG, "tuning.spill_nnz must be a power of two in 256..4096");
     if (t->block_rows != 32 && t->block_rows != 64 && t->block_rows != 128)
         return fail(MSP_ERR_INVALID_ARG, "tuning.block_rows must be 32, 64 or 128");
     return MSP_OK;
@@ -222,7 +227,8 @@ msp_status check_tuning(msp_tuning* t) {
 msp_tuning effective_tuning(const msp_handle* h, const msp_opts* o) {
     if (!o) return h->tuning;
     const msp_tuning& t = o->tuning;
-    if (t.hash_scale == 0 && t.group_scale == 0 && t.spill_nnz == 0 && t.block_rows == 0) return h->tuning;
+    if (t.hash_scale == 0 && t.group_scale == 0 && t.spill_nnz == 0 && t.block_rows == 0 && t.merge_k == 0)
+        return h->tuning;
     msp_tuning c = t;
     if (check_tuning(&c) != MSP_OK) return h->tuning;
     return c;

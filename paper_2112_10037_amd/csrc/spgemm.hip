@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <unordered_map>
 
 #include "internal.hpp"
 #include "kernels.hpp"
@@ -34,15 +36,35 @@ static void add_bin(BinPlan& p, int umax, BinSpec s) {
     p.table.nb = b + 1;
 }
 
-static void add_group_bins(BinPlan& p, const msp_tuning& t, int limit) {
+// Small bins (bound <= 128).  Symbolic: wave-local row batches (k_sym_wave) of
+// at most R rows with T key slots.  Numeric: wave batches while T <= 64, lane groups of
+// G lanes per row (k_num_group) for larger tables.
+static int sym_batch_rows(int T) { return T <= 64 ? 16 : 1024 / T; }
+
+static void add_small_bins(BinPlan& p, const msp_tuning& t, int limit, bool numeric) {
     static const int umax[4] = {16, 32, 64, 128};
     static const int g0[4] = {8, 16, 32, 64};
+    int covered = 0;
+    // the merge takes row_nnz steps of K comparisons each: worth it for the
+    // shortest rows only
+    if (t.merge_k > 0 && limit >= 32) {
+        add_bin(p, 32, BinSpec{Kind::Merge, t.merge_k, kMergeFT});
+        covered = 32;
+    }
     for (int i = 0; i < 4; ++i) {
         if (umax[i] > limit) break;
+        if (umax[i] <= covered) continue;
         const int T = next_pow2(umax[i]) << t.hash_scale;
-        int G = std::min(64, g0[i] << t.group_scale);
-        G = std::min(G, T / 2);
-        add_bin(p, umax[i], BinSpec{Kind::Group, G, T});
+        if (!numeric) {
+            add_bin(p, umax[i], BinSpec{Kind::Batch, sym_batch_rows(T), T});
+        } else if (T <= 64) {
+            const int R = (T == 32 ? (t.group_scale == 0 ? 12 : 8 >> (t.group_scale - 1)) : 8 >> t.group_scale);
+            add_bin(p, umax[i], BinSpec{Kind::Batch, R, T});
+        } else {
+            int G = std::min(64, g0[i] << t.group_scale);
+            G = std::min(G, T / 2);
+            add_bin(p, umax[i], BinSpec{Kind::Group, G, T});
+        }
     }
 }
 
@@ -51,7 +73,7 @@ BinPlan symbolic_plan(const msp_tuning& t, bool force_spill) {
     memset(&p.table, 0, sizeof(p.table));
     p.table.nb = 1;                    // bin 0: u == 0
     if (!force_spill) {
-        add_group_bins(p, t, t.block_rows);
+        add_small_bins(p, t, t.block_rows, false);
         static const int umax[4] = {512, 2048, 8192, 16384};
         static const int bs[4] = {256, 512, 1024, 1024};
         int last = p.table.umax[p.table.nb - 1];
@@ -72,7 +94,7 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
     memset(&p.table, 0, sizeof(p.table));
     p.table.nb = 1;
     if (!force_spill) {
-        add_group_bins(p, t, std::min(t.block_rows, t.spill_nnz));
+        add_small_bins(p, t, std::min(t.block_rows, t.spill_nnz), true);
         int last = p.table.umax[p.table.nb - 1];
         int list[4] = {512, 2048, 4096, t.spill_nnz};
         std::sort(list, list + 4);
@@ -99,10 +121,66 @@ constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense ker
 #define MSP_GROUP_SHAPES(X) \
     X(8, 32) X(16, 32) X(8, 64) X(16, 64) X(32, 64) X(16, 128) X(32, 128) X(64, 128) \
     X(32, 256) X(64, 256) X(64, 512)
+#define MSP_SYM_BATCH_SHAPES(X) X(32, 16) X(64, 16) X(128, 8) X(256, 4) X(512, 2)
+#define MSP_NUM_BATCH_SHAPES(X) X(32, 12) X(32, 8) X(32, 4) X(64, 8) X(64, 4) X(64, 2)
 #define MSP_SYM_BLOCK_SHAPES(X) \
     X(256, 1024) X(256, 2048) X(512, 4096) X(512, 8192) X(1024, 16384) X(1024, 32768)
 #define MSP_NUM_BLOCK_SHAPES(X) \
     X(256, 512) X(256, 1024) X(256, 2048) X(512, 2048) X(512, 4096) X(512, 8192) X(1024, 8192)
+
+static bool spec_supported(const BinSpec& sp, bool numeric) {
+    switch (sp.kind) {
+        case Kind::Merge: return sp.lanes == 4 || sp.lanes == 8;
+        case Kind::Batch:
+#define X(T, R) if (sp.slots == T && sp.lanes == R) return true;
+            if (numeric) { MSP_NUM_BATCH_SHAPES(X) } else { MSP_SYM_BATCH_SHAPES(X) }
+#undef X
+            return false;
+        case Kind::Group:
+#define X(G, T) if (sp.lanes == G && sp.slots == T) return true;
+            MSP_GROUP_SHAPES(X)
+#undef X
+            return false;
+        case Kind::Block:
+#define X(BS, T) if (sp.lanes == BS && sp.slots == T) return true;
+            if (numeric) { MSP_NUM_BLOCK_SHAPES(X) } else { MSP_SYM_BLOCK_SHAPES(X) }
+#undef X
+            return false;
+        case Kind::Bitmap: return !numeric;
+        case Kind::Dense: return numeric;
+        default: return false;
+    }
+}
+
+// Number of (tuning, bin) pairs whose plan names a kernel shape that is not
+// instantiated; 0 means every accepted tuning can run.  Host-only check.
+int count_unsupported_plans(int verbose) {
+    int bad = 0;
+    for (int hs = 1; hs <= 2; ++hs)
+        for (int gs = 0; gs <= 2; ++gs)
+            for (int sp : {64, 128, 256, 512, 1024, 2048, 4096})
+                for (int br : {32, 64, 128})
+                    for (int fs = 0; fs <= 1; ++fs) {
+                      for (int mk : {4, 8, -1}) {
+                        msp_tuning t{hs, gs, sp, br, mk};
+                        if (check_tuning(&t) != MSP_OK) continue;
+                        const BinPlan a = symbolic_plan(t, fs), b = numeric_plan(t, fs);
+                        for (int i = 1; i <= a.table.nb; ++i)
+                            if (!spec_supported(a.spec[i], false)) {
+                                ++bad;
+                                if (verbose) fprintf(stderr, "symbolic t=(%d,%d,%d,%d) bin %d kind %d shape (%d,%d)\n", hs, gs, sp, br, i, (int)a.spec[i].kind, a.spec[i].lanes, a.spec[i].slots);
+                            }
+                        for (int i = 1; i <= b.table.nb; ++i)
+                            if (!spec_supported(b.spec[i], true)) {
+                                ++bad;
+                                if (verbose) fprintf(stderr, "numeric t=(%d,%d,%d,%d) bin %d kind %d shape (%d,%d)\n", hs, gs, sp, br, i, (int)b.spec[i].kind, b.spec[i].lanes, b.spec[i].slots);
+                            }
+                        for (int i = 2; i < a.table.nb; ++i) bad += a.table.umax[i] <= a.table.umax[i - 1];
+                        for (int i = 2; i < b.table.nb; ++i) bad += b.table.umax[i] <= b.table.umax[i - 1];
+                      }
+                    }
+    return bad;
+}
 
 template <typename VT>
 static void* dense_kernel(bool lds) {
@@ -123,10 +201,26 @@ msp_status configure_kernels(msp_handle* h) {
     return MSP_OK;
 }
 
-static int group_grid(int rows, int G) {
-    const int ng = 256 / G;
-    int blocks = (rows + ng - 1) / ng;
-    return (blocks + 7) & ~7;           // multiple of 8 for the XCD-aware order
+// Grid of a persistent lane-group kernel: as many workgroups as can be
+// resident (occupancy from the kernel's registers and LDS), a multiple of 8
+// for the XCD-aware order, and no more than the rows need.
+static int group_grid(msp_handle* h, const void* fn, int rows, int rows_per_block) {
+    static std::unordered_map<const void*, int> occ_cache;
+    int occ = 0;
+    auto it = occ_cache.find(fn);
+    if (it != occ_cache.end()) {
+        occ = it->second;
+    } else {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0) != hipSuccess || occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+        occ_cache[fn] = occ;
+    }
+    const int need = (rows + rows_per_block - 1) / rows_per_block;
+    const int full = occ * h->num_cu;
+    const int blocks = std::max(1, std::min(need, full));
+    return (blocks + 7) & ~7;
 }
 
 static msp_status launch_check(const char* what) {
@@ -142,10 +236,28 @@ static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, con
     DevInfo* info = h->info.as<DevInfo>();
     const int m = (int)A->nrows;
     hipStream_t st = h->stream;
-    if (s.kind == Kind::Group) {
-        const int grid = group_grid(rows, s.lanes);
+    if (s.kind == Kind::Merge) {
+        const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4> : (const void*)k_sym_merge<8>;
+        const int grid = group_grid(h, fn, rows, 256);
+        if (s.lanes == 4)
+            k_sym_merge<4><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, rnnz, info);
+        else
+            k_sym_merge<8><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, rnnz, info);
+        return launch_check("k_sym_merge");
+    } else if (s.kind == Kind::Batch) {
+#define X(T, R)                                                                                  \
+    if (s.slots == T && s.lanes == R) {                                                          \
+        const int grid = group_grid(h, (const void*)k_sym_wave<T, R>, rows, 4 * R);             \
+        k_sym_wave<T, R><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, \
+                                                rnnz, info);                                     \
+        return launch_check("k_sym_wave");                                                      \
+    }
+        MSP_SYM_BATCH_SHAPES(X)
+#undef X
+    } else if (s.kind == Kind::Group) {
 #define X(G, T)                                                                                 \
     if (s.lanes == G && s.slots == T) {                                                         \
+        const int grid = group_grid(h, (const void*)k_sym_group<G, T>, rows, 256 / G);         \
         k_sym_group<G, T><<<grid, 256, 0, st>>>(rows, perm, m, A->row_ptr, A->col, B->row_ptr, \
                                                 B->col, rnnz, info);                           \
         return launch_check("k_sym_group");                                                     \
@@ -192,10 +304,32 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
     hipStream_t st = h->stream;
     const VT* av = (const VT*)A->val;
     const VT* bv = (const VT*)B->val;
-    if (s.kind == Kind::Group) {
-        const int grid = group_grid(rows, s.lanes);
+    if (s.kind == Kind::Merge) {
+        const bool small = B->nnz < INT32_MAX;     // 32-bit positions into B
+#define MSP_MERGE(KK, IT)                                                                             \
+    {                                                                                                 \
+        const int grid = group_grid(h, (const void*)k_num_merge<KK, VT, IT>, rows, 256);             \
+        k_num_merge<KK, VT, IT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
+                                                      B->col, bv, crp, ccol, cval, info);            \
+        return launch_check("k_num_merge");                                                           \
+    }
+        if (s.lanes == 4) { if (small) MSP_MERGE(4, int) else MSP_MERGE(4, long long) }
+        else { if (small) MSP_MERGE(8, int) else MSP_MERGE(8, long long) }
+#undef MSP_MERGE
+    } else if (s.kind == Kind::Batch) {
+#define X(T, R)                                                                                    \
+    if (s.slots == T && s.lanes == R) {                                                            \
+        const int grid = group_grid(h, (const void*)k_num_wave<T, R, VT>, rows, 4 * R);           \
+        k_num_wave<T, R, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr,  \
+                                                    B->col, bv, crp, ccol, cval, info);           \
+        return launch_check("k_num_wave");                                                        \
+    }
+        MSP_NUM_BATCH_SHAPES(X)
+#undef X
+    } else if (s.kind == Kind::Group) {
 #define X(G, T)                                                                                   \
     if (s.lanes == G && s.slots == T) {                                                           \
+        const int grid = group_grid(h, (const void*)k_num_group<G, T, VT>, rows, 256 / G);       \
         k_num_group<G, T, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
                                                     B->col, bv, crp, ccol, cval, info);          \
         return launch_check("k_num_group");                                                       \
@@ -291,29 +425,47 @@ msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, cons
     return launch_check("k_row_stats");
 }
 
-// Launch the kernels of every nonempty bin.  With a single nonempty bin the
-// rows are taken in their natural order (no scatter, and every kernel also
-// handles the rows of bin 0); otherwise row ids are scattered into per-bin
-// lists first.
+void sum_parts(const int (*part)[kPartStride], int out[kNB]) {
+    for (int b = 0; b < kNB; ++b) {
+        int t = 0;
+        for (int p = 0; p < kParts; ++p) t += part[p][b];
+        out[b] = t;
+    }
+}
+
+// Launch the kernels of every nonempty bin.  With one nonempty bin, or when
+// every nonempty bin is a hash bin of the small kernels (whose larger tables
+// subsume the smaller ones), one kernel takes all rows in their natural
+// order (no scatter; these kernels handle smaller and empty rows too).
+// Otherwise row ids are scattered into per-bin lists first.
 static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                           const int* counts, const int32_t* key, int* cursor, bool numeric,
+                           const int* counts, const int32_t* key, bool numeric,
                            const int64_t* crp, int32_t* ccol, void* cval, int32_t* rnnz) {
     const int m = (int)A->nrows;
     const int nb = plan.table.nb;
-    int nonempty = 0, only = -1;
+    int nonempty = 0, last = -1;
+    bool all_group = true;
     for (int b = 1; b <= nb; ++b)
-        if (counts[b] > 0) { ++nonempty; only = b; }
+        if (counts[b] > 0) {
+            ++nonempty;
+            last = b;
+            all_group = all_group && (plan.spec[b].kind == Kind::Group || plan.spec[b].kind == Kind::Batch);
+        }
     if (nonempty == 0) return MSP_OK;
-    if (nonempty == 1) {
-        return numeric ? launch_numeric(h, plan.spec[only], m, nullptr, A, B, crp, ccol, cval)
-                       : launch_symbolic(h, plan.spec[only], m, nullptr, A, B, rnnz);
+    if (nonempty == 1 || all_group) {
+        return numeric ? launch_numeric(h, plan.spec[last], m, nullptr, A, B, crp, ccol, cval)
+                       : launch_symbolic(h, plan.spec[last], m, nullptr, A, B, rnnz);
     }
     msp_status s = h->perm.ensure((size_t)m * 4);
     if (s != MSP_OK) return s;
     int32_t* perm = h->perm.as<int32_t>();
     DevInfo* info = h->info.as<DevInfo>();
-    k_scatter<<<(m + 255) / 256, 256, 0, h->stream>>>(m, key, plan.table,
-                                                     numeric ? info->num_count : info->sym_count, cursor, perm);
+    int* cursor = &info->cursor[0][0];
+    k_zero_words<<<1, 256, 0, h->stream>>>(cursor, kParts * kPartStride);
+    if ((s = launch_check("k_zero_words")) != MSP_OK) return s;
+    k_scatter<<<(m + 255) / 256, 256, 0, h->stream>>>(
+        m, key, plan.table, numeric ? &info->num_part[0][0] : &info->sym_part[0][0],
+        numeric ? kScanTile : 256, cursor, perm);
     if ((s = launch_check("k_scatter")) != MSP_OK) return s;
     int start = counts[0];
     for (int b = 1; b <= nb; ++b) {
@@ -329,8 +481,7 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
 
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                              const int* counts_host, int32_t* row_nnz) {
-    return run_bins(h, A, B, plan, counts_host, h->u.as<int32_t>(), h->info.as<DevInfo>()->cursor, false,
-                    nullptr, nullptr, nullptr, row_nnz);
+    return run_bins(h, A, B, plan, counts_host, h->u.as<int32_t>(), false, nullptr, nullptr, nullptr, row_nnz);
 }
 
 msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan) {
@@ -354,8 +505,7 @@ msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_p
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                             const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
                             int32_t* ccol, void* cval, const int32_t*, int) {
-    return run_bins(h, A, B, plan, counts_host, row_nnz, h->info.as<DevInfo>()->cursor, true, crp, ccol,
-                    cval, nullptr);
+    return run_bins(h, A, B, plan, counts_host, row_nnz, true, crp, ccol, cval, nullptr);
 }
 
 static msp_status check_pair(const msp_csr* A, const msp_csr* B) {
@@ -403,8 +553,8 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr)) != MSP_OK) return s;
     h->prof.end(h->stream);
     if ((s = read_info(h)) != MSP_OK) return s;
-    int counts[kMaxBins + 1];
-    memcpy(counts, h->hinfo->sym_count, sizeof(counts));
+    int counts[kNB];
+    sum_parts(h->hinfo->sym_part, counts);
     h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
     s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>());
     h->prof.end(h->stream);
@@ -450,8 +600,8 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
     if ((s = read_info(h)) != MSP_OK) return cleanup(s);
     if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
     const long long nnz = h->hinfo->nnz;
-    int counts[kMaxBins + 1];
-    memcpy(counts, h->hinfo->num_count, sizeof(counts));
+    int counts[kNB];
+    sum_parts(h->hinfo->num_part, counts);
     const size_t vsz = A->dtype == MSP_F64 ? 8 : 4;
     C->nrows = m;
     C->ncols = B->ncols;
@@ -461,9 +611,6 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
         C->col = (int32_t*)h->alloc(h->alloc_ctx, (size_t)nnz * 4, h->stream);
         C->val = h->alloc(h->alloc_ctx, (size_t)nnz * vsz, h->stream);
         if (!C->col || !C->val) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
-        // the scatter cursors are reused by the numeric binning
-        k_zero_words<<<1, 64, 0, h->stream>>>(h->info.as<DevInfo>()->cursor, kMaxBins + 1);
-        if ((s = launch_check("k_zero_words")) != MSP_OK) return cleanup(s);
         h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
         if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col, C->val,
                                   nullptr, 0)) != MSP_OK)
@@ -517,3 +664,5 @@ extern "C" msp_status msp_row_features(msp_handle* h, const msp_csr* A, const ms
     if ((s = zero_info(h)) != MSP_OK) return s;
     return run_row_stats(h, A, B, none, prod, features ? features : nullptr);
 }
+
+extern "C" int msp_internal_unsupported_plans(int verbose) { return msp::count_unsupported_plans(verbose); }

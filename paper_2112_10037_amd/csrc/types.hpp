@@ -16,14 +16,20 @@ constexpr int kErrUnsorted = 2;   // input columns not strictly increasing
 constexpr int kErrRange = 4;      // input index out of range / row_ptr not monotone
 constexpr int kErrCount = 8;      // numeric count disagrees with the symbolic count
 
+// Global bin counters are split over kParts partitions (workgroup w counts
+// into partition w % kParts), each padded to its own 128-byte line, so that
+// thousands of workgroups do not serialise on one address.
+constexpr int kParts = 32;
+constexpr int kNB = kMaxBins + 1;
+constexpr int kPartStride = 32;    // ints per partition row (128 bytes)
+
 struct DevInfo {
-    long long nnz;                 // nnz(C) after the scan
-    long long total_prod;          // sum of intermediate products
+    long long nnz;                        // nnz(C) after the scan
     int err;
-    int pad;
-    int sym_count[kMaxBins + 1];   // rows per symbolic bin
-    int num_count[kMaxBins + 1];   // rows per numeric bin
-    int cursor[kMaxBins + 1];      // scatter cursors
+    int pad[29];
+    int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
+    int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
+    int cursor[kParts][kPartStride];      // scatter cursors
 };
 
 // Bin b (1 <= b < nb) holds rows with umax[b-1] < u <= umax[b]; bin 0 holds

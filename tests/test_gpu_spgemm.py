@@ -154,6 +154,19 @@ def test_hash_hostile_columns(h):
     check_full(h, A, B)
 
 
+@pytest.mark.parametrize("merge_k", [4, 8])
+def test_merge_rows_with_many_entries_fall_back(h, merge_k):
+    """Rows in the merge bin with more A entries than merge_k take the wave
+    fallback; mixed with rows that merge."""
+    n = 64
+    k = np.random.default_rng(3).integers(1, 12, 3000)
+    A = gen.erdos_renyi(3000, n, k, seed=31)
+    B = gen.erdos_renyi(n, 2000, 1, seed=32)
+    check_full(h, A, B, tuning=(1, 0, 4096, 128, merge_k))
+    C = gen.erdos_renyi(3000, 3000, 5, seed=33, dtype=np.float32)
+    check_full(h, C, C, tuning=(1, 0, 4096, 128, merge_k))
+
+
 def test_rectangular_chain(h):
     rng = np.random.default_rng(21)
     A = _rand(rng, 300, 700, 0.02)
@@ -179,8 +192,8 @@ def test_transpose_identity_structure(h):
     oracle.compare(Ct.row_ptr, Ct.col, Ct.val, ref, 1e-12)
 
 
-@pytest.mark.parametrize("tuning", [(1, 0, 4096, 128), (2, 0, 4096, 128), (1, 1, 1024, 64),
-                                    (2, 2, 256, 32), (1, 2, 512, 128)])
+@pytest.mark.parametrize("tuning", [(1, 0, 4096, 128, 8), (2, 0, 4096, 128, 4), (1, 1, 1024, 64, -1),
+                                    (2, 2, 256, 32, 8), (1, 2, 512, 128, -1), (2, 1, 2048, 128, 4)])
 def test_tuning_variants_same_result(h, tuning):
     A = gen.rmat(12, 12 << 12, seed=15, dtype=np.float64)
     check_full(h, A, A, tuning=tuning)
