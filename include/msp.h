@@ -138,12 +138,22 @@ msp_status msp_get_tuning(const msp_handle* h, msp_tuning* t);
  *      global dense accumulator with an ordered bitmap scan for rows too
  *      large for LDS.
  * Host synchronisation: two small device-to-host reads (bin counts, then
- * nnz(C) with the numeric bin counts).  Values of C are rounded once from
- * FP64 sums; they satisfy |c - exact| <= k * eps64 * sum|a||b| for a row
- * with k terms.
+ * nnz(C) with the numeric bin counts).  The numeric pass is only queued:
+ * it completes on the handle's stream after the call returns.  Its internal
+ * consistency checks (a row count that differs from the symbolic count, a
+ * hash probe bound) are reported by the next call on the handle or by
+ * msp_sync.  Values of C are rounded once from FP64 sums; they satisfy
+ * |c - exact| <= k * eps64 * sum|a||b| for a row with k terms.
+ * C.col and C.val share one allocation from the allocator: C.col is its
+ * start (release that pointer) and C.val follows at the next 256-byte
+ * boundary.
  */
 msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B,
                       msp_csr_out* C, const msp_opts* opts);
+
+/* Wait for the work queued on the handle's stream; report any internal
+ * error the numeric kernels of earlier calls flagged. */
+msp_status msp_sync(msp_handle* h);
 
 /* Only the symbolic part: row_nnz (device, A.nrows int32) and the total.
  * Used to produce training targets for the predictor. */

@@ -75,6 +75,7 @@ SIGNATURES = [
     ("msp_get_tuning", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_tuning)]),
     ("msp_spgemm", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
                                   ctypes.POINTER(c_csr_out), ctypes.POINTER(c_opts)]),
+    ("msp_sync", ctypes.c_int, [ctypes.c_void_p]),
     ("msp_spgemm_symbolic", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(c_opts)]),
@@ -187,9 +188,13 @@ class Handle:
     def _free(self, ctx, ptr, stream):
         self._live.pop(ptr, None)
 
-    def _take(self, ptr, n, dtype):
+    def _take_c(self, ptr, nnz, vdtype):
+        """Column and value views of C's single allocation (values start at
+        the next 256-byte boundary after the columns)."""
         t = self._live.pop(ptr)
-        return t[: n * self._torch.empty(0, dtype=dtype).element_size()].view(dtype)
+        voff = (nnz * 4 + 255) & ~255
+        vsz = self._torch.empty(0, dtype=vdtype).element_size()
+        return t[: nnz * 4].view(self._torch.int32), t[voff: voff + nnz * vsz].view(vdtype)
 
     def close(self):
         if self._h:
@@ -220,9 +225,15 @@ class Handle:
         _check(self._lib.msp_get_tuning(self._h, ctypes.byref(t)))
         return (t.hash_scale, t.group_scale, t.spill_nnz, t.block_rows, t.merge_k)
 
+    def sync(self):
+        """Wait for the handle's stream; raise on any internal error that the
+        numeric kernels of earlier calls flagged."""
+        _check(self._lib.msp_sync(self._h))
+
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False,
-               tuning=None, row_ptr=None) -> DeviceCSR:
-        """C = A * B (plain two-phase path)."""
+               tuning=None, row_ptr=None, check=True) -> DeviceCSR:
+        """C = A * B (plain two-phase path).  With check, wait for the
+        result and raise on internal errors (msp_sync)."""
         torch = self._torch
         a, b = A.c(), B.c()
         out = c_csr_out()
@@ -235,11 +246,12 @@ class Handle:
         nnz = int(out.nnz)
         vdt = torch.float64 if out.dtype == MSP_F64 else torch.float32
         if nnz > 0:
-            col = self._take(out.col, nnz, torch.int32)
-            val = self._take(out.val, nnz, vdt)
+            col, val = self._take_c(out.col, nnz, vdt)
         else:
             col = torch.empty(0, dtype=torch.int32, device=rp.device)
             val = torch.empty(0, dtype=vdt, device=rp.device)
+        if check:
+            self.sync()
         return DeviceCSR(A.nrows, B.ncols, rp, col, val)
 
     def symbolic(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False, tuning=None):

@@ -71,6 +71,9 @@ struct msp_handle {
     size_t dslab_cols = 0;          // ncols the dense slabs were zeroed for
     int dslab_count = 0;
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
+    int* hpending = nullptr;        // pinned: error bits of the last call's numeric
+                                    // kernels, copied back without waiting
+    int scan_epoch = 0;             // epoch of the single-pass scan's tile states
     msp::ExtraState* extra = nullptr;
     msp::Profiler prof;
 };
@@ -97,8 +100,9 @@ msp_status zero_info(msp_handle* h);
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                          int64_t* prod_out, float* feat);
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                             const int* counts_host, int32_t* row_nnz);
+                             const int* counts_host, int32_t* row_nnz, int done_bin);
 msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan);
+msp_status take_pending_error(msp_handle* h);
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                             const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
                             int32_t* ccol, void* cval, const int32_t* perm_override, int perm_rows);

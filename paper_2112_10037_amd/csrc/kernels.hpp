@@ -712,6 +712,7 @@ __global__ void __launch_bounds__(256)
 k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
+            const int32_t* __restrict__ ufilter, int umax,
             int32_t* __restrict__ row_nnz, DevInfo* info) {
     __shared__ int32_t fb_keys[4][kMergeFT + 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -723,12 +724,17 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
         const bool valid = slot < hi;
         int row = -1;
         long long a0 = 0, a1 = 0;
+        bool take = valid;
         if (valid) {
             row = perm ? perm[slot] : (int)slot;
-            a0 = arp[row];
-            a1 = arp[row + 1];
+            // with a filter, only rows whose bound is in (0, umax] are taken
+            if (ufilter) { const int u = ufilter[row]; take = u > 0 && u <= umax; }
+            if (take) {
+                a0 = arp[row];
+                a1 = arp[row + 1];
+            }
         }
-        const bool mine = valid && a1 - a0 <= K;
+        const bool mine = take && a1 - a0 <= K;
         if (mine) {
             const int len = (int)(a1 - a0);
             int hk[K];
@@ -761,7 +767,7 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
             }
             row_nnz[row] = cnt;
         }
-        uint64_t fb = __ballot(valid && !mine);
+        uint64_t fb = __ballot(take && !mine);
         while (fb) {                                   // wave-uniform
             const int r = __builtin_ctzll(fb);
             fb &= fb - 1;
@@ -940,49 +946,43 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
 
 // ===========================================================================
 // Exclusive prefix sum of row_nnz -> row_ptr (int64), fused with the
-// numeric binning histogram.  Three kernels: tile sums, a scan of the tile
-// sums in one workgroup, and the tile scans with their offsets.
+// numeric binning histogram
 // ===========================================================================
 constexpr int kScanBS = 1024;
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kScanBS * kScanPer;
 
-static __global__ void __launch_bounds__(kScanBS)
-k_scan_tiles(int m, const int32_t* __restrict__ cnt, long long* __restrict__ tile_sum) {
-    __shared__ BlockScanSmem<kScanBS> sm;
-    const long long base = (long long)blockIdx.x * kScanTile;
-    long long s = 0;
-#pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-        const long long r = base + (long long)i * kScanBS + threadIdx.x;
-        if (r < m) s += cnt[r];
-    }
-    const long long t = block_sum<kScanBS>(s, sm);
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
+// Single-pass prefix sum with decoupled look-back (Merrill and Garland,
+// 2016).  Workgroups take tiles in ticket order; each publishes its tile
+// total, then walks back over its predecessors' published totals until it
+// meets an inclusive prefix.  A state word packs a 2-bit flag, a 16-bit
+// epoch (the call's number, so that no clearing pass is needed between
+// calls) and a 46-bit value.  The wait is bounded and reports instead of
+// spinning forever.
+constexpr int kFlagAgg = 1, kFlagIncl = 2;
+constexpr unsigned long long kValMask = (1ull << 46) - 1;
+
+__device__ __forceinline__ unsigned long long scan_word(int flag, int epoch, long long v) {
+    return ((unsigned long long)flag << 62) | ((unsigned long long)(epoch & 0xffff) << 46) |
+           ((unsigned long long)v & kValMask);
 }
 
 static __global__ void __launch_bounds__(kScanBS)
-k_scan_tile_sums(int ntiles, long long* __restrict__ tile_sum, DevInfo* info) {
-    __shared__ BlockScanSmem<kScanBS> sm;
-    long long carry = 0;
-    for (int c0 = 0; c0 < ntiles; c0 += kScanBS) {
-        const int i = c0 + threadIdx.x;
-        const long long v = i < ntiles ? tile_sum[i] : 0;
-        long long tot;
-        const long long incl = block_incl_scan<kScanBS>(v, sm, &tot);
-        if (i < ntiles) tile_sum[i] = carry + incl - v;   // exclusive
-        carry += tot;
-    }
-    if (threadIdx.x == 0) info->nnz = carry;
-}
-
-static __global__ void __launch_bounds__(kScanBS)
-k_scan_apply(int m, const int32_t* __restrict__ cnt, const long long* __restrict__ tile_off,
-             int64_t* __restrict__ row_ptr, BinTable bins, DevInfo* info) {
+k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile_state, int epoch,
+                int64_t* __restrict__ row_ptr, BinTable bins, DevInfo* info) {
     __shared__ BlockScanSmem<kScanBS> sm;
     __shared__ int hist[kNB];
+    __shared__ int s_tile;
+    __shared__ long long s_prefix;
     if (threadIdx.x < kNB) hist[threadIdx.x] = 0;
-    const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&info->scan_ticket, 1);
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= (int)gridDim.x) {            // tickets not reset: report, touch nothing
+        if (threadIdx.x == 0) atomicOr(&info->err, kErrProbe);
+        return;
+    }
+    const long long base = (long long)tile * kScanTile + (long long)threadIdx.x * kScanPer;
     int v[kScanPer];
     long long s = 0;
 #pragma unroll
@@ -992,23 +992,72 @@ k_scan_apply(int m, const int32_t* __restrict__ cnt, const long long* __restrict
         s += v[i];
     }
     long long tot;
-    const long long incl = block_incl_scan<kScanBS>(s, sm, &tot);   // has __syncthreads
-    long long run = tile_off[blockIdx.x] + incl - s;
+    const long long incl = block_incl_scan<kScanBS>(s, sm, &tot);
+    if (threadIdx.x < 64) {
+        // wave 0: publish the tile total, then look back over 64 predecessor
+        // states per round trip until an inclusive prefix is found
+        const int lane = threadIdx.x;
+        if (lane == 0)
+            __hip_atomic_store(&tile_state[tile], scan_word(tile == 0 ? kFlagIncl : kFlagAgg, epoch, tot),
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        long long prefix = 0;
+        int p = tile - 1;                       // nearest predecessor not yet added
+        long long spins = 0;
+        while (p >= 0) {
+            const int idx = p - lane;           // lane 0 reads the nearest one
+            int flag = kFlagIncl, ep = epoch & 0xffff;
+            long long val = 0;                  // before tile 0: an empty inclusive prefix
+            if (idx >= 0) {
+                const unsigned long long wd =
+                    __hip_atomic_load(&tile_state[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                flag = (int)(wd >> 62);
+                ep = (int)((wd >> 46) & 0xffff);
+                val = (long long)(wd & kValMask);
+            }
+            const bool ready = flag != 0 && ep == (epoch & 0xffff);
+            const uint64_t incl_mask = __ballot(ready && flag == kFlagIncl);
+            const uint64_t wait_mask = __ballot(!ready);
+            const int first = incl_mask ? __builtin_ctzll(incl_mask) : 64;
+            const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+            if (wait_mask & need) {             // a state we need is not published yet
+                if (++spins > (1LL << 26)) { if (lane == 0) atomicOr(&info->err, kErrProbe); break; }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            long long part = lane <= first ? val : 0;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d);
+            prefix += part;
+            if (first < 64) break;
+            p -= 64;
+        }
+        if (lane == 0) {
+            if (tile > 0)
+                __hip_atomic_store(&tile_state[tile], scan_word(kFlagIncl, epoch, prefix + tot), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = prefix;
+        }
+    }
+    __syncthreads();
+    long long run = s_prefix + incl - s;
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
         const long long r = base + i;
-        if (r < m) row_ptr[r] = run;
+        if (r < m && row_ptr) row_ptr[r] = run;
         run += v[i];
         if (bins.nb > 0) wave_hist_add(hist, r < m ? bin_of(bins, v[i]) : -1);
     }
-    if (m == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) row_ptr[0] = 0;
-    } else if (base <= m - 1 && m - 1 < base + kScanPer) {
-        row_ptr[m] = run;      // the thread holding row m-1 closes row_ptr
+    if (m > 0 && base <= m - 1 && m - 1 < base + kScanPer) {
+        if (row_ptr) row_ptr[m] = run;     // the thread holding row m-1 closes row_ptr
+        info->nnz = run;
+    }
+    if (m == 0 && tile == 0 && threadIdx.x == 0) {
+        if (row_ptr) row_ptr[0] = 0;
+        info->nnz = 0;
     }
     __syncthreads();
     if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
-        atomicAdd(&info->num_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
+        atomicAdd(&info->num_part[tile % kParts][threadIdx.x], hist[threadIdx.x]);
 }
 
 // ===========================================================================

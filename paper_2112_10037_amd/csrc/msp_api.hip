@@ -127,7 +127,15 @@ extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
         delete h;
         return hip_fail(e, "hipHostMalloc");
     }
+    if ((e = hipHostMalloc((void**)&h->hpending, sizeof(int), hipHostMallocDefault)) != hipSuccess) {
+        (void)hipHostFree(h->hinfo);
+        h->info.release();
+        delete h;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    *h->hpending = 0;
     if ((s = configure_kernels(h)) != MSP_OK) {
+        (void)hipHostFree(h->hpending);
         (void)hipHostFree(h->hinfo);
         h->info.release();
         delete h;
@@ -146,6 +154,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     release_extra(h);
     h->prof.release();
     if (h->hinfo) (void)hipHostFree(h->hinfo);
+    if (h->hpending) (void)hipHostFree(h->hpending);
     delete h;
     return MSP_OK;
 }
@@ -329,4 +338,14 @@ extern "C" msp_status msp_profile_get(msp_handle* h, msp_profile* out) {
     h->prof.collect();
     for (int i = 0; i < MSP_NUM_PHASES; ++i) { out->ms[i] = h->prof.ms[i]; out->count[i] = h->prof.count[i]; }
     return MSP_OK;
+}
+
+extern "C" msp_status msp_sync(msp_handle* h) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (h->prof.on) h->prof.collect();
+    return take_pending_error(h);
 }

@@ -231,7 +231,8 @@ static msp_status launch_check(const char* what) {
 
 // symbolic kernel of one bin over `rows` rows listed in perm (or all rows)
 static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
-                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz) {
+                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz,
+                                  const int32_t* ufilter = nullptr, int umax = 0) {
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
     const int m = (int)A->nrows;
@@ -240,9 +241,11 @@ static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, con
         const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4> : (const void*)k_sym_merge<8>;
         const int grid = group_grid(h, fn, rows, 256);
         if (s.lanes == 4)
-            k_sym_merge<4><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, rnnz, info);
+            k_sym_merge<4><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, ufilter, umax,
+                                                 rnnz, info);
         else
-            k_sym_merge<8><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, rnnz, info);
+            k_sym_merge<8><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, ufilter, umax,
+                                                 rnnz, info);
         return launch_check("k_sym_merge");
     } else if (s.kind == Kind::Batch) {
 #define X(T, R)                                                                                  \
@@ -398,13 +401,21 @@ msp_status zero_info(msp_handle* h) {
     return launch_check("k_zero_words");
 }
 
+msp_status take_pending_error(msp_handle* h) {
+    const int pend = *h->hpending;
+    if (!pend) return MSP_OK;
+    *h->hpending = 0;
+    if (pend & kErrProbe) return fail(MSP_ERR_HIP, "internal: hash probe bound exceeded (earlier call)");
+    return fail(MSP_ERR_HIP, "internal: numeric row count differs from symbolic count (earlier call)");
+}
+
 msp_status read_info(msp_handle* h) {
     hipError_t e = hipMemcpyAsync(h->hinfo, h->info.ptr, sizeof(DevInfo), hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(info)");
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (h->prof.on) h->prof.collect();
-    return MSP_OK;
+    return take_pending_error(h);
 }
 
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
@@ -440,19 +451,21 @@ void sum_parts(const int (*part)[kPartStride], int out[kNB]) {
 // Otherwise row ids are scattered into per-bin lists first.
 static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                            const int* counts, const int32_t* key, bool numeric,
-                           const int64_t* crp, int32_t* ccol, void* cval, int32_t* rnnz) {
+                           const int64_t* crp, int32_t* ccol, void* cval, int32_t* rnnz, int done_bin) {
     const int m = (int)A->nrows;
     const int nb = plan.table.nb;
     int nonempty = 0, last = -1;
     bool all_group = true;
     for (int b = 1; b <= nb; ++b)
-        if (counts[b] > 0) {
+        if (counts[b] > 0 && b != done_bin) {
             ++nonempty;
             last = b;
             all_group = all_group && (plan.spec[b].kind == Kind::Group || plan.spec[b].kind == Kind::Batch);
         }
     if (nonempty == 0) return MSP_OK;
-    if (nonempty == 1 || all_group) {
+    // bin done_bin was already processed: its rows must not be taken again
+    const bool done_rows = done_bin > 0 && counts[done_bin] > 0;
+    if (!done_rows && (nonempty == 1 || all_group)) {
         return numeric ? launch_numeric(h, plan.spec[last], m, nullptr, A, B, crp, ccol, cval)
                        : launch_symbolic(h, plan.spec[last], m, nullptr, A, B, rnnz);
     }
@@ -469,7 +482,7 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
     if ((s = launch_check("k_scatter")) != MSP_OK) return s;
     int start = counts[0];
     for (int b = 1; b <= nb; ++b) {
-        if (counts[b] > 0) {
+        if (counts[b] > 0 && b != done_bin) {
             s = numeric ? launch_numeric(h, plan.spec[b], counts[b], perm + start, A, B, crp, ccol, cval)
                         : launch_symbolic(h, plan.spec[b], counts[b], perm + start, A, B, rnnz);
             if (s != MSP_OK) return s;
@@ -480,32 +493,35 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
 }
 
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                             const int* counts_host, int32_t* row_nnz) {
-    return run_bins(h, A, B, plan, counts_host, h->u.as<int32_t>(), false, nullptr, nullptr, nullptr, row_nnz);
+                             const int* counts_host, int32_t* row_nnz, int done_bin) {
+    return run_bins(h, A, B, plan, counts_host, h->u.as<int32_t>(), false, nullptr, nullptr, nullptr, row_nnz,
+                    done_bin);
 }
 
 msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan) {
-    const int tiles = (m + kScanTile - 1) / kScanTile;
-    msp_status s = h->tiles.ensure((size_t)std::max(tiles, 1) * 8);
-    if (s != MSP_OK) return s;
+    const int tiles = std::max(1, (m + kScanTile - 1) / kScanTile);
+    const size_t need = (size_t)tiles * 8;
+    if (need > h->tiles.bytes || h->scan_epoch == 0 || h->scan_epoch >= 0xffff) {
+        // fresh tile states: zero them and restart the epochs
+        msp_status s = h->tiles.ensure(need);
+        if (s != MSP_OK) return s;
+        hipError_t e = hipMemsetAsync(h->tiles.ptr, 0, h->tiles.bytes, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(scan state)");
+        h->scan_epoch = 0;
+    }
+    ++h->scan_epoch;
     BinTable bt;
     memset(&bt, 0, sizeof(bt));
     if (plan) bt = plan->table;
-    if (tiles > 0) {
-        k_scan_tiles<<<tiles, kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<long long>());
-        if ((s = launch_check("k_scan_tiles")) != MSP_OK) return s;
-    }
-    k_scan_tile_sums<<<1, kScanBS, 0, h->stream>>>(tiles, h->tiles.as<long long>(), h->info.as<DevInfo>());
-    if ((s = launch_check("k_scan_tile_sums")) != MSP_OK) return s;
-    k_scan_apply<<<std::max(tiles, 1), kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<long long>(), row_ptr,
-                                                               bt, h->info.as<DevInfo>());
-    return launch_check("k_scan_apply");
+    k_scan_lookback<<<tiles, kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<unsigned long long>(),
+                                                     h->scan_epoch, row_ptr, bt, h->info.as<DevInfo>());
+    return launch_check("k_scan_lookback");
 }
 
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                             const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
                             int32_t* ccol, void* cval, const int32_t*, int) {
-    return run_bins(h, A, B, plan, counts_host, row_nnz, true, crp, ccol, cval, nullptr);
+    return run_bins(h, A, B, plan, counts_host, row_nnz, true, crp, ccol, cval, nullptr, 0);
 }
 
 static msp_status check_pair(const msp_csr* A, const msp_csr* B) {
@@ -552,11 +568,21 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
     if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr)) != MSP_OK) return s;
     h->prof.end(h->stream);
+    // The merge bin (bin 1 when enabled) is queued before the bin counts are
+    // read back: it picks its rows by their bound, so the GPU keeps working
+    // while the host waits for the counts.
+    int done_bin = 0;
+    h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
+    if (m > 0 && sp.table.nb > 1 && sp.spec[1].kind == Kind::Merge) {
+        if ((s = launch_symbolic(h, sp.spec[1], m, nullptr, A, B, h->rnnz.as<int32_t>(), h->u.as<int32_t>(),
+                                 sp.table.umax[1])) != MSP_OK)
+            return s;
+        done_bin = 1;
+    }
     if ((s = read_info(h)) != MSP_OK) return s;
     int counts[kNB];
     sum_parts(h->hinfo->sym_part, counts);
-    h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
-    s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>());
+    s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), done_bin);
     h->prof.end(h->stream);
     return s;
 }
@@ -584,8 +610,7 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
     C->col = nullptr;
     C->val = nullptr;
     auto cleanup = [&](msp_status st) {
-        if (C->col) h->free_fn(h->alloc_ctx, C->col, h->stream);
-        if (C->val) h->free_fn(h->alloc_ctx, C->val, h->stream);
+        if (C->col) h->free_fn(h->alloc_ctx, C->col, h->stream);   // col and val share it
         C->col = nullptr;
         C->val = nullptr;
         if (own_rp) { h->free_fn(h->alloc_ctx, C->row_ptr, h->stream); C->row_ptr = nullptr; }
@@ -608,16 +633,21 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
     C->nnz = nnz;
     C->dtype = A->dtype;
     if (nnz > 0) {
-        C->col = (int32_t*)h->alloc(h->alloc_ctx, (size_t)nnz * 4, h->stream);
-        C->val = h->alloc(h->alloc_ctx, (size_t)nnz * vsz, h->stream);
-        if (!C->col || !C->val) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
+        // one allocation: columns, then values at the next 256-byte boundary
+        const size_t voff = ((size_t)nnz * 4 + 255) & ~(size_t)255;
+        void* base = h->alloc(h->alloc_ctx, voff + (size_t)nnz * vsz, h->stream);
+        if (!base) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
+        C->col = (int32_t*)base;
         h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
-        if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col, C->val,
-                                  nullptr, 0)) != MSP_OK)
+        if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col,
+                                  (char*)base + voff, nullptr, 0)) != MSP_OK)
             return cleanup(s);
         h->prof.end(h->stream);
-        if ((s = read_info(h)) != MSP_OK) return cleanup(s);
-        if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
+        C->val = (char*)base + voff;
+        // the numeric kernels' consistency flags come back without a wait
+        hipError_t e2 = hipMemcpyAsync(h->hpending, &h->info.as<DevInfo>()->err, sizeof(int),
+                                       hipMemcpyDeviceToHost, h->stream);
+        if (e2 != hipSuccess) return cleanup(hip_fail(e2, "hipMemcpyAsync(error flags)"));
     }
     return MSP_OK;
 }
@@ -638,12 +668,8 @@ extern "C" msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const
         e = hipMemcpyAsync(row_nnz, h->rnnz.ptr, (size_t)m * 4, hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(row_nnz)");
     }
-    // total via the scan's tile sums (no row_ptr output needed)
-    const int tiles = (m + kScanTile - 1) / kScanTile;
-    if ((s = h->tiles.ensure((size_t)std::max(tiles, 1) * 8)) != MSP_OK) return s;
-    if (tiles > 0) k_scan_tiles<<<tiles, kScanBS, 0, h->stream>>>(m, h->rnnz.as<int32_t>(), h->tiles.as<long long>());
-    k_scan_tile_sums<<<1, kScanBS, 0, h->stream>>>(tiles, h->tiles.as<long long>(), h->info.as<DevInfo>());
-    if ((s = launch_check("k_scan")) != MSP_OK) return s;
+    // total through the scan (no row_ptr output)
+    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), nullptr, nullptr)) != MSP_OK) return s;
     if ((s = read_info(h)) != MSP_OK) return s;
     if ((s = device_error(h->hinfo->err)) != MSP_OK) return s;
     if (nnz_total) *nnz_total = h->hinfo->nnz;

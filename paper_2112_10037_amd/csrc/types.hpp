@@ -25,8 +25,9 @@ constexpr int kPartStride = 32;    // ints per partition row (128 bytes)
 
 struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
-    int err;
-    int pad[29];
+    int err;                              // error bits of the current call
+    int scan_ticket;                      // tile tickets of the single-pass scan
+    int pad[28];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
