@@ -162,8 +162,8 @@ msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const msp_csr* B
                                const msp_opts* opts);
 
 /* Per-row features of A*B (device outputs, A.nrows rows each; any pointer
- * may be NULL): prod (int64), and the 8 FP32 predictor features per row
- * (row-major m x 8): log2(1+x) of nnz(A(i,:)), prod_i, min/mean/max
+ * may be NULL): prod (int64), and the 8 FP32 predictor inputs per row
+ * (row-major m x 8): log2(1+x)/16 of nnz(A(i,:)), prod_i, min/mean/max
  * nnz(B(k,:)) and ncols(B), then min(1, prod_i/n) and span_i/n, where
  * span_i is the largest minus the smallest column index over the B rows
  * A(i,:) selects. */

@@ -153,8 +153,8 @@ def row_stats(A, B, r0: int = 0, r1: int | None = None) -> dict:
 
 
 def features(A, B) -> np.ndarray:
-    """The 8 per-row predictor features (FP64), from ``row_stats``:
-    log2(1+x) of nnz_a, prod, min_b, mean_b, max_b and ncols(B); then
+    """The 8 per-row predictor inputs (FP64), from ``row_stats``:
+    log2(1+x)/16 of nnz_a, prod, min_b, mean_b, max_b and ncols(B); then
     min(1, prod/ncols(B)) and span/ncols(B)."""
     s = row_stats(A, B)
     n = max(int(B.ncols), 1)
@@ -162,12 +162,12 @@ def features(A, B) -> np.ndarray:
     prod = s["prod"].astype(np.float64)
     mean_b = np.divide(prod, nnz_a, out=np.zeros_like(prod), where=nnz_a > 0)
     f = np.empty((A.nrows, 8), dtype=np.float64)
-    f[:, 0] = np.log2(1.0 + nnz_a)
-    f[:, 1] = np.log2(1.0 + prod)
-    f[:, 2] = np.log2(1.0 + s["min_b"])
-    f[:, 3] = np.log2(1.0 + mean_b)
-    f[:, 4] = np.log2(1.0 + s["max_b"])
-    f[:, 5] = np.log2(1.0 + float(B.ncols))
+    f[:, 0] = np.log2(1.0 + nnz_a) / 16.0
+    f[:, 1] = np.log2(1.0 + prod) / 16.0
+    f[:, 2] = np.log2(1.0 + s["min_b"]) / 16.0
+    f[:, 3] = np.log2(1.0 + mean_b) / 16.0
+    f[:, 4] = np.log2(1.0 + s["max_b"]) / 16.0
+    f[:, 5] = np.log2(1.0 + float(B.ncols)) / 16.0
     f[:, 6] = np.minimum(1.0, prod / n)
     f[:, 7] = s["span"] / n
     return f

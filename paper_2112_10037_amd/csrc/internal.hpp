@@ -98,13 +98,13 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill);
 msp_status read_info(msp_handle* h);
 msp_status zero_info(msp_handle* h);
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                         int64_t* prod_out, float* feat);
+                         int64_t* prod_out, float* feat, int32_t* lo_out);
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                              const int* counts_host, int32_t* row_nnz, int done_bin);
 msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan);
 msp_status take_pending_error(msp_handle* h);
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                            const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
-                            int32_t* ccol, void* cval, const int32_t* perm_override, int perm_rows);
+                            const int* counts_host, const int32_t* key, const int64_t* crp,
+                            int32_t* ccol, void* cval, int32_t* cnt_out);
 
 }  // namespace msp

@@ -183,7 +183,7 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             int32_t* __restrict__ u_out, int64_t* __restrict__ prod_out,
             int32_t* __restrict__ row_nnz, BinTable bins, DevInfo* info,
-            float* __restrict__ feat) {
+            float* __restrict__ feat, int32_t* __restrict__ lo_out) {
     __shared__ int hist[kNB];
     __shared__ long long s_rp[4][65];
     __shared__ unsigned long long s_prod[4][64];
@@ -243,14 +243,15 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
             const double n = (double)(ncols > 0 ? ncols : 1);
             const float mean = len > 0 ? (float)((double)s / (double)len) : 0.f;
             float* f = feat + row * 8;
-            f[0] = log2f(1.f + (float)len);
-            f[1] = log2f(1.f + (float)s);
-            f[2] = log2f(1.f + (float)mn);
-            f[3] = log2f(1.f + mean);
-            f[4] = log2f(1.f + (float)mx);
-            f[5] = log2f(1.f + (float)ncols);
+            f[0] = log2f(1.f + (float)len) * kFeatLogScale;
+            f[1] = log2f(1.f + (float)s) * kFeatLogScale;
+            f[2] = log2f(1.f + (float)mn) * kFeatLogScale;
+            f[3] = log2f(1.f + mean) * kFeatLogScale;
+            f[4] = log2f(1.f + (float)mx) * kFeatLogScale;
+            f[5] = log2f(1.f + (float)ncols) * kFeatLogScale;
             f[6] = fminf(1.f, (float)((double)s / n));
             f[7] = (float)((double)(hi < 0 ? 0 : hi - lo) / n);
+            if (lo_out) lo_out[row] = mx;
         }
     }
     if (bins.nb > 0) wave_hist_add(hist, bin);
@@ -517,6 +518,7 @@ struct WaveRows {
     long long c1[RM];         // C row end (numeric)
     int row[RM];
     int cnt[RM];
+    int ovf[RM];              // capacity mode: the row's table overflowed
 };
 
 // Take the next batch starting at slot pos (< hi); returns the number of
@@ -544,6 +546,7 @@ __device__ __forceinline__ int wave_rows_take(WaveRows<RM>& wr, long long pos, l
         wr.a0[lane] = a0;
         wr.row[lane] = r;
         wr.cnt[lane] = 0;
+        wr.ovf[lane] = 0;
         if (NUMERIC) { wr.c0[lane] = crp[r]; wr.c1[lane] = crp[r + 1]; }
     }
     if (lane == nb - 1) wr.off[nb] = incl;
@@ -623,7 +626,7 @@ k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
            const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-           DevInfo* info) {
+           int32_t* __restrict__ cnt_out, DevInfo* info) {
     constexpr int KS = T + 4;                 // 16-byte aligned key rows, shifted banks
     constexpr int L = T < 64 ? T : 64;        // extraction lanes per row
     __shared__ __align__(16) int32_t keys_all[4][RM][KS];
@@ -659,8 +662,11 @@ k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     if (j[u] != kEmpty) {
-                        const int h = hash_slot_of<T>(keys[r], j[u], &err);
+                        int e2 = 0;
+                        const int h = hash_slot_of<T>(keys[r], j[u], &e2);
                         if (h >= 0) atomicAdd(&vals[r][h], a * v[u]);
+                        else if (cnt_out) wr.ovf[r] = 1;
+                        else err |= e2;
                     }
             }
         }
@@ -685,7 +691,11 @@ k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
             }
         }
         lds_fence();
-        if (lane < nb && wr.cnt[lane] != (int)(wr.c1[lane] - wr.c0[lane])) err |= 2;
+        if (lane < nb) {
+            const int cap = (int)(wr.c1[lane] - wr.c0[lane]);
+            if (cnt_out) cnt_out[wr.row[lane]] = (wr.ovf[lane] || wr.cnt[lane] > cap) ? -1 : wr.cnt[lane];
+            else if (wr.cnt[lane] != cap) err |= 2;
+        }
         lds_fence();
         pos += nb;
     }
@@ -803,7 +813,7 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            DevInfo* info) {
+            int32_t* __restrict__ cnt_out, DevInfo* info) {
     constexpr int FT = kMergeFT;
     constexpr int SN = kMergeStage;
     static_assert(SN >= FT / 2, "a fallback row must fit the staging area");
@@ -877,7 +887,8 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
                 if (t < nn) { st_k[w][so + t] = m; st_v[w][so + t] = acc; }
                 ++t;
             }
-            if (t != nn) err |= 2;
+            if (cnt_out) cnt_out[row] = t <= nn ? t : -1;
+            else if (t != nn) err |= 2;
         }
         // rows with more than K A entries: the whole wave, one row at a time
         uint64_t fb = __ballot(in && !mine);
@@ -886,7 +897,9 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
             fb &= fb - 1;
             const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
             const long long fnn = __shfl(nn, r);
+            const int frow = __shfl(row, r);
             const int fso = st_off[w][r];
+            int fe = 0;
             for (int i = lane; i < FT; i += 64) { fb_keys[w][i] = kEmpty; fb_vals[w][i] = 0.0; }
             lds_fence();
             for (long long p = fa0; p < fa1; ++p) {
@@ -894,10 +907,11 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
                 const double a = to_f64(aval[p]);
                 const long long q1 = brp[kk + 1];
                 for (long long q = brp[kk] + lane; q < q1; q += 64) {
-                    const int h = hash_slot_of<FT>(fb_keys[w], bcol[q], &err);
+                    const int h = hash_slot_of<FT>(fb_keys[w], bcol[q], &fe);
                     if (h >= 0) atomicAdd(&fb_vals[w][h], a * to_f64(bval[q]));
                 }
             }
+            const bool failed = __ballot(fe != 0) != 0;
             lds_fence();
             int c = 0;
             for (int sl = lane; sl < FT; sl += 64) {
@@ -913,7 +927,12 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
                 ++c;
             }
             c = group_sum<64>(c);
-            if (c != fnn) err |= 2;
+            if (cnt_out) {
+                if (lane == 0) cnt_out[frow] = (failed || c > fnn) ? -1 : c;
+            } else {
+                if (failed) err |= 1;
+                if (c != fnn) err |= 2;
+            }
             lds_fence();
         }
         lds_fence();
@@ -1075,7 +1094,7 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            DevInfo* info) {
+            int32_t* __restrict__ cnt_out, DevInfo* info) {
     constexpr int NG = GroupCfg<G>::NG;
     constexpr int CK = T / 2 + 4;                 // compacted keys, 16-byte rows
     __shared__ int32_t keys[NG][T + 1];
@@ -1097,6 +1116,7 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
     const long long hi = lo + per < nrows_bin ? lo + per : nrows_bin;
     for (long long slot = lo + g; slot < hi; slot += NG) {      // group-uniform
     const int row = perm ? perm[slot] : (int)slot;
+    int re = 0;                                  // this row's table overflowed
 #pragma unroll
     for (int s = gl; s < T; s += G) { kt[s] = kEmpty; vt[s] = 0.0; }
     lds_fence();
@@ -1123,7 +1143,7 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
             const long long bi = s_bst[g][t] + q;
             const int32_t j = bcol[bi];
             const double prod = s_a[g][t] * to_f64(bval[bi]);
-            const int h = hash_slot_of<T>(kt, j, &err);
+            const int h = hash_slot_of<T>(kt, j, &re);
             if (h >= 0) atomicAdd(&vt[h], prod);
         }
         lds_fence();
@@ -1144,8 +1164,13 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
     }
     const long long rp = crp[row];
     const int expect = (int)(crp[row + 1] - rp);
-    if (n != expect || n > T / 2) {
-        if (gl == 0) atomicOr(&info->err, kErrCount);
+    const bool failed = group_ballot<G>(re != 0, lane) != 0;
+    if (cnt_out) {                               // capacity mode
+        const bool fits = !failed && n <= expect && n <= T / 2;
+        if (gl == 0) cnt_out[row] = fits ? n : -1;
+        if (!fits) { lds_fence(); continue; }
+    } else if (failed || n != expect || n > T / 2) {
+        if (gl == 0) atomicOr(&info->err, failed ? kErrProbe : kErrCount);
         lds_fence();
         continue;
     }
@@ -1176,7 +1201,7 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            DevInfo* info) {
+            int32_t* __restrict__ cnt_out, DevInfo* info) {
     constexpr int PER = T / BS;    // slots per thread in the compaction
     static_assert(PER >= 1, "T must be >= BS");
     __shared__ int32_t keys[T];
@@ -1185,11 +1210,13 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
     __shared__ long long s_bst[BS];
     __shared__ double s_a[BS];
     __shared__ BlockScanSmem<BS> sm;
+    __shared__ int s_fail;
     const int tid = threadIdx.x;
     int err = 0;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
         for (int s = tid; s < T; s += BS) { keys[s] = kEmpty; vals[s] = 0.0; }
+        if (tid == 0) s_fail = 0;
         __syncthreads();
         const long long a0 = arp[row], a1 = arp[row + 1];
         for (long long c0 = a0; c0 < a1; c0 += BS) {
@@ -1214,8 +1241,10 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
                 const long long bi = s_bst[t] + q;
                 const int32_t j = bcol[bi];
                 const double prod = s_a[t] * to_f64(bval[bi]);
-                const int h = hash_slot_of<T>(keys, j, &err);
+                int e2 = 0;
+                const int h = hash_slot_of<T>(keys, j, &e2);
                 if (h >= 0) atomicAdd(&vals[h], prod);
+                else s_fail = 1;
             }
             __syncthreads();
         }
@@ -1234,7 +1263,9 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
         int pos = (int)(incl - c);
         const long long rp = crp[row];
         const int expect = (int)(crp[row + 1] - rp);
-        const bool bad = (n != expect) || (n > T / 2);
+        const bool failed = s_fail != 0;         // read after the scan's barriers
+        const bool bad = cnt_out ? (failed || n > expect || n > T / 2) : (failed || n != expect || n > T / 2);
+        if (cnt_out && tid == 0) cnt_out[row] = bad ? -1 : (int)n;
         if (!bad) {
 #pragma unroll
             for (int i = 0; i < PER; ++i)
@@ -1246,7 +1277,7 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
             for (int s = (int)n + tid; s < P; s += BS) keys[s] = 0x7fffffff;   // pad: sorts last
         __syncthreads();
         if (bad) {
-            if (tid == 0) atomicOr(&info->err, kErrCount);
+            if (tid == 0 && !cnt_out) atomicOr(&info->err, failed ? kErrProbe : kErrCount);
             continue;
         }
         // bitonic sort of keys[0..P) ascending, values follow
@@ -1289,7 +1320,7 @@ k_num_dense(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            double* dslab, uint32_t* gbm, DevInfo* info) {
+            double* dslab, uint32_t* gbm, int32_t* __restrict__ cnt_out, DevInfo* info) {
     extern __shared__ uint32_t dyn_smem[];
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -1335,8 +1366,9 @@ k_num_dense(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
         }
         __threadfence();
         __syncthreads();
-        // ordered extraction
+        // ordered extraction (writes stay inside the row's range)
         const long long rp = crp[row];
+        const long long rend = crp[row + 1];
         long long run = 0;
         for (long long w0 = 0; w0 < words; w0 += BS) {
             const long long w = w0 + tid;
@@ -1351,15 +1383,21 @@ k_num_dense(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
                 bits &= bits - 1;
                 const long long col = w * 32 + b;
                 const double v = load_coherent(&dense[col]);
-                ccol[pos] = (int32_t)col;
-                cval[pos] = (VT)v;
+                if (pos < rend) {
+                    ccol[pos] = (int32_t)col;
+                    cval[pos] = (VT)v;
+                }
                 dense[col] = 0.0;
                 ++pos;
             }
             if (w < words && !LDSBM) gbm[(long long)blockIdx.x * words + w] = 0u;
             run += tot;
         }
-        if (tid == 0 && run != crp[row + 1] - rp) atomicOr(&info->err, kErrCount);
+        if (tid == 0) {
+            const long long cap = rend - rp;
+            if (cnt_out) cnt_out[row] = run <= cap ? (int)run : -1;
+            else if (run != cap) atomicOr(&info->err, kErrCount);
+        }
         __threadfence();
         __syncthreads();
     }

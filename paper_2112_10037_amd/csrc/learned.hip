@@ -1,0 +1,690 @@
+// Learned output-size predictor and the one-pass product it enables.
+//
+// The network is a fully connected 8-64-64-1 ReLU MLP in FP32.  Its inputs
+// are the per-row features of the row-statistics kernel; its output
+// estimates log2(1 + row_nnz) / 16.  The capacity of row i is
+//     cap_i = clamp(ceil(2^(16 y_i + delta)), lo_i, hi_i)
+// with the exact bounds lo_i = max_k nnz(B(k,:)) (the union is at least its
+// largest set) and hi_i = min(prod_i, ncols(B)); delta is a calibrated
+// quantile of the training residuals.  Rows whose bounds are small take
+// cap_i = hi_i without running the network.
+//
+// The one-pass product bins rows by capacity, runs the numeric kernels in
+// capacity mode into a padded C (each row's true count, or -1 when it did
+// not fit), recomputes the overflowed rows exactly with the plain two-phase
+// path on the sub-matrix of those rows, and compacts everything into a
+// tight CSR.  The structure is exact whatever the network predicts.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "msp.h"
+
+using namespace msp;
+
+namespace msp {
+
+constexpr int kNF = 8, kH1 = 64, kH2 = 64;
+constexpr int kOffW1 = 0, kOffB1 = 512, kOffW2 = 576, kOffB2 = 4672, kOffW3 = 4736, kOffB3 = 4800;
+constexpr int kNParam = 4801;
+constexpr int kSmallCap = 32;      // rows with hi <= this skip the network
+
+// ---------------------------------------------------------------------------
+// network evaluation (weights in LDS, one row per thread)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float mlp_eval(const float* __restrict__ w, const float* __restrict__ xin) {
+    float x[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f) x[f] = xin[f];
+    float h1[kH1];
+#pragma unroll
+    for (int i = 0; i < kH1; ++i) {
+        float z = w[kOffB1 + i];
+#pragma unroll
+        for (int f = 0; f < kNF; ++f) z += w[kOffW1 + i * kNF + f] * x[f];
+        h1[i] = z > 0.f ? z : 0.f;
+    }
+    float y = w[kOffB3];
+    for (int j = 0; j < kH2; ++j) {
+        float z = w[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kH1; ++i) z += w[kOffW2 + j * kH1 + i] * h1[i];
+        y += w[kOffW3 + j] * (z > 0.f ? z : 0.f);
+    }
+    return y;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_predict(long long n, const float* __restrict__ feats, const float* __restrict__ params, float* __restrict__ y) {
+    __shared__ float w[kNParam];
+    for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
+    __syncthreads();
+    for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < n; r += (long long)gridDim.x * 256)
+        y[r] = mlp_eval(w, feats + r * kNF);
+}
+
+// capacity rule; rows with small bounds skip the network
+__global__ void __launch_bounds__(256)
+k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ hi, const int32_t* __restrict__ lo,
+           const float* __restrict__ params, float delta, int32_t* __restrict__ cap) {
+    __shared__ float w[kNParam];
+    for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
+    __syncthreads();
+    for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < m; r += (long long)gridDim.x * 256) {
+        const int h = hi[r];
+        const int l = lo[r] < h ? lo[r] : h;
+        int c = h;
+        if (h > kSmallCap && l < h) {
+            const float y = mlp_eval(w, feats + r * kNF);
+            const double est = exp2((double)(16.f * y + delta));
+            c = est >= (double)h ? h : (int)ceil(est);
+            c = c < l ? l : c;
+        }
+        cap[r] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training: forward + per-sample backward, gradient reduction, Adam
+// ---------------------------------------------------------------------------
+// Per sample s of the batch: activations and the backward deltas of the
+// mean-squared error, stored for the reduction kernel.
+__global__ void __launch_bounds__(256)
+k_mlp_fwd_bwd(int batch, const int32_t* __restrict__ idx, const float* __restrict__ feats,
+              const float* __restrict__ targets, const float* __restrict__ params,
+              float* __restrict__ X, float* __restrict__ H1, float* __restrict__ H2,
+              float* __restrict__ DZ1, float* __restrict__ DZ2, float* __restrict__ D) {
+    __shared__ float w[kNParam];
+    for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
+    __syncthreads();
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= batch) return;
+    const long long r = idx[s];
+    float x[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f) { x[f] = feats[r * kNF + f]; X[(long long)s * kNF + f] = x[f]; }
+    float h1[kH1];
+#pragma unroll
+    for (int i = 0; i < kH1; ++i) {
+        float z = w[kOffB1 + i];
+#pragma unroll
+        for (int f = 0; f < kNF; ++f) z += w[kOffW1 + i * kNF + f] * x[f];
+        h1[i] = z > 0.f ? z : 0.f;
+        H1[(long long)s * kH1 + i] = h1[i];
+    }
+    float y = w[kOffB3];
+    float h2pos[kH2];                   // h2_j (0 where z2_j <= 0)
+    for (int j = 0; j < kH2; ++j) {
+        float z = w[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kH1; ++i) z += w[kOffW2 + j * kH1 + i] * h1[i];
+        const float h2 = z > 0.f ? z : 0.f;
+        h2pos[j] = h2;
+        H2[(long long)s * kH2 + j] = h2;
+        y += w[kOffW3 + j] * h2;
+    }
+    const float d = y - targets[r];
+    D[s] = d;
+    const float dy = 2.f * d / (float)batch;
+    float dz1[kH1];
+#pragma unroll
+    for (int i = 0; i < kH1; ++i) dz1[i] = 0.f;
+    for (int j = 0; j < kH2; ++j) {
+        const float dz2 = h2pos[j] > 0.f ? dy * w[kOffW3 + j] : 0.f;
+        DZ2[(long long)s * kH2 + j] = dz2;
+#pragma unroll
+        for (int i = 0; i < kH1; ++i) dz1[i] += w[kOffW2 + j * kH1 + i] * dz2;
+    }
+#pragma unroll
+    for (int i = 0; i < kH1; ++i) DZ1[(long long)s * kH1 + i] = h1[i] > 0.f ? dz1[i] : 0.f;
+}
+
+// One thread per parameter: its gradient is a sum over the batch, taken in
+// sample order (deterministic) in FP64.  The b3 thread also writes the loss.
+__global__ void __launch_bounds__(256)
+k_mlp_grad(int batch, const float* __restrict__ X, const float* __restrict__ H1, const float* __restrict__ H2,
+           const float* __restrict__ DZ1, const float* __restrict__ DZ2, const float* __restrict__ D,
+           float* __restrict__ grad, float* __restrict__ loss) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kNParam) return;
+    double acc = 0.0;
+    const double scale = 2.0 / (double)batch;
+    if (p < kOffB1) {
+        const int i = p / kNF, f = p % kNF;
+        for (int s = 0; s < batch; ++s) acc += (double)DZ1[(long long)s * kH1 + i] * X[(long long)s * kNF + f];
+    } else if (p < kOffW2) {
+        const int i = p - kOffB1;
+        for (int s = 0; s < batch; ++s) acc += DZ1[(long long)s * kH1 + i];
+    } else if (p < kOffB2) {
+        const int q = p - kOffW2, j = q / kH1, i = q % kH1;
+        for (int s = 0; s < batch; ++s) acc += (double)DZ2[(long long)s * kH2 + j] * H1[(long long)s * kH1 + i];
+    } else if (p < kOffW3) {
+        const int j = p - kOffB2;
+        for (int s = 0; s < batch; ++s) acc += DZ2[(long long)s * kH2 + j];
+    } else if (p < kOffB3) {
+        const int j = p - kOffW3;
+        for (int s = 0; s < batch; ++s) acc += scale * D[s] * H2[(long long)s * kH2 + j];
+    } else {
+        double l = 0.0;
+        for (int s = 0; s < batch; ++s) {
+            acc += scale * D[s];
+            l += (double)D[s] * D[s];
+        }
+        if (loss) *loss = (float)(l / batch);
+    }
+    grad[p] = (float)acc;
+}
+
+// Adam (Kingma and Ba, 2015) with bias-corrected moments; step is 1-based.
+__global__ void __launch_bounds__(256)
+k_adam(float* __restrict__ params, const float* __restrict__ grad, float* __restrict__ m, float* __restrict__ v,
+       int step, float lr, float beta1, float beta2, float eps) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kNParam) return;
+    const float g = grad[p];
+    const float mm = beta1 * m[p] + (1.f - beta1) * g;
+    const float vv = beta2 * v[p] + (1.f - beta2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float mhat = mm / (1.f - powf(beta1, (float)step));
+    const float vhat = vv / (1.f - powf(beta2, (float)step));
+    params[p] -= lr * mhat / (sqrtf(vhat) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// one-pass product helpers
+// ---------------------------------------------------------------------------
+// Overflowed rows (cnt < 0): list them in row order per wave, with their A
+// lengths, and count them.
+__global__ void __launch_bounds__(256)
+k_collect_overflow(int m, const int32_t* __restrict__ cnt, const int64_t* __restrict__ arp,
+                   int32_t* __restrict__ list, int* __restrict__ count, unsigned long long* __restrict__ sum_len) {
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool o = r < m && cnt[r] < 0;
+    const int lane = threadIdx.x & 63;
+    const uint64_t mask = __ballot(o);
+    if (!mask) return;
+    int base = 0;
+    const int leader = __builtin_ctzll(mask);
+    if (lane == leader) base = atomicAdd(count, __builtin_popcountll(mask));
+    base = __shfl(base, leader);
+    if (o) {
+        list[base + __builtin_popcountll(mask & ((1ull << lane) - 1))] = (int32_t)r;
+        atomicAdd(sum_len, (unsigned long long)(arp[r + 1] - arp[r]));
+    }
+}
+
+// Row pointers of the gathered sub-matrix (rows of A listed in `list`),
+// computed serially per block chunk: lens then a single-block scan.
+__global__ void __launch_bounds__(1024)
+k_sub_rowptr(int ns, const int32_t* __restrict__ list, const int64_t* __restrict__ arp, int64_t* __restrict__ srp) {
+    __shared__ BlockScanSmem<1024> sm;
+    long long carry = 0;
+    for (int c0 = 0; c0 < ns; c0 += 1024) {
+        const int j = c0 + threadIdx.x;
+        const long long len = j < ns ? arp[list[j] + 1] - arp[list[j]] : 0;
+        long long tot;
+        const long long incl = block_incl_scan<1024>(len, sm, &tot);
+        if (j < ns) srp[j] = carry + incl - len;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) srp[ns] = carry;
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256)
+k_sub_gather(int ns, const int32_t* __restrict__ list, const int64_t* __restrict__ arp,
+             const int32_t* __restrict__ acol, const VT* __restrict__ aval, const int64_t* __restrict__ srp,
+             int32_t* __restrict__ scol, VT* __restrict__ sval) {
+    // one wave per listed row
+    const long long wid = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wid >= ns) return;
+    const long long a0 = arp[list[wid]], a1 = arp[list[wid] + 1], d0 = srp[wid];
+    for (long long p = a0 + lane; p < a1; p += 64) {
+        scol[d0 + p - a0] = acol[p];
+        sval[d0 + p - a0] = aval[p];
+    }
+}
+
+// Overflowed rows take their counts and sources from the sub-product.
+__global__ void __launch_bounds__(256)
+k_patch_overflow(int ns, const int32_t* __restrict__ list, const int64_t* __restrict__ crp_sub,
+                 int32_t* __restrict__ cnt, int64_t* __restrict__ src_off) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= ns) return;
+    const int r = list[j];
+    cnt[r] = (int32_t)(crp_sub[j + 1] - crp_sub[j]);
+    src_off[r] = -(crp_sub[j] + 1);              // negative: from the sub-product
+}
+
+// Compaction: a wave copies 64 consecutive rows, whose destination range is
+// contiguous; each destination entry finds its row by binary search over
+// the 65 row pointers in LDS.  A row's source is the padded product at
+// rp_pad[row], or the sub-product when src_off[row] < 0.
+template <typename VT>
+__global__ void __launch_bounds__(256)
+k_compact(int m, const int64_t* __restrict__ rp, const int64_t* __restrict__ rp_pad,
+          const int64_t* __restrict__ src_off, const int32_t* __restrict__ pcol, const VT* __restrict__ pval,
+          const int32_t* __restrict__ scol, const VT* __restrict__ sval,
+          int32_t* __restrict__ ccol, VT* __restrict__ cval) {
+    __shared__ long long s_rp[4][65];
+    __shared__ long long s_src[4][64];
+    __shared__ int s_sub[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long r0 = ((long long)blockIdx.x * 4 + w) * 64;
+    if (r0 >= m) return;
+    const int nr = (int)(m - r0 < 64 ? m - r0 : 64);
+    if (lane < nr) {
+        s_rp[w][lane] = rp[r0 + lane];
+        const long long so = src_off ? src_off[r0 + lane] : 0;
+        s_sub[w][lane] = so < 0;
+        s_src[w][lane] = so < 0 ? -so - 1 : rp_pad[r0 + lane];
+    }
+    if (lane == 0) s_rp[w][nr] = rp[r0 + nr];
+    lds_fence();
+    const long long d0 = s_rp[w][0], d1 = s_rp[w][nr];
+    for (long long d = d0 + lane; d < d1; d += 64) {
+        int lo = 0, hi = nr;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_rp[w][mid] <= d) lo = mid; else hi = mid;
+        }
+        const long long src = s_src[w][lo] + (d - s_rp[w][lo]);
+        if (s_sub[w][lo]) { ccol[d] = scol[src]; cval[d] = sval[src]; }
+        else { ccol[d] = pcol[src]; cval[d] = pval[src]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// predictor object
+// ---------------------------------------------------------------------------
+struct ExtraState {
+    DevBuf feat, lo, cap, rp_pad, cnt, src_off, pad, list, sub_rp, sub_a, sub_c, sub_crp;
+};
+
+static ExtraState* extra(msp_handle* h) {
+    if (!h->extra) h->extra = new (std::nothrow) ExtraState();
+    return h->extra;
+}
+
+void release_extra(msp_handle* h) {
+    if (!h->extra) return;
+    ExtraState* x = h->extra;
+    for (DevBuf* b : {&x->feat, &x->lo, &x->cap, &x->rp_pad, &x->cnt, &x->src_off, &x->pad, &x->list, &x->sub_rp,
+                      &x->sub_a, &x->sub_c, &x->sub_crp})
+        b->release();
+    delete x;
+    h->extra = nullptr;
+}
+
+static msp_status launch_check2(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return MSP_OK;
+}
+
+}  // namespace msp
+
+struct msp_predictor {
+    int device = 0;
+    msp::DevBuf params, m, v, grad, loss, X, H1, H2, DZ1, DZ2, D;
+    int batch_cap = 0;
+    float delta = 0.f;
+    long long step = 0;
+};
+
+extern "C" msp_status msp_predictor_create(msp_handle* h, const float* init_params, msp_predictor** out) {
+    if (!h || !init_params || !out) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    msp_predictor* p = new (std::nothrow) msp_predictor();
+    if (!p) return fail(MSP_ERR_OOM, "host allocation failed");
+    p->device = h->device;
+    msp_status s;
+    for (DevBuf* b : {&p->params, &p->m, &p->v, &p->grad}) {
+        if ((s = b->ensure(kNParam * sizeof(float))) != MSP_OK) { delete p; return s; }
+        if ((e = hipMemsetAsync(b->ptr, 0, kNParam * sizeof(float), h->stream)) != hipSuccess) {
+            delete p;
+            return hip_fail(e, "hipMemsetAsync");
+        }
+    }
+    if ((e = hipMemcpyAsync(p->params.ptr, init_params, kNParam * sizeof(float), hipMemcpyHostToDevice, h->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMemcpyAsync(params)");
+    }
+    *out = p;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_destroy(msp_predictor* p) {
+    if (!p) return MSP_OK;
+    (void)hipSetDevice(p->device);
+    for (DevBuf* b : {&p->params, &p->m, &p->v, &p->grad, &p->loss, &p->X, &p->H1, &p->H2, &p->DZ1, &p->DZ2, &p->D})
+        b->release();
+    delete p;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_get(msp_handle* h, const msp_predictor* p, float* params, float* delta) {
+    if (!h || !p) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    if (params) {
+        hipError_t e = hipMemcpyAsync(params, p->params.ptr, kNParam * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(params)");
+    }
+    if (delta) *delta = p->delta;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_set(msp_handle* h, msp_predictor* p, const float* params, float delta) {
+    if (!h || !p) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    if (params) {
+        hipError_t e = hipMemcpyAsync(p->params.ptr, params, kNParam * sizeof(float), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(params)");
+    }
+    p->delta = delta;
+    return MSP_OK;
+}
+
+static msp_status ensure_batch(msp_predictor* p, int batch) {
+    if (batch <= p->batch_cap) return MSP_OK;
+    msp_status s;
+    const size_t b = (size_t)batch;
+    if ((s = p->X.ensure(b * kNF * 4)) != MSP_OK || (s = p->H1.ensure(b * kH1 * 4)) != MSP_OK ||
+        (s = p->H2.ensure(b * kH2 * 4)) != MSP_OK || (s = p->DZ1.ensure(b * kH1 * 4)) != MSP_OK ||
+        (s = p->DZ2.ensure(b * kH2 * 4)) != MSP_OK || (s = p->D.ensure(b * 4)) != MSP_OK)
+        return s;
+    p->batch_cap = batch;
+    return MSP_OK;
+}
+
+// one forward/backward + gradient reduction on batch rows idx[0..batch)
+static msp_status grad_step(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+                            const int32_t* idx, int batch, float* loss_dev) {
+    msp_status s = ensure_batch(p, batch);
+    if (s != MSP_OK) return s;
+    k_mlp_fwd_bwd<<<(batch + 255) / 256, 256, 0, h->stream>>>(
+        batch, idx, feats, targets, p->params.as<float>(), p->X.as<float>(), p->H1.as<float>(), p->H2.as<float>(),
+        p->DZ1.as<float>(), p->DZ2.as<float>(), p->D.as<float>());
+    if ((s = launch_check2("k_mlp_fwd_bwd")) != MSP_OK) return s;
+    k_mlp_grad<<<(kNParam + 255) / 256, 256, 0, h->stream>>>(batch, p->X.as<float>(), p->H1.as<float>(),
+                                                              p->H2.as<float>(), p->DZ1.as<float>(),
+                                                              p->DZ2.as<float>(), p->D.as<float>(),
+                                                              p->grad.as<float>(), loss_dev);
+    return launch_check2("k_mlp_grad");
+}
+
+extern "C" msp_status msp_predictor_grad(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+                                         const int32_t* idx, int batch, float* grad_host, float* loss_host) {
+    if (!h || !p || !feats || !targets || !idx || batch <= 0) return fail(MSP_ERR_INVALID_ARG, "bad argument");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    msp_status s = p->loss.ensure(sizeof(float));
+    if (s != MSP_OK) return s;
+    if ((s = grad_step(h, p, feats, targets, idx, batch, p->loss.as<float>())) != MSP_OK) return s;
+    if (grad_host &&
+        (e = hipMemcpyAsync(grad_host, p->grad.ptr, kNParam * 4, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(grad)");
+    if (loss_host && (e = hipMemcpyAsync(loss_host, p->loss.ptr, 4, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(loss)");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_train(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+                                          int64_t n, const int32_t* batch_idx, int steps, int batch,
+                                          const msp_train_opts* o, float* losses_host) {
+    if (!h || !p || !feats || !targets || !batch_idx || n <= 0 || steps < 0 || batch <= 0)
+        return fail(MSP_ERR_INVALID_ARG, "bad argument");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const float lr = o && o->lr > 0 ? o->lr : 1e-3f;
+    const float b1 = o && o->beta1 > 0 ? o->beta1 : 0.9f;
+    const float b2 = o && o->beta2 > 0 ? o->beta2 : 0.999f;
+    const float eps = o && o->eps > 0 ? o->eps : 1e-8f;
+    msp_status s = p->loss.ensure((size_t)std::max(steps, 1) * sizeof(float));
+    if (s != MSP_OK) return s;
+    for (int t = 0; t < steps; ++t) {
+        if ((s = grad_step(h, p, feats, targets, batch_idx + (size_t)t * batch, batch, p->loss.as<float>() + t)) !=
+            MSP_OK)
+            return s;
+        ++p->step;
+        k_adam<<<(kNParam + 255) / 256, 256, 0, h->stream>>>(p->params.as<float>(), p->grad.as<float>(),
+                                                             p->m.as<float>(), p->v.as<float>(), (int)p->step, lr, b1,
+                                                             b2, eps);
+        if ((s = launch_check2("k_adam")) != MSP_OK) return s;
+    }
+    if (losses_host && steps > 0 &&
+        (e = hipMemcpyAsync(losses_host, p->loss.ptr, (size_t)steps * 4, hipMemcpyDeviceToHost, h->stream)) !=
+            hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(losses)");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_infer(msp_handle* h, const msp_predictor* p, const float* feats, int64_t n,
+                                          float* y) {
+    if (!h || !p || (n > 0 && (!feats || !y)) || n < 0) return fail(MSP_ERR_INVALID_ARG, "bad argument");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (n == 0) return MSP_OK;
+    const long long blocks = std::min<long long>((n + 255) / 256, 8LL * h->num_cu);
+    k_mlp_predict<<<(int)blocks, 256, 0, h->stream>>>(n, feats, p->params.as<float>(), y);
+    return launch_check2("k_mlp_predict");
+}
+
+// delta = the q-quantile of 16 (t - y) over the rows given (log2 units).
+extern "C" msp_status msp_predictor_calibrate(msp_handle* h, msp_predictor* p, const float* feats,
+                                              const float* targets, int64_t n, double q) {
+    if (!h || !p || !feats || !targets || n <= 0 || !(q > 0 && q < 1)) return fail(MSP_ERR_INVALID_ARG, "bad argument");
+    DevBuf y;
+    msp_status s = y.ensure((size_t)n * 4);
+    if (s != MSP_OK) return s;
+    if ((s = msp_predictor_infer(h, p, feats, n, y.as<float>())) != MSP_OK) { y.release(); return s; }
+    std::vector<float> yh((size_t)n), th((size_t)n);
+    hipError_t e = hipMemcpyAsync(yh.data(), y.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(th.data(), targets, (size_t)n * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    y.release();
+    if (e != hipSuccess) return hip_fail(e, "calibration copy");
+    std::vector<float> res((size_t)n);
+    for (size_t i = 0; i < (size_t)n; ++i) res[i] = 16.f * (th[i] - yh[i]);
+    const size_t k = std::min((size_t)n - 1, (size_t)std::ceil(q * (double)n) - 1);
+    std::nth_element(res.begin(), res.begin() + k, res.end());
+    p->delta = res[k];
+    return MSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the one-pass product
+// ---------------------------------------------------------------------------
+extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, const msp_csr* A, const msp_csr* B,
+                                         msp_csr_out* C, const msp_opts* opts, msp_learned_stats* st) {
+    if (!h || !p) return fail(MSP_ERR_INVALID_ARG, "null handle or predictor");
+    if (!C) return fail(MSP_ERR_INVALID_ARG, "C is NULL");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    ExtraState* x = extra(h);
+    if (!x) return fail(MSP_ERR_OOM, "host allocation failed");
+    const msp_tuning t = effective_tuning(h, opts);
+    const int m = (int)A->nrows;
+    const size_t vsz = A->dtype == MSP_F64 ? 8 : 4;
+    if (opts && opts->validate && (s = validate_inputs(h, A, B)) != MSP_OK) return s;
+    msp_learned_stats stats;
+    memset(&stats, 0, sizeof(stats));
+
+    const size_t mm = (size_t)std::max(m, 1);
+    if ((s = h->rnnz.ensure(mm * 4)) != MSP_OK || (s = x->feat.ensure(mm * kNF * 4)) != MSP_OK ||
+        (s = x->lo.ensure(mm * 4)) != MSP_OK || (s = x->cap.ensure(mm * 4)) != MSP_OK ||
+        (s = x->rp_pad.ensure((mm + 1) * 8)) != MSP_OK || (s = x->cnt.ensure(mm * 4)) != MSP_OK)
+        return s;
+
+    bool own_rp = false;
+    if (!C->row_ptr) {
+        C->row_ptr = (int64_t*)h->alloc(h->alloc_ctx, (size_t)(m + 1) * 8, h->stream);
+        if (!C->row_ptr) return fail(MSP_ERR_OOM, "allocation of C.row_ptr failed");
+        own_rp = true;
+    }
+    C->col = nullptr;
+    C->val = nullptr;
+    auto cleanup = [&](msp_status r) {
+        if (C->col) h->free_fn(h->alloc_ctx, C->col, h->stream);
+        C->col = nullptr;
+        C->val = nullptr;
+        if (own_rp) { h->free_fn(h->alloc_ctx, C->row_ptr, h->stream); C->row_ptr = nullptr; }
+        return r;
+    };
+
+    // 1. features and bounds, 2. capacities
+    BinPlan none;
+    memset(&none, 0, sizeof(none));
+    if ((s = zero_info(h)) != MSP_OK) return cleanup(s);
+    h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
+    if ((s = run_row_stats(h, A, B, none, nullptr, x->feat.as<float>(), x->lo.as<int32_t>())) != MSP_OK)
+        return cleanup(s);
+    h->prof.end(h->stream);
+    h->prof.begin(MSP_PHASE_PREDICT, h->stream);
+    if (m > 0) {
+        const int blocks = std::min((m + 255) / 256, 8 * h->num_cu);
+        k_capacity<<<blocks, 256, 0, h->stream>>>(m, x->feat.as<float>(), h->u.as<int32_t>(), x->lo.as<int32_t>(),
+                                                  p->params.as<float>(), p->delta, x->cap.as<int32_t>());
+        if ((s = launch_check2("k_capacity")) != MSP_OK) return cleanup(s);
+    }
+    h->prof.end(h->stream);
+    // 3. padded row pointers and bins by capacity
+    const BinPlan np = numeric_plan(t, opts && opts->force_spill);
+    h->prof.begin(MSP_PHASE_SCAN, h->stream);
+    if ((s = run_scan(h, m, x->cap.as<int32_t>(), x->rp_pad.as<int64_t>(), &np)) != MSP_OK) return cleanup(s);
+    h->prof.end(h->stream);
+    if ((s = read_info(h)) != MSP_OK) return cleanup(s);
+    if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
+    const long long sum_cap = h->hinfo->nnz;
+    stats.sum_cap = sum_cap;
+    int counts[kNB];
+    sum_parts(h->hinfo->num_part, counts);
+    // 4. numeric pass in capacity mode into the padded area
+    if ((s = x->pad.ensure((size_t)std::max(sum_cap, 1LL) * (4 + vsz) + 256)) != MSP_OK) return cleanup(s);
+    int32_t* pcol = x->pad.as<int32_t>();
+    char* pval = (char*)x->pad.ptr + (((size_t)std::max(sum_cap, 1LL) * 4 + 255) & ~(size_t)255);
+    if ((s = zero_info(h)) != MSP_OK) return cleanup(s);
+    h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
+    if ((s = run_numeric_bins(h, A, B, np, counts, x->cap.as<int32_t>(), x->rp_pad.as<int64_t>(), pcol, pval,
+                              x->cnt.as<int32_t>())) != MSP_OK)
+        return cleanup(s);
+    h->prof.end(h->stream);
+    // 5. final row pointers (overflowed rows count 0 for now) and overflow count
+    h->prof.begin(MSP_PHASE_COMPACT, h->stream);
+    if ((s = zero_info(h)) != MSP_OK) return cleanup(s);
+    if ((s = run_scan(h, m, x->cnt.as<int32_t>(), C->row_ptr, nullptr)) != MSP_OK) return cleanup(s);
+    h->prof.end(h->stream);
+    if ((s = read_info(h)) != MSP_OK) return cleanup(s);
+    if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
+    const int novf = h->hinfo->neg_count;
+    stats.overflow_rows = novf;
+    int64_t* src_off = nullptr;
+    int32_t* scol = nullptr;
+    char* sval = nullptr;
+    if (novf > 0) {
+        // 6. exact recomputation of the overflowed rows on their sub-matrix
+        h->prof.begin(MSP_PHASE_FALLBACK, h->stream);
+        if ((s = x->list.ensure((size_t)novf * 4)) != MSP_OK || (s = x->src_off.ensure(mm * 8)) != MSP_OK ||
+            (s = x->sub_rp.ensure(((size_t)novf + 1) * 8)) != MSP_OK)
+            return cleanup(s);
+        if ((e = hipMemsetAsync(x->src_off.ptr, 0, mm * 8, h->stream)) != hipSuccess)
+            return cleanup(hip_fail(e, "hipMemsetAsync"));
+        if ((s = zero_info(h)) != MSP_OK) return cleanup(s);
+        DevInfo* info = h->info.as<DevInfo>();
+        k_collect_overflow<<<(m + 255) / 256, 256, 0, h->stream>>>(m, x->cnt.as<int32_t>(), A->row_ptr,
+                                                                   x->list.as<int32_t>(), &info->neg_count,
+                                                                   (unsigned long long*)&info->nnz);
+        if ((s = launch_check2("k_collect_overflow")) != MSP_OK) return cleanup(s);
+        if ((s = read_info(h)) != MSP_OK) return cleanup(s);
+        const long long sub_nnz = h->hinfo->nnz;
+        if (h->hinfo->neg_count != novf) return cleanup(fail(MSP_ERR_HIP, "internal: overflow list size"));
+        if ((s = x->sub_a.ensure((size_t)std::max(sub_nnz, 1LL) * (4 + vsz) + 256)) != MSP_OK) return cleanup(s);
+        int32_t* sacol = x->sub_a.as<int32_t>();
+        char* saval = (char*)x->sub_a.ptr + (((size_t)std::max(sub_nnz, 1LL) * 4 + 255) & ~(size_t)255);
+        k_sub_rowptr<<<1, 1024, 0, h->stream>>>(novf, x->list.as<int32_t>(), A->row_ptr, x->sub_rp.as<int64_t>());
+        if ((s = launch_check2("k_sub_rowptr")) != MSP_OK) return cleanup(s);
+        const int gb = (int)(((long long)novf * 64 + 255) / 256);
+        if (A->dtype == MSP_F64)
+            k_sub_gather<double><<<gb, 256, 0, h->stream>>>(novf, x->list.as<int32_t>(), A->row_ptr, A->col,
+                                                            (const double*)A->val, x->sub_rp.as<int64_t>(), sacol,
+                                                            (double*)saval);
+        else
+            k_sub_gather<float><<<gb, 256, 0, h->stream>>>(novf, x->list.as<int32_t>(), A->row_ptr, A->col,
+                                                           (const float*)A->val, x->sub_rp.as<int64_t>(), sacol,
+                                                           (float*)saval);
+        if ((s = launch_check2("k_sub_gather")) != MSP_OK) return cleanup(s);
+        msp_csr Asub{novf, A->ncols, sub_nnz, x->sub_rp.as<int64_t>(), sacol, saval, A->dtype};
+        if ((s = x->sub_crp.ensure(((size_t)novf + 1) * 8)) != MSP_OK) return cleanup(s);
+        msp_csr_out Csub;
+        memset(&Csub, 0, sizeof(Csub));
+        Csub.row_ptr = x->sub_crp.as<int64_t>();
+        DevBuf* subc = &x->sub_c;
+        auto ws_alloc = [subc](size_t bytes) -> void* {
+            if (subc->ensure(std::max(bytes, (size_t)256)) != MSP_OK) return nullptr;
+            return subc->ptr;
+        };
+        msp_opts so;
+        memset(&so, 0, sizeof(so));
+        so.tuning = t;
+        if ((s = spgemm_core(h, &Asub, B, &Csub, &so, ws_alloc)) != MSP_OK) return cleanup(s);
+        scol = Csub.col;
+        sval = (char*)Csub.val;
+        k_patch_overflow<<<(novf + 255) / 256, 256, 0, h->stream>>>(novf, x->list.as<int32_t>(), Csub.row_ptr,
+                                                                    x->cnt.as<int32_t>(), x->src_off.as<int64_t>());
+        if ((s = launch_check2("k_patch_overflow")) != MSP_OK) return cleanup(s);
+        if ((s = zero_info(h)) != MSP_OK) return cleanup(s);
+        if ((s = run_scan(h, m, x->cnt.as<int32_t>(), C->row_ptr, nullptr)) != MSP_OK) return cleanup(s);
+        if ((s = read_info(h)) != MSP_OK) return cleanup(s);
+        if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
+        if (h->hinfo->neg_count != 0) return cleanup(fail(MSP_ERR_HIP, "internal: rows left after the fallback"));
+        src_off = x->src_off.as<int64_t>();
+        h->prof.end(h->stream);
+    }
+    // 7. tight output
+    const long long nnz = h->hinfo->nnz;
+    stats.nnz = nnz;
+    C->nrows = m;
+    C->ncols = B->ncols;
+    C->nnz = nnz;
+    C->dtype = A->dtype;
+    if (nnz > 0) {
+        const size_t voff = ((size_t)nnz * 4 + 255) & ~(size_t)255;
+        void* base = h->alloc(h->alloc_ctx, voff + (size_t)nnz * vsz, h->stream);
+        if (!base) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
+        C->col = (int32_t*)base;
+        C->val = (char*)base + voff;
+        h->prof.begin(MSP_PHASE_COMPACT, h->stream);
+        const int blocks = (m + 255) / 256;
+        if (A->dtype == MSP_F64)
+            k_compact<double><<<blocks, 256, 0, h->stream>>>(m, C->row_ptr, x->rp_pad.as<int64_t>(), src_off, pcol,
+                                                             (const double*)pval, scol, (const double*)sval, C->col,
+                                                             (double*)C->val);
+        else
+            k_compact<float><<<blocks, 256, 0, h->stream>>>(m, C->row_ptr, x->rp_pad.as<int64_t>(), src_off, pcol,
+                                                            (const float*)pval, scol, (const float*)sval, C->col,
+                                                            (float*)C->val);
+        if ((s = launch_check2("k_compact")) != MSP_OK) return cleanup(s);
+        h->prof.end(h->stream);
+        hipError_t e2 = hipMemcpyAsync(h->hpending, &h->info.as<DevInfo>()->err, sizeof(int), hipMemcpyDeviceToHost,
+                                       h->stream);
+        if (e2 != hipSuccess) return cleanup(hip_fail(e2, "hipMemcpyAsync(error flags)"));
+    }
+    if (st) *st = stats;
+    return MSP_OK;
+}

@@ -302,7 +302,7 @@ static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, con
 template <typename VT>
 static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
                                    const msp_csr* A, const msp_csr* B, const int64_t* crp,
-                                   int32_t* ccol, VT* cval) {
+                                   int32_t* ccol, VT* cval, int32_t* cnt_out) {
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
     const VT* av = (const VT*)A->val;
@@ -313,7 +313,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
     {                                                                                                 \
         const int grid = group_grid(h, (const void*)k_num_merge<KK, VT, IT>, rows, 256);             \
         k_num_merge<KK, VT, IT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
-                                                      B->col, bv, crp, ccol, cval, info);            \
+                                                      B->col, bv, crp, ccol, cval, cnt_out, info);   \
         return launch_check("k_num_merge");                                                           \
     }
         if (s.lanes == 4) { if (small) MSP_MERGE(4, int) else MSP_MERGE(4, long long) }
@@ -324,7 +324,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
     if (s.slots == T && s.lanes == R) {                                                            \
         const int grid = group_grid(h, (const void*)k_num_wave<T, R, VT>, rows, 4 * R);           \
         k_num_wave<T, R, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr,  \
-                                                    B->col, bv, crp, ccol, cval, info);           \
+                                                    B->col, bv, crp, ccol, cval, cnt_out, info);  \
         return launch_check("k_num_wave");                                                        \
     }
         MSP_NUM_BATCH_SHAPES(X)
@@ -334,7 +334,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
     if (s.lanes == G && s.slots == T) {                                                           \
         const int grid = group_grid(h, (const void*)k_num_group<G, T, VT>, rows, 256 / G);       \
         k_num_group<G, T, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
-                                                    B->col, bv, crp, ccol, cval, info);          \
+                                                    B->col, bv, crp, ccol, cval, cnt_out, info); \
         return launch_check("k_num_group");                                                       \
     }
         MSP_GROUP_SHAPES(X)
@@ -344,7 +344,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
 #define X(BS, T)                                                                                  \
     if (s.lanes == BS && s.slots == T) {                                                          \
         k_num_block<BS, T, VT><<<grid, BS, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
-                                                    B->col, bv, crp, ccol, cval, info);          \
+                                                    B->col, bv, crp, ccol, cval, cnt_out, info); \
         return launch_check("k_num_block");                                                       \
     }
         MSP_NUM_BLOCK_SHAPES(X)
@@ -374,11 +374,11 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
         if (lds)
             k_num_dense<1024, true, VT><<<grid, 1024, words * 4, st>>>(
                 rows, perm, n, A->row_ptr, A->col, av, B->row_ptr, B->col, bv, crp, ccol, cval,
-                h->dslab.as<double>(), nullptr, info);
+                h->dslab.as<double>(), nullptr, cnt_out, info);
         else
             k_num_dense<1024, false, VT><<<grid, 1024, 0, st>>>(
                 rows, perm, n, A->row_ptr, A->col, av, B->row_ptr, B->col, bv, crp, ccol, cval,
-                h->dslab.as<double>(), h->gbm.as<uint32_t>(), info);
+                h->dslab.as<double>(), h->gbm.as<uint32_t>(), cnt_out, info);
         return launch_check("k_num_dense");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no numeric kernel for bin shape (%d, %d)", s.lanes, s.slots);
@@ -386,10 +386,11 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
 
 static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
                                  const msp_csr* A, const msp_csr* B, const int64_t* crp,
-                                 int32_t* ccol, void* cval) {
+                                 int32_t* ccol, void* cval, int32_t* cnt_out) {
     if (rows <= 0) return MSP_OK;
-    if (A->dtype == MSP_F64) return launch_numeric_t<double>(h, s, rows, perm, A, B, crp, ccol, (double*)cval);
-    return launch_numeric_t<float>(h, s, rows, perm, A, B, crp, ccol, (float*)cval);
+    if (A->dtype == MSP_F64)
+        return launch_numeric_t<double>(h, s, rows, perm, A, B, crp, ccol, (double*)cval, cnt_out);
+    return launch_numeric_t<float>(h, s, rows, perm, A, B, crp, ccol, (float*)cval, cnt_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -419,7 +420,7 @@ msp_status read_info(msp_handle* h) {
 }
 
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                         int64_t* prod_out, float* feat) {
+                         int64_t* prod_out, float* feat, int32_t* lo_out) {
     const int m = (int)A->nrows;
     msp_status s = h->u.ensure((size_t)std::max(m, 1) * 4);
     if (s != MSP_OK) return s;
@@ -428,11 +429,11 @@ msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, cons
     if (feat)
         k_row_stats<true><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                       h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
-                                                      plan.table, h->info.as<DevInfo>(), feat);
+                                                      plan.table, h->info.as<DevInfo>(), feat, lo_out);
     else
         k_row_stats<false><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                        h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
-                                                       plan.table, h->info.as<DevInfo>(), nullptr);
+                                                       plan.table, h->info.as<DevInfo>(), nullptr, nullptr);
     return launch_check("k_row_stats");
 }
 
@@ -451,7 +452,8 @@ void sum_parts(const int (*part)[kPartStride], int out[kNB]) {
 // Otherwise row ids are scattered into per-bin lists first.
 static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                            const int* counts, const int32_t* key, bool numeric,
-                           const int64_t* crp, int32_t* ccol, void* cval, int32_t* rnnz, int done_bin) {
+                           const int64_t* crp, int32_t* ccol, void* cval, int32_t* rnnz, int done_bin,
+                           int32_t* cnt_out = nullptr) {
     const int m = (int)A->nrows;
     const int nb = plan.table.nb;
     int nonempty = 0, last = -1;
@@ -466,7 +468,7 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
     // bin done_bin was already processed: its rows must not be taken again
     const bool done_rows = done_bin > 0 && counts[done_bin] > 0;
     if (!done_rows && (nonempty == 1 || all_group)) {
-        return numeric ? launch_numeric(h, plan.spec[last], m, nullptr, A, B, crp, ccol, cval)
+        return numeric ? launch_numeric(h, plan.spec[last], m, nullptr, A, B, crp, ccol, cval, cnt_out)
                        : launch_symbolic(h, plan.spec[last], m, nullptr, A, B, rnnz);
     }
     msp_status s = h->perm.ensure((size_t)m * 4);
@@ -483,7 +485,7 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
     int start = counts[0];
     for (int b = 1; b <= nb; ++b) {
         if (counts[b] > 0 && b != done_bin) {
-            s = numeric ? launch_numeric(h, plan.spec[b], counts[b], perm + start, A, B, crp, ccol, cval)
+            s = numeric ? launch_numeric(h, plan.spec[b], counts[b], perm + start, A, B, crp, ccol, cval, cnt_out)
                         : launch_symbolic(h, plan.spec[b], counts[b], perm + start, A, B, rnnz);
             if (s != MSP_OK) return s;
         }
@@ -519,9 +521,9 @@ msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_p
 }
 
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                            const int* counts_host, const int32_t* row_nnz, const int64_t* crp,
-                            int32_t* ccol, void* cval, const int32_t*, int) {
-    return run_bins(h, A, B, plan, counts_host, row_nnz, true, crp, ccol, cval, nullptr, 0);
+                            const int* counts_host, const int32_t* key, const int64_t* crp,
+                            int32_t* ccol, void* cval, int32_t* cnt_out) {
+    return run_bins(h, A, B, plan, counts_host, key, true, crp, ccol, cval, nullptr, 0, cnt_out);
 }
 
 static msp_status check_pair(const msp_csr* A, const msp_csr* B) {
@@ -566,7 +568,7 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     const BinPlan sp = symbolic_plan(t, opts && opts->force_spill);
     if ((s = zero_info(h)) != MSP_OK) return s;
     h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
-    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr)) != MSP_OK) return s;
+    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr)) != MSP_OK) return s;
     h->prof.end(h->stream);
     // The merge bin (bin 1 when enabled) is queued before the bin counts are
     // read back: it picks its rows by their bound, so the GPU keeps working
@@ -640,7 +642,7 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
         C->col = (int32_t*)base;
         h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
         if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col,
-                                  (char*)base + voff, nullptr, 0)) != MSP_OK)
+                                  (char*)base + voff, nullptr)) != MSP_OK)
             return cleanup(s);
         h->prof.end(h->stream);
         C->val = (char*)base + voff;
@@ -688,7 +690,7 @@ extern "C" msp_status msp_row_features(msp_handle* h, const msp_csr* A, const ms
     BinPlan none;
     memset(&none, 0, sizeof(none));
     if ((s = zero_info(h)) != MSP_OK) return s;
-    return run_row_stats(h, A, B, none, prod, features ? features : nullptr);
+    return run_row_stats(h, A, B, none, prod, features ? features : nullptr, nullptr);
 }
 
 extern "C" int msp_internal_unsupported_plans(int verbose) { return msp::count_unsupported_plans(verbose); }

@@ -16,6 +16,10 @@ constexpr int kErrUnsorted = 2;   // input columns not strictly increasing
 constexpr int kErrRange = 4;      // input index out of range / row_ptr not monotone
 constexpr int kErrCount = 8;      // numeric count disagrees with the symbolic count
 
+// Predictor features 0..5 are log2(1 + x) scaled by this factor so that
+// every network input is of order one.
+constexpr float kFeatLogScale = 1.0f / 16.0f;
+
 // Global bin counters are split over kParts partitions (workgroup w counts
 // into partition w % kParts), each padded to its own 128-byte line, so that
 // thousands of workgroups do not serialise on one address.
