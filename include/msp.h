@@ -170,6 +170,74 @@ msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const msp_csr* B
 msp_status msp_row_features(msp_handle* h, const msp_csr* A, const msp_csr* B,
                             int64_t* prod, float* features);
 
+/* ---- learned output-size predictor -------------------------------------- */
+
+/*
+ * An FP32 multilayer perceptron 8 -> 64 -> 64 -> 1 (ReLU) that maps the 8
+ * per-row inputs of msp_row_features to an estimate y of log2(1+row_nnz)/16.
+ * Parameters are one flat array of 4801 floats:
+ *     W1[64][8] b1[64] W2[64][64] b2[64] W3[64] b3[1]
+ * (hidden unit h of layer 1 is relu(sum_f W1[h][f] x[f] + b1[h])).
+ * The predictor is not part of the paper; it sizes the accumulators and the
+ * output of msp_spgemm_learned.
+ */
+typedef struct msp_predictor msp_predictor;
+
+typedef struct {
+    float lr, beta1, beta2, eps;   /* Adam; 0 selects 1e-3, 0.9, 0.999, 1e-8 */
+} msp_train_opts;
+
+typedef struct {
+    int64_t overflow_rows;   /* rows recomputed on the exact path          */
+    int64_t sum_cap;         /* total predicted capacity (padded entries)   */
+    int64_t nnz;             /* nnz(C)                                      */
+} msp_learned_stats;
+
+/* Create on the handle's device from 4801 host floats (copied). */
+msp_status msp_predictor_create(msp_handle* h, const float* init_params, msp_predictor** p);
+msp_status msp_predictor_destroy(msp_predictor* p);
+/* Copy the parameters to the host (params may be NULL) and the capacity
+ * margin delta; set them from the host (params NULL keeps them). */
+msp_status msp_predictor_get(msp_handle* h, const msp_predictor* p, float* params, float* delta);
+msp_status msp_predictor_set(msp_handle* h, msp_predictor* p, const float* params, float delta);
+/* Train with Adam on the mean squared error, `steps` mini-batches of
+ * `batch` rows: batch_idx (device, steps x batch int32) names rows of
+ * feats (device, n x 8) and targets (device, n).  losses_host (steps
+ * floats) receives each step's loss when not NULL.  Synchronises. */
+msp_status msp_predictor_train(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+                               int64_t n, const int32_t* batch_idx, int steps, int batch,
+                               const msp_train_opts* o, float* losses_host);
+/* Gradient of the mean squared error on one batch at the current
+ * parameters: idx (device, batch int32) names rows of feats (device, n x 8)
+ * and targets (device, n); host outputs: 4801 floats and the loss.
+ * Synchronises.  Indices outside [0, n) give MSP_ERR_INVALID_ARG (also in
+ * msp_predictor_train, whose parameters are then already updated). */
+msp_status msp_predictor_grad(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+                              int64_t n, const int32_t* idx, int batch, float* grad_host, float* loss_host);
+/* Training rows of A*B: the 8 inputs of msp_row_features and the target
+ * log2(1 + row_nnz_i) / 16 from the symbolic pass (device outputs, A.nrows
+ * rows).  Synchronises. */
+msp_status msp_training_rows(msp_handle* h, const msp_csr* A, const msp_csr* B, float* features,
+                             float* targets);
+/* y (device, n floats) = network output for feats (device, n x 8). */
+msp_status msp_predictor_infer(msp_handle* h, const msp_predictor* p, const float* feats, int64_t n, float* y);
+/* delta = the q-quantile of 16 (target - y) over the given rows. */
+msp_status msp_predictor_calibrate(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+                                   int64_t n, double q);
+
+/*
+ * C = A * B in one pass: per-row capacities
+ *     cap_i = clamp(ceil(2^(16 y_i + delta)), max_k nnz(B(k,:)), min(prod_i, n))
+ * (rows with min(prod_i, n) <= 32 take that bound without the network),
+ * rows binned by capacity, numeric kernels writing into a padded buffer,
+ * the rows that did not fit recomputed exactly (two-phase path on their
+ * sub-matrix), and a compaction into tight CSR.  The result equals
+ * msp_spgemm's (identical structure) for any predictor.  Two host reads in
+ * the common case, four when rows overflow.  `st` may be NULL.
+ */
+msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, const msp_csr* A, const msp_csr* B,
+                              msp_csr_out* C, const msp_opts* opts, msp_learned_stats* st);
+
 /* ---- timing ------------------------------------------------------------- */
 
 /* Phases timed with HIP events on the handle's stream when profiling is on. */

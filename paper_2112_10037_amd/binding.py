@@ -52,6 +52,15 @@ class c_opts(ctypes.Structure):
                 ("tuning", c_tuning)]
 
 
+class c_train_opts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class c_learned_stats(ctypes.Structure):
+    _fields_ = [("overflow_rows", ctypes.c_int64), ("sum_cap", ctypes.c_int64), ("nnz", ctypes.c_int64)]
+
+
 NUM_PHASES = 8
 PHASES = ["row_stats", "symbolic", "scan", "numeric", "predict", "fallback", "compact", "batch"]
 
@@ -81,6 +90,26 @@ SIGNATURES = [
                                            ctypes.POINTER(c_opts)]),
     ("msp_row_features", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    ("msp_predictor_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    ("msp_predictor_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("msp_predictor_get", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_float)]),
+    ("msp_predictor_set", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float]),
+    ("msp_predictor_train", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(c_train_opts), ctypes.c_void_p]),
+    ("msp_predictor_grad", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    ("msp_predictor_infer", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p]),
+    ("msp_predictor_calibrate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_double]),
+    ("msp_training_rows", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    ("msp_spgemm_learned", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(c_csr),
+                                          ctypes.POINTER(c_csr), ctypes.POINTER(c_csr_out),
+                                          ctypes.POINTER(c_opts), ctypes.POINTER(c_learned_stats)]),
     ("msp_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("msp_profile_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_profile)]),
     ("msp_status_string", ctypes.c_char_p, [ctypes.c_int]),
@@ -254,6 +283,45 @@ class Handle:
             self.sync()
         return DeviceCSR(A.nrows, B.ncols, rp, col, val)
 
+    def spgemm_learned(self, pred: "Predictor", A: DeviceCSR, B: DeviceCSR, validate=False,
+                       force_spill=False, tuning=None, check=True):
+        """C = A * B in one pass sized by the predictor; returns (C, stats)."""
+        torch = self._torch
+        a, b = A.c(), B.c()
+        out = c_csr_out()
+        rp = torch.empty(A.nrows + 1, dtype=torch.int64, device=f"cuda:{self.device}")
+        out.row_ptr = rp.data_ptr()
+        st = c_learned_stats()
+        o = _opts(validate, force_spill, tuning)
+        _check(self._lib.msp_spgemm_learned(self._h, pred._p, ctypes.byref(a), ctypes.byref(b),
+                                            ctypes.byref(out), ctypes.byref(o), ctypes.byref(st)))
+        nnz = int(out.nnz)
+        vdt = torch.float64 if out.dtype == MSP_F64 else torch.float32
+        if nnz > 0:
+            col, val = self._take_c(out.col, nnz, vdt)
+        else:
+            col = torch.empty(0, dtype=torch.int32, device=rp.device)
+            val = torch.empty(0, dtype=vdt, device=rp.device)
+        if check:
+            self.sync()
+        stats = {"overflow_rows": int(st.overflow_rows), "sum_cap": int(st.sum_cap), "nnz": int(st.nnz)}
+        return DeviceCSR(A.nrows, B.ncols, rp, col, val), stats
+
+    def training_rows(self, A: DeviceCSR, B: DeviceCSR, feats=None, targets=None):
+        """(features m x 8, targets m) float32 for the rows of A*B; writes
+        into the given tensors (views into a larger training set) if any."""
+        torch = self._torch
+        m = A.nrows
+        if feats is None:
+            feats = torch.empty((max(m, 1), 8), dtype=torch.float32, device=f"cuda:{self.device}")
+        if targets is None:
+            targets = torch.empty(max(m, 1), dtype=torch.float32, device=f"cuda:{self.device}")
+        a, b = A.c(), B.c()
+        _check(self._lib.msp_training_rows(self._h, ctypes.byref(a), ctypes.byref(b),
+                                           ctypes.c_void_p(feats.data_ptr()),
+                                           ctypes.c_void_p(targets.data_ptr())))
+        return feats[:m], targets[:m]
+
     def symbolic(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False, tuning=None):
         """(row_nnz int32 tensor, nnz(C)) from the symbolic pass alone."""
         torch = self._torch
@@ -277,3 +345,76 @@ class Handle:
                                           ctypes.c_void_p(prod.data_ptr()),
                                           ctypes.c_void_p(feat.data_ptr())))
         return prod[:m], feat[:m]
+
+
+NPARAM = 4801
+
+
+class Predictor:
+    """The FP32 8-64-64-1 output-size network on the handle's device."""
+
+    def __init__(self, handle: Handle, params):
+        self.h = handle
+        self._lib = handle._lib
+        self._p = ctypes.c_void_p()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == NPARAM
+        _check(self._lib.msp_predictor_create(handle._h, p.ctypes.data_as(ctypes.c_void_p),
+                                              ctypes.byref(self._p)))
+
+    def close(self):
+        if self._p:
+            self._lib.msp_predictor_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get(self):
+        out = np.zeros(NPARAM, dtype=np.float32)
+        d = ctypes.c_float()
+        _check(self._lib.msp_predictor_get(self.h._h, self._p, out.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.byref(d)))
+        return out, float(d.value)
+
+    def set(self, params=None, delta: float = 0.0):
+        ptr = None
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            ptr = p.ctypes.data_as(ctypes.c_void_p)
+        _check(self._lib.msp_predictor_set(self.h._h, self._p, ptr, ctypes.c_float(delta)))
+
+    def train(self, feats, targets, batch_idx, lr=1e-3):
+        """feats (n x 8), targets (n) float32 and batch_idx (steps x batch)
+        int32 device tensors; returns the per-step losses."""
+        steps, batch = batch_idx.shape
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        o = c_train_opts(lr, 0.0, 0.0, 0.0)
+        _check(self._lib.msp_predictor_train(self.h._h, self._p, feats.data_ptr(), targets.data_ptr(),
+                                             feats.shape[0], batch_idx.data_ptr(), steps, batch,
+                                             ctypes.byref(o), losses.ctypes.data_as(ctypes.c_void_p)))
+        return losses[:steps]
+
+    def grad(self, feats, targets, idx):
+        g = np.zeros(NPARAM, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check(self._lib.msp_predictor_grad(self.h._h, self._p, feats.data_ptr(), targets.data_ptr(),
+                                            feats.shape[0], idx.data_ptr(), idx.numel(),
+                                            g.ctypes.data_as(ctypes.c_void_p),
+                                            loss.ctypes.data_as(ctypes.c_void_p)))
+        return float(loss[0]), g
+
+    def infer(self, feats):
+        import torch
+        y = torch.empty(max(feats.shape[0], 1), dtype=torch.float32, device=feats.device)
+        _check(self._lib.msp_predictor_infer(self.h._h, self._p, feats.data_ptr(), feats.shape[0],
+                                             y.data_ptr()))
+        return y[: feats.shape[0]]
+
+    def calibrate(self, feats, targets, q=0.99):
+        _check(self._lib.msp_predictor_calibrate(self.h._h, self._p, feats.data_ptr(), targets.data_ptr(),
+                                                 feats.shape[0], ctypes.c_double(q)))
+        return self.get()[1]

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 #include "msp.h"
@@ -103,6 +104,11 @@ msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, 
                              const int* counts_host, int32_t* row_nnz, int done_bin);
 msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan);
 msp_status take_pending_error(msp_handle* h);
+msp_status check_pair(const msp_csr* A, const msp_csr* B);
+msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B);
+msp_status device_error(int err);
+msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C, const msp_opts* opts,
+                       const std::function<void*(size_t)>& alloc_cv, const std::function<void(void*)>& free_cv);
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                             const int* counts_host, const int32_t* key, const int64_t* crp,
                             int32_t* ccol, void* cval, int32_t* cnt_out);

@@ -1004,11 +1004,19 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
     const long long base = (long long)tile * kScanTile + (long long)threadIdx.x * kScanPer;
     int v[kScanPer];
     long long s = 0;
+    int neg = 0;
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
         const long long r = base + i;
         v[i] = r < m ? cnt[r] : 0;
+        if (v[i] < 0) { ++neg; v[i] = 0; }   // an overflowed row: counted, sums as 0
         s += v[i];
+    }
+    if (__ballot(neg != 0)) {
+        int wn = neg;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) wn += __shfl_xor(wn, d);
+        if ((threadIdx.x & 63) == 0 && wn) atomicAdd(&info->neg_count, wn);
     }
     long long tot;
     const long long incl = block_incl_scan<kScanBS>(s, sm, &tot);

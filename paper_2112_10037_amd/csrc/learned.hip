@@ -51,42 +51,53 @@ __device__ __forceinline__ float mlp_eval(const float* __restrict__ w, const flo
         h1[i] = z > 0.f ? z : 0.f;
     }
     float y = w[kOffB3];
+#pragma unroll 1
     for (int j = 0; j < kH2; ++j) {
+        const float4* row = reinterpret_cast<const float4*>(w + kOffW2 + j * kH1);
         float z = w[kOffB2 + j];
 #pragma unroll
-        for (int i = 0; i < kH1; ++i) z += w[kOffW2 + j * kH1 + i] * h1[i];
+        for (int i4 = 0; i4 < kH1 / 4; ++i4) {
+            const float4 q = row[i4];
+            z += q.x * h1[4 * i4] + q.y * h1[4 * i4 + 1] + q.z * h1[4 * i4 + 2] + q.w * h1[4 * i4 + 3];
+        }
         y += w[kOffW3 + j] * (z > 0.f ? z : 0.f);
     }
     return y;
 }
 
-__global__ void __launch_bounds__(256)
+// (at least 4 waves per SIMD: the weight loads are not hoisted into registers)
+__global__ void __launch_bounds__(256, 4)
 k_mlp_predict(long long n, const float* __restrict__ feats, const float* __restrict__ params, float* __restrict__ y) {
-    __shared__ float w[kNParam];
+    __shared__ __align__(16) float w[kNParam + 3];
     for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
     __syncthreads();
-    for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < n; r += (long long)gridDim.x * 256)
-        y[r] = mlp_eval(w, feats + r * kNF);
+    // one row per thread (a row loop would let the compiler hoist every
+    // weight load out of it into registers)
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r < n) y[r] = mlp_eval(w, feats + r * kNF);
 }
 
-// capacity rule; rows with small bounds skip the network
-__global__ void __launch_bounds__(256)
+// capacity rule; rows with small bounds skip the network.  Rows without
+// products (cap 0) are in no numeric bin: their count is set to 0 here.
+__global__ void __launch_bounds__(256, 4)
 k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ hi, const int32_t* __restrict__ lo,
-           const float* __restrict__ params, float delta, int32_t* __restrict__ cap) {
-    __shared__ float w[kNParam];
+           const float* __restrict__ params, float delta, int32_t* __restrict__ cap, int32_t* __restrict__ cnt) {
+    __shared__ __align__(16) float w[kNParam + 3];
     for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
     __syncthreads();
-    for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < m; r += (long long)gridDim.x * 256) {
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r < m) {
         const int h = hi[r];
         const int l = lo[r] < h ? lo[r] : h;
         int c = h;
         if (h > kSmallCap && l < h) {
             const float y = mlp_eval(w, feats + r * kNF);
             const double est = exp2((double)(16.f * y + delta));
-            c = est >= (double)h ? h : (int)ceil(est);
+            c = est < (double)h ? (int)ceil(est) : h;    // NaN or overflow: the upper bound
             c = c < l ? l : c;
         }
         cap[r] = c;
+        if (c == 0) cnt[r] = 0;
     }
 }
 
@@ -96,53 +107,75 @@ k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ h
 // Per sample s of the batch: activations and the backward deltas of the
 // mean-squared error, stored for the reduction kernel.
 __global__ void __launch_bounds__(256)
-k_mlp_fwd_bwd(int batch, const int32_t* __restrict__ idx, const float* __restrict__ feats,
+k_mlp_fwd_bwd(int batch, long long n, const int32_t* __restrict__ idx, const float* __restrict__ feats,
               const float* __restrict__ targets, const float* __restrict__ params,
               float* __restrict__ X, float* __restrict__ H1, float* __restrict__ H2,
-              float* __restrict__ DZ1, float* __restrict__ DZ2, float* __restrict__ D) {
-    __shared__ float w[kNParam];
+              float* __restrict__ DZ1, float* __restrict__ DZ2, float* __restrict__ D, int* __restrict__ bad) {
+    __shared__ __align__(16) float w[kNParam + 3];
     for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
     __syncthreads();
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= batch) return;
-    const long long r = idx[s];
+    long long r = idx[s];
+    if (r < 0 || r >= n) {          // flagged; the sample reads row 0 instead
+        atomicOr(bad, 1);
+        r = 0;
+    }
     float x[kNF];
 #pragma unroll
     for (int f = 0; f < kNF; ++f) { x[f] = feats[r * kNF + f]; X[(long long)s * kNF + f] = x[f]; }
-    float h1[kH1];
-#pragma unroll
-    for (int i = 0; i < kH1; ++i) {
-        float z = w[kOffB1 + i];
-#pragma unroll
-        for (int f = 0; f < kNF; ++f) z += w[kOffW1 + i * kNF + f] * x[f];
-        h1[i] = z > 0.f ? z : 0.f;
-        H1[(long long)s * kH1 + i] = h1[i];
-    }
+    // forward; activity masks of both hidden layers
+    uint64_t act1 = 0, act2 = 0;
     float y = w[kOffB3];
-    float h2pos[kH2];                   // h2_j (0 where z2_j <= 0)
-    for (int j = 0; j < kH2; ++j) {
-        float z = w[kOffB2 + j];
+    {
+        float h1[kH1];
 #pragma unroll
-        for (int i = 0; i < kH1; ++i) z += w[kOffW2 + j * kH1 + i] * h1[i];
-        const float h2 = z > 0.f ? z : 0.f;
-        h2pos[j] = h2;
-        H2[(long long)s * kH2 + j] = h2;
-        y += w[kOffW3 + j] * h2;
+        for (int i = 0; i < kH1; ++i) {
+            float z = w[kOffB1 + i];
+#pragma unroll
+            for (int f = 0; f < kNF; ++f) z += w[kOffW1 + i * kNF + f] * x[f];
+            h1[i] = z > 0.f ? z : 0.f;
+            act1 |= (uint64_t)(z > 0.f) << i;
+            H1[(long long)s * kH1 + i] = h1[i];
+        }
+#pragma unroll 1
+        for (int j = 0; j < kH2; ++j) {
+            const float4* row = reinterpret_cast<const float4*>(w + kOffW2 + j * kH1);
+            float z = w[kOffB2 + j];
+#pragma unroll
+            for (int i4 = 0; i4 < kH1 / 4; ++i4) {
+                const float4 q = row[i4];
+                z += q.x * h1[4 * i4] + q.y * h1[4 * i4 + 1] + q.z * h1[4 * i4 + 2] + q.w * h1[4 * i4 + 3];
+            }
+            const float h2 = z > 0.f ? z : 0.f;
+            act2 |= (uint64_t)(z > 0.f) << j;
+            H2[(long long)s * kH2 + j] = h2;
+            y += w[kOffW3 + j] * h2;
+        }
     }
     const float d = y - targets[r];
     D[s] = d;
     const float dy = 2.f * d / (float)batch;
+    // backward: dz2_j = dy W3_j [z2_j > 0]; dz1_i = [z1_i > 0] sum_j W2[j][i] dz2_j
     float dz1[kH1];
 #pragma unroll
     for (int i = 0; i < kH1; ++i) dz1[i] = 0.f;
+#pragma unroll 1
     for (int j = 0; j < kH2; ++j) {
-        const float dz2 = h2pos[j] > 0.f ? dy * w[kOffW3 + j] : 0.f;
+        const float dz2 = (act2 >> j) & 1 ? dy * w[kOffW3 + j] : 0.f;
         DZ2[(long long)s * kH2 + j] = dz2;
+        const float4* row = reinterpret_cast<const float4*>(w + kOffW2 + j * kH1);
 #pragma unroll
-        for (int i = 0; i < kH1; ++i) dz1[i] += w[kOffW2 + j * kH1 + i] * dz2;
+        for (int i4 = 0; i4 < kH1 / 4; ++i4) {
+            const float4 q = row[i4];
+            dz1[4 * i4] += q.x * dz2;
+            dz1[4 * i4 + 1] += q.y * dz2;
+            dz1[4 * i4 + 2] += q.z * dz2;
+            dz1[4 * i4 + 3] += q.w * dz2;
+        }
     }
 #pragma unroll
-    for (int i = 0; i < kH1; ++i) DZ1[(long long)s * kH1 + i] = h1[i] > 0.f ? dz1[i] : 0.f;
+    for (int i = 0; i < kH1; ++i) DZ1[(long long)s * kH1 + i] = (act1 >> i) & 1 ? dz1[i] : 0.f;
 }
 
 // One thread per parameter: its gradient is a sum over the batch, taken in
@@ -195,6 +228,13 @@ k_adam(float* __restrict__ params, const float* __restrict__ grad, float* __rest
     const float mhat = mm / (1.f - powf(beta1, (float)step));
     const float vhat = vv / (1.f - powf(beta2, (float)step));
     params[p] -= lr * mhat / (sqrtf(vhat) + eps);
+}
+
+// training target of a row: log2(1 + row_nnz) / 16
+__global__ void __launch_bounds__(256)
+k_targets(int m, const int32_t* __restrict__ row_nnz, float* __restrict__ t) {
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r < m) t[r] = log2f(1.f + (float)row_nnz[r]) * kFeatLogScale;
 }
 
 // ---------------------------------------------------------------------------
@@ -334,7 +374,7 @@ static msp_status launch_check2(const char* what) {
 
 struct msp_predictor {
     int device = 0;
-    msp::DevBuf params, m, v, grad, loss, X, H1, H2, DZ1, DZ2, D;
+    msp::DevBuf params, m, v, grad, loss, bad, X, H1, H2, DZ1, DZ2, D;
     int batch_cap = 0;
     float delta = 0.f;
     long long step = 0;
@@ -349,17 +389,17 @@ extern "C" msp_status msp_predictor_create(msp_handle* h, const float* init_para
     if (!p) return fail(MSP_ERR_OOM, "host allocation failed");
     p->device = h->device;
     msp_status s;
-    for (DevBuf* b : {&p->params, &p->m, &p->v, &p->grad}) {
-        if ((s = b->ensure(kNParam * sizeof(float))) != MSP_OK) { delete p; return s; }
+    for (DevBuf* b : {&p->params, &p->m, &p->v, &p->grad, &p->bad}) {
+        if ((s = b->ensure(kNParam * sizeof(float))) != MSP_OK) { msp_predictor_destroy(p); return s; }
         if ((e = hipMemsetAsync(b->ptr, 0, kNParam * sizeof(float), h->stream)) != hipSuccess) {
-            delete p;
+            msp_predictor_destroy(p);
             return hip_fail(e, "hipMemsetAsync");
         }
     }
     if ((e = hipMemcpyAsync(p->params.ptr, init_params, kNParam * sizeof(float), hipMemcpyHostToDevice, h->stream)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
-        delete p;
+        msp_predictor_destroy(p);
         return hip_fail(e, "hipMemcpyAsync(params)");
     }
     *out = p;
@@ -369,7 +409,8 @@ extern "C" msp_status msp_predictor_create(msp_handle* h, const float* init_para
 extern "C" msp_status msp_predictor_destroy(msp_predictor* p) {
     if (!p) return MSP_OK;
     (void)hipSetDevice(p->device);
-    for (DevBuf* b : {&p->params, &p->m, &p->v, &p->grad, &p->loss, &p->X, &p->H1, &p->H2, &p->DZ1, &p->DZ2, &p->D})
+    for (DevBuf* b :
+         {&p->params, &p->m, &p->v, &p->grad, &p->loss, &p->bad, &p->X, &p->H1, &p->H2, &p->DZ1, &p->DZ2, &p->D})
         b->release();
     delete p;
     return MSP_OK;
@@ -410,13 +451,13 @@ static msp_status ensure_batch(msp_predictor* p, int batch) {
 }
 
 // one forward/backward + gradient reduction on batch rows idx[0..batch)
-static msp_status grad_step(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
+static msp_status grad_step(msp_handle* h, msp_predictor* p, const float* feats, const float* targets, int64_t n,
                             const int32_t* idx, int batch, float* loss_dev) {
     msp_status s = ensure_batch(p, batch);
     if (s != MSP_OK) return s;
     k_mlp_fwd_bwd<<<(batch + 255) / 256, 256, 0, h->stream>>>(
-        batch, idx, feats, targets, p->params.as<float>(), p->X.as<float>(), p->H1.as<float>(), p->H2.as<float>(),
-        p->DZ1.as<float>(), p->DZ2.as<float>(), p->D.as<float>());
+        batch, n, idx, feats, targets, p->params.as<float>(), p->X.as<float>(), p->H1.as<float>(), p->H2.as<float>(),
+        p->DZ1.as<float>(), p->DZ2.as<float>(), p->D.as<float>(), p->bad.as<int>());
     if ((s = launch_check2("k_mlp_fwd_bwd")) != MSP_OK) return s;
     k_mlp_grad<<<(kNParam + 255) / 256, 256, 0, h->stream>>>(batch, p->X.as<float>(), p->H1.as<float>(),
                                                               p->H2.as<float>(), p->DZ1.as<float>(),
@@ -425,21 +466,34 @@ static msp_status grad_step(msp_handle* h, msp_predictor* p, const float* feats,
     return launch_check2("k_mlp_grad");
 }
 
+// Sample indices outside [0, n) were flagged by the forward/backward kernel:
+// report them (and clear the flag) once the stream has drained.
+static msp_status take_bad_index(msp_handle* h, msp_predictor* p) {
+    int bad = 0;
+    hipError_t e = hipMemcpyAsync(&bad, p->bad.ptr, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index flag)");
+    if (!bad) return MSP_OK;
+    if ((e = hipMemsetAsync(p->bad.ptr, 0, sizeof(int), h->stream)) != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    return fail(MSP_ERR_INVALID_ARG, "a batch index is outside [0, n)");
+}
+
 extern "C" msp_status msp_predictor_grad(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
-                                         const int32_t* idx, int batch, float* grad_host, float* loss_host) {
-    if (!h || !p || !feats || !targets || !idx || batch <= 0) return fail(MSP_ERR_INVALID_ARG, "bad argument");
+                                         int64_t n, const int32_t* idx, int batch, float* grad_host,
+                                         float* loss_host) {
+    if (!h || !p || !feats || !targets || !idx || batch <= 0 || n <= 0) return fail(MSP_ERR_INVALID_ARG, "bad argument");
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     msp_status s = p->loss.ensure(sizeof(float));
     if (s != MSP_OK) return s;
-    if ((s = grad_step(h, p, feats, targets, idx, batch, p->loss.as<float>())) != MSP_OK) return s;
+    if ((s = grad_step(h, p, feats, targets, n, idx, batch, p->loss.as<float>())) != MSP_OK) return s;
     if (grad_host &&
         (e = hipMemcpyAsync(grad_host, p->grad.ptr, kNParam * 4, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(grad)");
     if (loss_host && (e = hipMemcpyAsync(loss_host, p->loss.ptr, 4, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(loss)");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    return MSP_OK;
+    return take_bad_index(h, p);
 }
 
 extern "C" msp_status msp_predictor_train(msp_handle* h, msp_predictor* p, const float* feats, const float* targets,
@@ -456,7 +510,7 @@ extern "C" msp_status msp_predictor_train(msp_handle* h, msp_predictor* p, const
     msp_status s = p->loss.ensure((size_t)std::max(steps, 1) * sizeof(float));
     if (s != MSP_OK) return s;
     for (int t = 0; t < steps; ++t) {
-        if ((s = grad_step(h, p, feats, targets, batch_idx + (size_t)t * batch, batch, p->loss.as<float>() + t)) !=
+        if ((s = grad_step(h, p, feats, targets, n, batch_idx + (size_t)t * batch, batch, p->loss.as<float>() + t)) !=
             MSP_OK)
             return s;
         ++p->step;
@@ -470,7 +524,7 @@ extern "C" msp_status msp_predictor_train(msp_handle* h, msp_predictor* p, const
             hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(losses)");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    return MSP_OK;
+    return take_bad_index(h, p);
 }
 
 extern "C" msp_status msp_predictor_infer(msp_handle* h, const msp_predictor* p, const float* feats, int64_t n,
@@ -479,7 +533,8 @@ extern "C" msp_status msp_predictor_infer(msp_handle* h, const msp_predictor* p,
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if (n == 0) return MSP_OK;
-    const long long blocks = std::min<long long>((n + 255) / 256, 8LL * h->num_cu);
+    const long long blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return fail(MSP_ERR_INDEX_OVERFLOW, "too many rows");
     k_mlp_predict<<<(int)blocks, 256, 0, h->stream>>>(n, feats, p->params.as<float>(), y);
     return launch_check2("k_mlp_predict");
 }
@@ -558,9 +613,10 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     h->prof.end(h->stream);
     h->prof.begin(MSP_PHASE_PREDICT, h->stream);
     if (m > 0) {
-        const int blocks = std::min((m + 255) / 256, 8 * h->num_cu);
+        const int blocks = (m + 255) / 256;
         k_capacity<<<blocks, 256, 0, h->stream>>>(m, x->feat.as<float>(), h->u.as<int32_t>(), x->lo.as<int32_t>(),
-                                                  p->params.as<float>(), p->delta, x->cap.as<int32_t>());
+                                                  p->params.as<float>(), p->delta, x->cap.as<int32_t>(),
+                                                  x->cnt.as<int32_t>());
         if ((s = launch_check2("k_capacity")) != MSP_OK) return cleanup(s);
     }
     h->prof.end(h->stream);
@@ -579,7 +635,8 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     if ((s = x->pad.ensure((size_t)std::max(sum_cap, 1LL) * (4 + vsz) + 256)) != MSP_OK) return cleanup(s);
     int32_t* pcol = x->pad.as<int32_t>();
     char* pval = (char*)x->pad.ptr + (((size_t)std::max(sum_cap, 1LL) * 4 + 255) & ~(size_t)255);
-    if ((s = zero_info(h)) != MSP_OK) return cleanup(s);
+    // (the device info is not cleared here: the scatter of rows into bins
+    // reads the per-partition bin counts that the scan just wrote)
     h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
     if ((s = run_numeric_bins(h, A, B, np, counts, x->cap.as<int32_t>(), x->rp_pad.as<int64_t>(), pcol, pval,
                               x->cnt.as<int32_t>())) != MSP_OK)
@@ -642,7 +699,7 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
         msp_opts so;
         memset(&so, 0, sizeof(so));
         so.tuning = t;
-        if ((s = spgemm_core(h, &Asub, B, &Csub, &so, ws_alloc)) != MSP_OK) return cleanup(s);
+        if ((s = spgemm_core(h, &Asub, B, &Csub, &so, ws_alloc, [](void*) {})) != MSP_OK) return cleanup(s);
         scol = Csub.col;
         sval = (char*)Csub.val;
         k_patch_overflow<<<(novf + 255) / 256, 256, 0, h->stream>>>(novf, x->list.as<int32_t>(), Csub.row_ptr,
@@ -687,4 +744,24 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     }
     if (st) *st = stats;
     return MSP_OK;
+}
+
+extern "C" msp_status msp_training_rows(msp_handle* h, const msp_csr* A, const msp_csr* B, float* features,
+                                        float* targets) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    const int m = (int)A->nrows;
+    if (m > 0 && (!features || !targets)) return fail(MSP_ERR_INVALID_ARG, "null output");
+    if ((s = msp_row_features(h, A, B, nullptr, features)) != MSP_OK) return s;
+    int64_t tot = 0;
+    DevBuf rn;
+    if ((s = rn.ensure((size_t)std::max(m, 1) * 4)) != MSP_OK) return s;
+    if ((s = msp_spgemm_symbolic(h, A, B, rn.as<int32_t>(), &tot, nullptr)) != MSP_OK) { rn.release(); return s; }
+    if (m > 0) k_targets<<<(m + 255) / 256, 256, 0, h->stream>>>(m, rn.as<int32_t>(), targets);
+    s = launch_check2("k_targets");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    rn.release();
+    if (s == MSP_OK && e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize");
+    return s;
 }

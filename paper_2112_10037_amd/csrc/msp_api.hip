@@ -76,8 +76,6 @@ msp_status DevBuf::ensure(size_t need) {
     return MSP_OK;
 }
 
-void __attribute__((weak)) release_extra(msp_handle*) {}
-
 void DevBuf::release() {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 
 #include "internal.hpp"
@@ -526,7 +527,7 @@ msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, c
     return run_bins(h, A, B, plan, counts_host, key, true, crp, ccol, cval, nullptr, 0, cnt_out);
 }
 
-static msp_status check_pair(const msp_csr* A, const msp_csr* B) {
+msp_status check_pair(const msp_csr* A, const msp_csr* B) {
     msp_status s;
     if ((s = check_csr(A, "A")) != MSP_OK) return s;
     if ((s = check_csr(B, "B")) != MSP_OK) return s;
@@ -537,7 +538,7 @@ static msp_status check_pair(const msp_csr* A, const msp_csr* B) {
     return MSP_OK;
 }
 
-static msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B) {
+msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B) {
     msp_status s;
     if ((s = zero_info(h)) != MSP_OK) return s;
     for (const msp_csr* M : {A, B}) {
@@ -553,7 +554,7 @@ static msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr
     return MSP_OK;
 }
 
-static msp_status device_error(int err) {
+msp_status device_error(int err) {
     if (err & kErrProbe) return fail(MSP_ERR_HIP, "internal: hash probe bound exceeded");
     if (err & kErrCount) return fail(MSP_ERR_HIP, "internal: numeric row count differs from symbolic count");
     return MSP_OK;
@@ -591,8 +592,13 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
 
 }  // namespace msp
 
-extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C,
-                                 const msp_opts* opts) {
+namespace msp {
+
+// The plain two-phase product; `alloc_cv` provides the single allocation of
+// C's columns and values once nnz(C) is known (the caller's allocator, or a
+// workspace for internal sub-products).
+msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C, const msp_opts* opts,
+                       const std::function<void*(size_t)>& alloc_cv, const std::function<void(void*)>& free_cv) {
     if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
     if (!C) return fail(MSP_ERR_INVALID_ARG, "C is NULL");
     msp_status s = check_pair(A, B);
@@ -612,7 +618,7 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
     C->col = nullptr;
     C->val = nullptr;
     auto cleanup = [&](msp_status st) {
-        if (C->col) h->free_fn(h->alloc_ctx, C->col, h->stream);   // col and val share it
+        if (C->col) free_cv(C->col);   // col and val share it
         C->col = nullptr;
         C->val = nullptr;
         if (own_rp) { h->free_fn(h->alloc_ctx, C->row_ptr, h->stream); C->row_ptr = nullptr; }
@@ -637,7 +643,7 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
     if (nnz > 0) {
         // one allocation: columns, then values at the next 256-byte boundary
         const size_t voff = ((size_t)nnz * 4 + 255) & ~(size_t)255;
-        void* base = h->alloc(h->alloc_ctx, voff + (size_t)nnz * vsz, h->stream);
+        void* base = alloc_cv(voff + (size_t)nnz * vsz);
         if (!base) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
         C->col = (int32_t*)base;
         h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
@@ -652,6 +658,16 @@ extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr*
         if (e2 != hipSuccess) return cleanup(hip_fail(e2, "hipMemcpyAsync(error flags)"));
     }
     return MSP_OK;
+}
+
+}  // namespace msp
+
+extern "C" msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C,
+                                 const msp_opts* opts) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    return spgemm_core(
+        h, A, B, C, opts, [h](size_t bytes) -> void* { return h->alloc(h->alloc_ctx, bytes, h->stream); },
+        [h](void* ptr) { h->free_fn(h->alloc_ctx, ptr, h->stream); });
 }
 
 extern "C" msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const msp_csr* B, int32_t* row_nnz,

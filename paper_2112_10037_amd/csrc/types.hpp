@@ -31,7 +31,8 @@ struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
     int err;                              // error bits of the current call
     int scan_ticket;                      // tile tickets of the single-pass scan
-    int pad[28];
+    int neg_count;                        // scan inputs < 0 (rows that overflowed)
+    int pad[27];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
