@@ -238,6 +238,88 @@ msp_status msp_predictor_calibrate(msp_handle* h, msp_predictor* p, const float*
 msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, const msp_csr* A, const msp_csr* B,
                               msp_csr_out* C, const msp_opts* opts, msp_learned_stats* st);
 
+/* ---- batches of products in one graph launch ----------------------------- */
+
+/*
+ * A batch of sparse matrices in packed form.  Problem p owns the rows
+ * [row_start[p], row_start[p+1]) of one row_ptr array whose entries are
+ * offsets into one col/val array (row_ptr[0] need not be 0); its column
+ * indices are local to the problem, 0 <= col < ncols[p], sorted and unique
+ * within each row.  row_start and ncols are host arrays (nprob + 1 and nprob
+ * entries); row_ptr, col and val are device arrays.  A problem's view
+ * {rows, ncols[p], nnz, row_ptr + row_start[p], col, val} is a valid
+ * msp_csr for the single-product calls.
+ */
+typedef struct {
+    int32_t nprob;
+    const int64_t* row_start;   /* host, nprob + 1, row_start[0] = 0 */
+    const int64_t* ncols;       /* host, nprob */
+    int64_t nnz;                /* entries of col/val */
+    const int64_t* row_ptr;     /* device, row_start[nprob] + 1 */
+    const int32_t* col;         /* device */
+    const void* val;            /* device */
+    msp_dtype dtype;
+} msp_batch_csr;
+
+typedef struct msp_batch msp_batch;
+
+typedef struct {
+    int32_t nstage;             /* 1: C_p = A_p P_p; 2: C_p = R_p (A_p P_p)       */
+    int64_t rows[2];            /* rows of each stage (all problems)            */
+    int64_t nnz[2];             /* nnz of each stage's product at plan time     */
+    int32_t sym_bins[2];        /* bin kernels of each stage's symbolic pass    */
+    int32_t num_bins[2];        /* bin kernels of each stage's numeric pass     */
+} msp_batch_stats;
+
+/*
+ * Plan a batch: C_p = A_p * P_p for every problem p, or, with R not NULL,
+ * the Galerkin products C_p = R_p * (A_p * P_p) (two dependent stages, the
+ * intermediate A_p P_p kept in the plan).  Shapes: A.ncols[p] = rows of
+ * P_p; R.ncols[p] = rows of A_p.  Values of R, A and P have one dtype.
+ * Runs the batch once eagerly to size the plan's workspace and output
+ * arenas and to pick the bin kernels, then captures every pass of every
+ * stage into one hipGraph on a private stream.  The inputs are borrowed:
+ * each replay reads them again, so their values may change between
+ * replays; their structure must not (a replay that detects a change
+ * reports an error and produces nothing).  opts->tuning selects the bin
+ * thresholds (zero: the handle's); validate and force_spill are not
+ * supported.  Synchronises.
+ */
+msp_status msp_batch_create(msp_handle* h, const msp_batch_csr* R, const msp_batch_csr* A,
+                            const msp_batch_csr* P, const msp_opts* opts, msp_batch** plan);
+msp_status msp_batch_destroy(msp_batch* plan);
+/* Replay the plan's graph on the handle's stream (one graph launch and two
+ * small device-to-host copies; no wait).  The results of the previous
+ * replay are collected first. */
+msp_status msp_batch_execute(msp_handle* h, msp_batch* plan);
+/* Wait for the last replay; report a structure change or an internal error
+ * it detected. */
+msp_status msp_batch_sync(msp_handle* h, msp_batch* plan);
+/* Problem p's result of the last replay as a canonical CSR view into the
+ * plan's arena (valid until the next replay or msp_batch_destroy; the
+ * caller does not free it).  Waits for the replay. */
+msp_status msp_batch_result(msp_handle* h, msp_batch* plan, int p, msp_csr* C);
+/* Problem p's result copied out: C->row_ptr as in msp_spgemm (caller's,
+ * or allocated when NULL), col and val in one allocation from the handle's
+ * allocator, owned by the caller.  Queued on the handle's stream. */
+msp_status msp_batch_copy_result(msp_handle* h, msp_batch* plan, int p, msp_csr_out* C);
+msp_status msp_batch_info(const msp_batch* plan, msp_batch_stats* st);
+/*
+ * Autotuner: plan the batch with each of the ncand tunings, replay it
+ * `reps` times after one warm replay, and return in *best the tuning with
+ * the smallest median replay time (times_ms, if not NULL, receives each
+ * candidate's median, or infinity where the candidate failed).
+ */
+msp_status msp_batch_autotune(msp_handle* h, const msp_batch_csr* R, const msp_batch_csr* A,
+                              const msp_batch_csr* P, const msp_tuning* cand, int ncand, int reps,
+                              msp_tuning* best, double* times_ms);
+/* A tuning as a flat JSON object of its five fields; returns the length
+ * written (snprintf semantics), or -1 when t is NULL. */
+int msp_tuning_to_json(const msp_tuning* t, char* buf, size_t n);
+/* Parse that object (field order and spacing free); checks the values as
+ * msp_set_tuning does. */
+msp_status msp_tuning_from_json(const char* json, msp_tuning* t);
+
 /* ---- timing ------------------------------------------------------------- */
 
 /* Phases timed with HIP events on the handle's stream when profiling is on. */

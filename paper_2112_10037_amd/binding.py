@@ -61,6 +61,17 @@ class c_learned_stats(ctypes.Structure):
     _fields_ = [("overflow_rows", ctypes.c_int64), ("sum_cap", ctypes.c_int64), ("nnz", ctypes.c_int64)]
 
 
+class c_batch_csr(ctypes.Structure):
+    _fields_ = [("nprob", ctypes.c_int32), ("row_start", ctypes.c_void_p), ("ncols", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("dtype", ctypes.c_int)]
+
+
+class c_batch_stats(ctypes.Structure):
+    _fields_ = [("nstage", ctypes.c_int32), ("rows", ctypes.c_int64 * 2), ("nnz", ctypes.c_int64 * 2),
+                ("sym_bins", ctypes.c_int32 * 2), ("num_bins", ctypes.c_int32 * 2)]
+
+
 NUM_PHASES = 8
 PHASES = ["row_stats", "symbolic", "scan", "numeric", "predict", "fallback", "compact", "batch"]
 
@@ -110,6 +121,22 @@ SIGNATURES = [
     ("msp_spgemm_learned", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(c_csr),
                                           ctypes.POINTER(c_csr), ctypes.POINTER(c_csr_out),
                                           ctypes.POINTER(c_opts), ctypes.POINTER(c_learned_stats)]),
+    ("msp_batch_create", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_batch_csr), ctypes.POINTER(c_batch_csr),
+                                        ctypes.POINTER(c_batch_csr), ctypes.POINTER(c_opts),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    ("msp_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("msp_batch_execute", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("msp_batch_sync", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("msp_batch_result", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(c_csr)]),
+    ("msp_batch_copy_result", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.POINTER(c_csr_out)]),
+    ("msp_batch_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_batch_stats)]),
+    ("msp_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_batch_csr),
+                                          ctypes.POINTER(c_batch_csr), ctypes.POINTER(c_batch_csr),
+                                          ctypes.POINTER(c_tuning), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(c_tuning), ctypes.POINTER(ctypes.c_double)]),
+    ("msp_tuning_to_json", ctypes.c_int, [ctypes.POINTER(c_tuning), ctypes.c_char_p, ctypes.c_size_t]),
+    ("msp_tuning_from_json", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(c_tuning)]),
     ("msp_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("msp_profile_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_profile)]),
     ("msp_status_string", ctypes.c_char_p, [ctypes.c_int]),
@@ -418,3 +445,152 @@ class Predictor:
         _check(self._lib.msp_predictor_calibrate(self.h._h, self._p, feats.data_ptr(), targets.data_ptr(),
                                                  feats.shape[0], ctypes.c_double(q)))
         return self.get()[1]
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+@dataclass
+class PackedBatch:
+    """A batch in packed form (see msp_batch_csr): device row_ptr/col/val,
+    host row_start (nprob + 1) and ncols (nprob)."""
+    row_start: np.ndarray
+    ncols: np.ndarray
+    row_ptr: object
+    col: object
+    val: object
+
+    @property
+    def nprob(self) -> int:
+        return int(self.ncols.size)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_host(cls, mats, device="cuda") -> "PackedBatch":
+        """Pack host CSR matrices (gen.CSR) into one device batch."""
+        import torch
+        row_start = np.zeros(len(mats) + 1, dtype=np.int64)
+        np.cumsum([m.nrows for m in mats], out=row_start[1:])
+        ncols = np.array([m.ncols for m in mats], dtype=np.int64)
+        nnz_off = np.zeros(len(mats) + 1, dtype=np.int64)
+        np.cumsum([m.nnz for m in mats], out=nnz_off[1:])
+        rp = np.empty(int(row_start[-1]) + 1, dtype=np.int64)
+        for i, m in enumerate(mats):
+            rp[row_start[i]:row_start[i + 1]] = m.row_ptr[:-1] + nnz_off[i]
+        rp[-1] = nnz_off[-1]
+        col = np.concatenate([m.col for m in mats]) if mats else np.zeros(0, np.int32)
+        val = np.concatenate([m.val for m in mats]) if mats else np.zeros(0)
+        d = torch.device(device)
+        return cls(row_start, ncols, torch.from_numpy(rp).to(d), torch.from_numpy(col.astype(np.int32)).to(d),
+                   torch.from_numpy(val).to(d))
+
+    def view(self, p: int) -> DeviceCSR:
+        """Problem p as a single-product operand (row_ptr not starting at 0)."""
+        r0, r1 = int(self.row_start[p]), int(self.row_start[p + 1])
+        return DeviceCSR(r1 - r0, int(self.ncols[p]), self.row_ptr[r0:r1 + 1], self.col, self.val)
+
+    def c(self) -> c_batch_csr:
+        self._rs = np.ascontiguousarray(self.row_start, dtype=np.int64)
+        self._nc = np.ascontiguousarray(self.ncols, dtype=np.int64)
+        dt = MSP_F64 if self.val.dtype == self._torch_f64() else MSP_F32
+        return c_batch_csr(self.nprob, self._rs.ctypes.data, self._nc.ctypes.data, self.nnz,
+                           self.row_ptr.data_ptr(), self.col.data_ptr() if self.nnz else None,
+                           self.val.data_ptr() if self.nnz else None, dt)
+
+    @staticmethod
+    def _torch_f64():
+        import torch
+        return torch.float64
+
+
+class Batch:
+    """A planned batch C_p = A_p P_p, or C_p = R_p (A_p P_p) with R."""
+
+    def __init__(self, handle: "Handle", A: PackedBatch, P: PackedBatch, R: PackedBatch | None = None,
+                 tuning=None):
+        self.h = handle
+        self._lib = handle._lib
+        self._inputs = (A, P, R)                # the plan reads them on every replay
+        ca, cp = A.c(), P.c()
+        cr = R.c() if R is not None else None
+        self._c = (ca, cp, cr)
+        o = _opts(False, False, tuning)
+        self._b = ctypes.c_void_p()
+        _check(self._lib.msp_batch_create(handle._h, ctypes.byref(cr) if cr is not None else None,
+                                          ctypes.byref(ca), ctypes.byref(cp), ctypes.byref(o),
+                                          ctypes.byref(self._b)))
+        self.nprob = A.nprob
+
+    def close(self):
+        if self._b:
+            self._lib.msp_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def execute(self):
+        _check(self._lib.msp_batch_execute(self.h._h, self._b))
+
+    def sync(self):
+        _check(self._lib.msp_batch_sync(self.h._h, self._b))
+
+    def result(self, p: int) -> DeviceCSR:
+        """Problem p of the last replay, copied out of the plan's arena."""
+        torch = self.h._torch
+        out = c_csr_out()
+        _check(self._lib.msp_batch_copy_result(self.h._h, self._b, p, ctypes.byref(out)))
+        rp = self.h._live.pop(out.row_ptr)[: (out.nrows + 1) * 8].view(torch.int64)
+        nnz = int(out.nnz)
+        vdt = torch.float64 if out.dtype == MSP_F64 else torch.float32
+        if nnz > 0:
+            col, val = self.h._take_c(out.col, nnz, vdt)
+        else:
+            col = torch.empty(0, dtype=torch.int32, device=rp.device)
+            val = torch.empty(0, dtype=vdt, device=rp.device)
+        return DeviceCSR(int(out.nrows), int(out.ncols), rp, col, val)
+
+    def info(self) -> dict:
+        st = c_batch_stats()
+        _check(self._lib.msp_batch_info(self._b, ctypes.byref(st)))
+        n = st.nstage
+        return {"nstage": n, "rows": list(st.rows)[:n], "nnz": list(st.nnz)[:n],
+                "sym_bins": list(st.sym_bins)[:n], "num_bins": list(st.num_bins)[:n]}
+
+
+def autotune(handle: "Handle", A: PackedBatch, P: PackedBatch, R: PackedBatch | None, candidates, reps=5):
+    """Median replay time of each candidate tuning; returns (best, times_ms)."""
+    n = len(candidates)
+    arr = (c_tuning * n)(*[c_tuning(*t) for t in candidates])
+    times = (ctypes.c_double * n)()
+    best = c_tuning()
+    ca, cp = A.c(), P.c()
+    cr = R.c() if R is not None else None
+    _check(handle._lib.msp_batch_autotune(handle._h, ctypes.byref(cr) if cr is not None else None,
+                                          ctypes.byref(ca), ctypes.byref(cp), arr, n, reps,
+                                          ctypes.byref(best), times))
+    return ((best.hash_scale, best.group_scale, best.spill_nnz, best.block_rows, best.merge_k),
+            [float(t) for t in times])
+
+
+def tuning_to_json(t) -> str:
+    lib = load()
+    ct = c_tuning(*t)
+    n = lib.msp_tuning_to_json(ctypes.byref(ct), None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.msp_tuning_to_json(ctypes.byref(ct), buf, n + 1)
+    return buf.value.decode()
+
+
+def tuning_from_json(js: str):
+    lib = load()
+    ct = c_tuning()
+    _check(lib.msp_tuning_from_json(js.encode(), ctypes.byref(ct)))
+    return (ct.hash_scale, ct.group_scale, ct.spill_nnz, ct.block_rows, ct.merge_k)

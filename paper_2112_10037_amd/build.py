@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsp.so")
-SOURCES = ["msp_api.hip", "spgemm.hip", "learned.hip"]
+SOURCES = ["msp_api.hip", "spgemm.hip", "learned.hip", "batched.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -36,6 +36,22 @@ struct BinPlan {
     BinSpec spec[kMaxBins + 1];     // spec[b] for b in 1..nb (nb = the global path)
 };
 
+// Operand pointers of one product, or of a packed batch of products (then
+// ncols is the widest problem's and the RowMap of the launch gives each
+// row's problem).
+struct Operands {
+    const int64_t* arp;
+    const int32_t* acol;
+    const void* aval;
+    const int64_t* brp;
+    const int32_t* bcol;
+    const void* bval;
+    long long ncols;       // columns of B
+    long long bnnz;        // entries of B
+    long long m;           // rows of A
+    msp_dtype dtype;
+};
+
 struct ExtraState;                  // learned / batched state (other units)
 
 // Per-phase event timing: intervals are recorded on the handle's stream and
@@ -81,6 +97,11 @@ struct msp_handle {
 
 namespace msp {
 
+// Set while a batch plan's launches are being captured into a graph: any
+// workspace growth or memset then is an internal error instead of a
+// silently recorded graph node.
+extern thread_local bool g_capturing;
+
 msp_status fail(msp_status s, const char* fmt, ...);
 msp_status hip_fail(hipError_t e, const char* what);
 msp_status check_csr(const msp_csr* M, const char* name);
@@ -112,5 +133,15 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                             const int* counts_host, const int32_t* key, const int64_t* crp,
                             int32_t* ccol, void* cval, int32_t* cnt_out);
+
+// One bin's kernel over the rows of wk (BATCH: packed operands, rows mapped
+// to problems by mp); `rows` sizes the persistent grid.
+Operands operands_of(const msp_csr* A, const msp_csr* B);
+template <bool BATCH>
+msp_status launch_symbolic_bin(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
+                               int32_t* rnnz, const RowMap& mp, const int32_t* ufilter, int umax);
+template <bool BATCH>
+msp_status launch_numeric_bin(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
+                              const int64_t* crp, int32_t* ccol, void* cval, int32_t* cnt_out, const RowMap& mp);
 
 }  // namespace msp

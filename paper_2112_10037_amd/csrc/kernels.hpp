@@ -177,14 +177,17 @@ __device__ __forceinline__ int wave_hist_add(int* hist, int b) {
 // Outputs: u_i = min(prod_i, ncols(B)) (int32), optional int64 prod_i and
 // FP32 features, row_nnz_i = 0 for rows with u_i = 0, and the bin
 // histogram of u_i (partitioned global counters).
-template <bool FEAT>
+template <bool FEAT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             int32_t* __restrict__ u_out, int64_t* __restrict__ prod_out,
             int32_t* __restrict__ row_nnz, BinTable bins, DevInfo* info,
-            float* __restrict__ feat, int32_t* __restrict__ lo_out) {
+            float* __restrict__ feat, int32_t* __restrict__ lo_out, RowMap mp) {
+    static_assert(!(FEAT && BATCH), "features are computed for single products");
     __shared__ int hist[kNB];
+    __shared__ long long s_bo[BATCH ? 4 : 1][64];   // batched: B-row offset and width of each row
+    __shared__ long long s_nc[BATCH ? 4 : 1][64];
     __shared__ long long s_rp[4][65];
     __shared__ unsigned long long s_prod[4][64];
     __shared__ int s_mn[FEAT ? 4 : 1][64], s_mx[FEAT ? 4 : 1][64];
@@ -197,6 +200,13 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     // row pointers of the wave's rows: entries 0..nr (nr + 1 <= 65 values)
     if (lane < nr) s_rp[w][lane] = arp[r0 + lane];
     if (lane == 0 && nr > 0) s_rp[w][nr] = arp[r0 + nr];
+    if constexpr (BATCH) {
+        if (lane < nr) {
+            const int pb = map_prob(mp, r0 + lane);
+            s_bo[w][lane] = mp.boff[pb];
+            s_nc[w][lane] = mp.ncols[pb];
+        }
+    }
     s_prod[w][lane] = 0;
     if constexpr (FEAT) {
         s_mn[w][lane] = 0x7fffffff; s_mx[w][lane] = 0; s_lo[w][lane] = 0x7fffffff; s_hi[w][lane] = -1;
@@ -205,15 +215,15 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     if (nr > 0) {
         const long long e0 = s_rp[w][0], e1 = s_rp[w][nr];
         for (long long p = e0 + lane; p < e1; p += 64) {
-            const int32_t k = acol[p];
-            const long long b0 = brp[k], b1 = brp[k + 1];
-            const long long l = b1 - b0;
             // last row r with s_rp[r] <= p (skips empty rows)
             int lo = 0, hi = nr;           // s_rp[lo] <= p < s_rp[hi]
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (s_rp[w][mid] <= p) lo = mid; else hi = mid;
             }
+            const long long k = (long long)acol[p] + (BATCH ? s_bo[w][lo] : 0);
+            const long long b0 = brp[k], b1 = brp[k + 1];
+            const long long l = b1 - b0;
             atomicAdd(&s_prod[w][lo], (unsigned long long)l);
             if constexpr (FEAT) {
                 atomicMin(&s_mn[w][lo], (int)l);
@@ -231,7 +241,8 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     int bin = -1;
     if (valid) {
         const long long s = (long long)s_prod[w][lane];
-        const long long u = s < ncols ? s : ncols;
+        const long long nc = BATCH ? s_nc[w][lane] : ncols;
+        const long long u = s < nc ? s : nc;
         u_out[row] = (int32_t)u;
         if (prod_out) prod_out[row] = s;
         if (u == 0 && row_nnz) row_nnz[row] = 0;
@@ -346,13 +357,16 @@ struct GroupCfg {
 // rows = perm (bin list) or identity when perm == nullptr.  Every per-group
 // LDS row is padded by one word so that the groups of a wave start on
 // different banks.
-template <int G, int T>
+template <int G, int T, bool BATCH = false>
 __global__ void __launch_bounds__(256)
-k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
+k_sym_group(Work wk, int m,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-            int32_t* __restrict__ row_nnz, DevInfo* info) {
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
     constexpr int NG = GroupCfg<G>::NG;
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     __shared__ int32_t keys[NG][T + 1];
     __shared__ long long s_off[NG][G + 1];
     __shared__ long long s_bst[NG][G + 1];
@@ -367,6 +381,7 @@ k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
     const long long hi = lo + per < nrows_bin ? lo + per : nrows_bin;
     for (long long slot = lo + g; slot < hi; slot += NG) {      // group-uniform
     const int row = perm ? perm[slot] : (int)slot;
+    const long long bo = row_boff<BATCH>(mp, row);
 #pragma unroll
     for (int s = gl; s < T; s += G) kt[s] = kEmpty;
     lds_fence();
@@ -376,7 +391,7 @@ k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
         const long long p = c0 + gl;
         long long len = 0, bst = 0;
         if (p < a1) {
-            const int32_t k = acol[p];
+            const long long k = acol[p] + bo;
             bst = brp[k];
             len = brp[k + 1] - bst;
         }
@@ -401,12 +416,15 @@ k_sym_group(int nrows_bin, const int32_t* __restrict__ perm, int m,
 }
 
 // Symbolic, one workgroup of BS threads per row, T key slots (LDS).
-template <int BS, int T>
+template <int BS, int T, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
-k_sym_block(int nrows_bin, const int32_t* __restrict__ perm,
+k_sym_block(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-            int32_t* __restrict__ row_nnz, DevInfo* info) {
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     __shared__ int32_t keys[T];
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -415,6 +433,7 @@ k_sym_block(int nrows_bin, const int32_t* __restrict__ perm,
     int err = 0;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
+        const long long bo = row_boff<BATCH>(mp, row);
         for (int s = tid; s < T; s += BS) keys[s] = kEmpty;
         __syncthreads();
         const long long a0 = arp[row], a1 = arp[row + 1];
@@ -423,7 +442,7 @@ k_sym_block(int nrows_bin, const int32_t* __restrict__ perm,
             const long long p = c0 + tid;
             long long len = 0, bst = 0;
             if (p < a1) {
-                const int32_t k = acol[p];
+                const long long k = acol[p] + bo;
                 bst = brp[k];
                 len = brp[k + 1] - bst;
             }
@@ -449,12 +468,15 @@ k_sym_block(int nrows_bin, const int32_t* __restrict__ perm,
 
 // Symbolic for the largest rows: an n-bit bitmap (LDS when it fits, else a
 // per-workgroup global slab), counting bits that an atomic OR newly sets.
-template <int BS, bool LDSBM>
+template <int BS, bool LDSBM, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
-k_sym_bitmap(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
+k_sym_bitmap(Work wk, long long ncols,
              const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
              const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-             int32_t* __restrict__ row_nnz, uint32_t* gslab, DevInfo* info) {
+             int32_t* __restrict__ row_nnz, uint32_t* gslab, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     extern __shared__ uint32_t dyn_smem[];
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -464,6 +486,7 @@ k_sym_bitmap(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
     uint32_t* bm = LDSBM ? dyn_smem : gslab + (long long)blockIdx.x * words;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
+        const long long bo = row_boff<BATCH>(mp, row);
         for (long long w = tid; w < words; w += BS) bm[w] = 0u;
         if (!LDSBM) __threadfence();
         __syncthreads();
@@ -473,7 +496,7 @@ k_sym_bitmap(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
             const long long p = c0 + tid;
             long long len = 0, bst = 0;
             if (p < a1) {
-                const int32_t k = acol[p];
+                const long long k = acol[p] + bo;
                 bst = brp[k];
                 len = brp[k + 1] - bst;
             }
@@ -516,6 +539,7 @@ struct WaveRows {
     long long a0[RM];         // first A entry of each row
     long long c0[RM];         // C row start (numeric)
     long long c1[RM];         // C row end (numeric)
+    long long bo[RM];         // batched: offset of the row's B rows
     int row[RM];
     int cnt[RM];
     int ovf[RM];              // capacity mode: the row's table overflowed
@@ -523,11 +547,11 @@ struct WaveRows {
 
 // Take the next batch starting at slot pos (< hi); returns the number of
 // rows nb >= 1 and leaves E = wr.off[nb].  Whole wave.
-template <int RM, bool NUMERIC>
+template <int RM, bool NUMERIC, bool BATCH>
 __device__ __forceinline__ int wave_rows_take(WaveRows<RM>& wr, long long pos, long long hi,
                                               const int32_t* __restrict__ perm,
                                               const int64_t* __restrict__ arp,
-                                              const int64_t* __restrict__ crp) {
+                                              const int64_t* __restrict__ crp, const RowMap& mp) {
     const int lane = threadIdx.x & 63;
     const int ncand = (int)(hi - pos < RM ? hi - pos : RM);
     long long a0 = 0, len = 0;
@@ -547,6 +571,7 @@ __device__ __forceinline__ int wave_rows_take(WaveRows<RM>& wr, long long pos, l
         wr.row[lane] = r;
         wr.cnt[lane] = 0;
         wr.ovf[lane] = 0;
+        wr.bo[lane] = row_boff<BATCH>(mp, r);
         if (NUMERIC) { wr.c0[lane] = crp[r]; wr.c1[lane] = crp[r + 1]; }
     }
     if (lane == nb - 1) wr.off[nb] = incl;
@@ -572,12 +597,15 @@ __device__ __forceinline__ void wave_range(long long n, long long* lo, long long
     *hi = *lo + per < n ? *lo + per : n;
 }
 
-template <int T, int RM>
+template <int T, int RM, bool BATCH = false>
 __global__ void __launch_bounds__(256)
-k_sym_wave(int nrows_bin, const int32_t* __restrict__ perm,
+k_sym_wave(Work wk,
            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-           int32_t* __restrict__ row_nnz, DevInfo* info) {
+           int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     __shared__ int32_t keys_all[4][RM][T + 1];
     __shared__ WaveRows<RM> wr_all[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -587,14 +615,14 @@ k_sym_wave(int nrows_bin, const int32_t* __restrict__ perm,
     long long lo, hi;
     wave_range(nrows_bin, &lo, &hi);
     for (long long pos = lo; pos < hi;) {
-        const int nb = wave_rows_take<RM, false>(wr, pos, hi, perm, arp, nullptr);
+        const int nb = wave_rows_take<RM, false, BATCH>(wr, pos, hi, perm, arp, nullptr, mp);
         for (int i = lane; i < nb * T; i += 64) keys[i / T][i % T] = kEmpty;
         lds_fence();
         const long long E = wr.off[nb];
         for (long long e = lane; e < E; e += 64) {
             const int r = wave_row_of<RM>(wr, nb, e);
             const long long p = wr.a0[r] + (e - wr.off[r]);
-            const int32_t k = acol[p];
+            const long long k = acol[p] + (BATCH ? wr.bo[r] : 0);
             const long long q0 = brp[k], q1 = brp[k + 1];
             int added = 0;
             for (long long q = q0; q < q1; q += 4) {
@@ -620,13 +648,16 @@ k_sym_wave(int nrows_bin, const int32_t* __restrict__ perm,
 // smaller keys in its row's table (unsigned compare, so empty slots count
 // as larger than every key), read 16 bytes at a time and broadcast to the
 // row's lanes.  Writes are guarded by the row's symbolic size.
-template <int T, int RM, typename VT>
+template <int T, int RM, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
-k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
+k_num_wave(Work wk,
            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
            const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-           int32_t* __restrict__ cnt_out, DevInfo* info) {
+           int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     constexpr int KS = T + 4;                 // 16-byte aligned key rows, shifted banks
     constexpr int L = T < 64 ? T : 64;        // extraction lanes per row
     __shared__ __align__(16) int32_t keys_all[4][RM][KS];
@@ -640,14 +671,14 @@ k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
     long long lo, hi;
     wave_range(nrows_bin, &lo, &hi);
     for (long long pos = lo; pos < hi;) {
-        const int nb = wave_rows_take<RM, true>(wr, pos, hi, perm, arp, crp);
+        const int nb = wave_rows_take<RM, true, BATCH>(wr, pos, hi, perm, arp, crp, mp);
         for (int i = lane; i < nb * T; i += 64) { keys[i / T][i % T] = kEmpty; vals[i / T][i % T] = 0.0; }
         lds_fence();
         const long long E = wr.off[nb];
         for (long long e = lane; e < E; e += 64) {
             const int r = wave_row_of<RM>(wr, nb, e);
             const long long p = wr.a0[r] + (e - wr.off[r]);
-            const int32_t k = acol[p];
+            const long long k = acol[p] + (BATCH ? wr.bo[r] : 0);
             const double a = to_f64(aval[p]);
             const long long q0 = brp[k], q1 = brp[k + 1];
             for (long long q = q0; q < q1; q += 4) {
@@ -717,13 +748,16 @@ k_num_wave(int nrows_bin, const int32_t* __restrict__ perm,
 
 constexpr int kMergeFT = 64;     // fallback table: the merge bins bound rows by 32
 
-template <int K>
+template <int K, bool BATCH = false>
 __global__ void __launch_bounds__(256)
-k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
+k_sym_merge(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             const int32_t* __restrict__ ufilter, int umax,
-            int32_t* __restrict__ row_nnz, DevInfo* info) {
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     __shared__ int32_t fb_keys[4][kMergeFT + 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int err = 0;
@@ -733,7 +767,7 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
         const long long slot = base + lane;
         const bool valid = slot < hi;
         int row = -1;
-        long long a0 = 0, a1 = 0;
+        long long a0 = 0, a1 = 0, bo = 0;
         bool take = valid;
         if (valid) {
             row = perm ? perm[slot] : (int)slot;
@@ -742,6 +776,7 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
             if (take) {
                 a0 = arp[row];
                 a1 = arp[row + 1];
+                bo = row_boff<BATCH>(mp, row);
             }
         }
         const bool mine = take && a1 - a0 <= K;
@@ -755,7 +790,7 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
                 hp[k] = 0;
                 he[k] = 0;
                 if (k < len) {
-                    const int32_t kk = acol[a0 + k];
+                    const long long kk = acol[a0 + k] + bo;
                     hp[k] = brp[kk];
                     he[k] = brp[kk + 1];
                     if (hp[k] < he[k]) hk[k] = bcol[hp[k]];
@@ -782,12 +817,12 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
             const int r = __builtin_ctzll(fb);
             fb &= fb - 1;
             const int frow = __shfl(row, r);
-            const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
+            const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r), fbo = __shfl(bo, r);
             for (int i = lane; i < kMergeFT; i += 64) fb_keys[w][i] = kEmpty;
             lds_fence();
             int c = 0;
             for (long long p = fa0; p < fa1; ++p) {
-                const int32_t kk = acol[p];
+                const long long kk = acol[p] + fbo;
                 const long long q1 = brp[kk + 1];
                 for (long long q = brp[kk] + lane; q < q1; q += 64)
                     c += hash_insert_key<kMergeFT>(fb_keys[w], bcol[q], &err);
@@ -807,13 +842,16 @@ k_sym_merge(int nrows_bin, const int32_t* __restrict__ perm,
 // stores, so each cache line of C is written once and completely.
 constexpr int kMergeStage = 512;
 
-template <int K, typename VT, typename IT>
+template <int K, typename VT, typename IT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
-k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
+k_num_merge(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            int32_t* __restrict__ cnt_out, DevInfo* info) {
+            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     constexpr int FT = kMergeFT;
     constexpr int SN = kMergeStage;
     static_assert(SN >= FT / 2, "a fallback row must fit the staging area");
@@ -830,13 +868,14 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
     for (long long pos = lo; pos < hi;) {
         const int ncand = (int)(hi - pos < 64 ? hi - pos : 64);
         int row = -1;
-        long long a0 = 0, a1 = 0, c0 = 0, c1 = 0;
+        long long a0 = 0, a1 = 0, c0 = 0, c1 = 0, bo = 0;
         if (lane < ncand) {
             row = perm ? perm[pos + lane] : (int)(pos + lane);
             a0 = arp[row];
             a1 = arp[row + 1];
             c0 = crp[row];
             c1 = crp[row + 1];
+            bo = row_boff<BATCH>(mp, row);
         }
         const long long nn = c1 - c0;           // row's output size (symbolic)
         const long long incl = group_incl_scan<64>(nn, lane);
@@ -862,7 +901,7 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
                 hp[k] = 0;
                 he[k] = 0;
                 if (k < (int)(a1 - a0)) {
-                    const int32_t kk = acol[a0 + k];
+                    const long long kk = acol[a0 + k] + bo;
                     ha[k] = to_f64(aval[a0 + k]);
                     hp[k] = (IT)brp[kk];
                     he[k] = (IT)brp[kk + 1];
@@ -895,7 +934,7 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
         while (fb) {                                   // wave-uniform
             const int r = __builtin_ctzll(fb);
             fb &= fb - 1;
-            const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
+            const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r), fbo = __shfl(bo, r);
             const long long fnn = __shfl(nn, r);
             const int frow = __shfl(row, r);
             const int fso = st_off[w][r];
@@ -903,7 +942,7 @@ k_num_merge(int nrows_bin, const int32_t* __restrict__ perm,
             for (int i = lane; i < FT; i += 64) { fb_keys[w][i] = kEmpty; fb_vals[w][i] = 0.0; }
             lds_fence();
             for (long long p = fa0; p < fa1; ++p) {
-                const int32_t kk = acol[p];
+                const long long kk = acol[p] + fbo;
                 const double a = to_f64(aval[p]);
                 const long long q1 = brp[kk + 1];
                 for (long long q = brp[kk] + lane; q < q1; q += 64) {
@@ -1096,13 +1135,16 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
 // are compacted (group ballot) and each entry's output position is its
 // rank among the row's keys (keys are distinct), counted with 16-byte LDS
 // reads.  Per-group LDS rows are padded so groups start on different banks.
-template <int G, int T, typename VT>
+template <int G, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
-k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
+k_num_group(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            int32_t* __restrict__ cnt_out, DevInfo* info) {
+            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     constexpr int NG = GroupCfg<G>::NG;
     constexpr int CK = T / 2 + 4;                 // compacted keys, 16-byte rows
     __shared__ int32_t keys[NG][T + 1];
@@ -1124,6 +1166,7 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
     const long long hi = lo + per < nrows_bin ? lo + per : nrows_bin;
     for (long long slot = lo + g; slot < hi; slot += NG) {      // group-uniform
     const int row = perm ? perm[slot] : (int)slot;
+    const long long bo = row_boff<BATCH>(mp, row);
     int re = 0;                                  // this row's table overflowed
 #pragma unroll
     for (int s = gl; s < T; s += G) { kt[s] = kEmpty; vt[s] = 0.0; }
@@ -1134,7 +1177,7 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
         long long len = 0, bst = 0;
         double a = 0.0;
         if (p < a1) {
-            const int32_t k = acol[p];
+            const long long k = acol[p] + bo;
             a = to_f64(aval[p]);
             bst = brp[k];
             len = brp[k + 1] - bst;
@@ -1203,13 +1246,16 @@ k_num_group(int nrows_bin, const int32_t* __restrict__ perm,
 // Numeric, one workgroup per row: LDS hash of T (key, FP64) slots, then the
 // occupied slots are compacted to the front and bitonic-sorted by key in
 // LDS, and the row is written with coalesced stores.
-template <int BS, int T, typename VT>
+template <int BS, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
-k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
+k_num_block(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            int32_t* __restrict__ cnt_out, DevInfo* info) {
+            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     constexpr int PER = T / BS;    // slots per thread in the compaction
     static_assert(PER >= 1, "T must be >= BS");
     __shared__ int32_t keys[T];
@@ -1223,6 +1269,7 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
     int err = 0;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
+        const long long bo = row_boff<BATCH>(mp, row);
         for (int s = tid; s < T; s += BS) { keys[s] = kEmpty; vals[s] = 0.0; }
         if (tid == 0) s_fail = 0;
         __syncthreads();
@@ -1232,7 +1279,7 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
             long long len = 0, bst = 0;
             double a = 0.0;
             if (p < a1) {
-                const int32_t k = acol[p];
+                const long long k = acol[p] + bo;
                 a = to_f64(aval[p]);
                 bst = brp[k];
                 len = brp[k + 1] - bst;
@@ -1322,13 +1369,16 @@ k_num_block(int nrows_bin, const int32_t* __restrict__ perm,
 // Products are added with device-scope FP64 atomics; the bitmap is then
 // scanned in column order, which writes the row already sorted and returns
 // the touched slab entries to zero.
-template <int BS, bool LDSBM, typename VT>
+template <int BS, bool LDSBM, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
-k_num_dense(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
+k_num_dense(Work wk, long long ncols,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            double* dslab, uint32_t* gbm, int32_t* __restrict__ cnt_out, DevInfo* info) {
+            double* dslab, uint32_t* gbm, int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
     extern __shared__ uint32_t dyn_smem[];
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -1340,6 +1390,7 @@ k_num_dense(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
     uint32_t* bm = LDSBM ? dyn_smem : gbm + (long long)blockIdx.x * words;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
+        const long long bo = row_boff<BATCH>(mp, row);
         if (LDSBM) {
             for (long long w = tid; w < words; w += BS) bm[w] = 0u;
         }
@@ -1350,7 +1401,7 @@ k_num_dense(int nrows_bin, const int32_t* __restrict__ perm, long long ncols,
             long long len = 0, bst = 0;
             double a = 0.0;
             if (p < a1) {
-                const int32_t k = acol[p];
+                const long long k = acol[p] + bo;
                 a = to_f64(aval[p]);
                 bst = brp[k];
                 len = brp[k + 1] - bst;

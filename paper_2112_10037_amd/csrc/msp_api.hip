@@ -57,8 +57,11 @@ extern "C" int msp_version(void) { return 1; }
 // ---------------------------------------------------------------------------
 namespace msp {
 
+thread_local bool g_capturing = false;
+
 msp_status DevBuf::ensure(size_t need) {
     if (need <= bytes) return MSP_OK;
+    if (g_capturing) return fail(MSP_ERR_HIP, "internal: workspace growth during graph capture");
     if (ptr) {
         hipError_t e = hipFree(ptr);
         ptr = nullptr;

@@ -183,15 +183,17 @@ int count_unsupported_plans(int verbose) {
     return bad;
 }
 
-template <typename VT>
+template <typename VT, bool BATCH>
 static void* dense_kernel(bool lds) {
-    return lds ? (void*)k_num_dense<1024, true, VT> : (void*)k_num_dense<1024, false, VT>;
+    return lds ? (void*)k_num_dense<1024, true, VT, BATCH> : (void*)k_num_dense<1024, false, VT, BATCH>;
 }
 
 msp_status configure_kernels(msp_handle* h) {
     // allow the bitmap kernels the device's full LDS for their dynamic part
     const int dyn = std::max(0, h->lds_per_block - kLdsReserve);
-    void* fns[] = {(void*)k_sym_bitmap<1024, true>, dense_kernel<float>(true), dense_kernel<double>(true)};
+    void* fns[] = {(void*)k_sym_bitmap<1024, true, false>, (void*)k_sym_bitmap<1024, true, true>,
+                   dense_kernel<float, false>(true), dense_kernel<double, false>(true),
+                   dense_kernel<float, true>(true), dense_kernel<double, true>(true)};
     for (void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         if (e != hipSuccess) {
@@ -230,56 +232,55 @@ static msp_status launch_check(const char* what) {
     return MSP_OK;
 }
 
-// symbolic kernel of one bin over `rows` rows listed in perm (or all rows)
-static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
-                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz,
-                                  const int32_t* ufilter = nullptr, int umax = 0) {
+// symbolic kernel of one bin over the rows of `wk`; `rows` (the row count,
+// or an estimate when wk reads it from the device) sizes persistent grids
+template <bool BATCH>
+static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
+                                    int32_t* rnnz, const RowMap& mp, const int32_t* ufilter = nullptr,
+                                    int umax = 0) {
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
-    const int m = (int)A->nrows;
     hipStream_t st = h->stream;
     if (s.kind == Kind::Merge) {
-        const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4> : (const void*)k_sym_merge<8>;
+        const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4, BATCH> : (const void*)k_sym_merge<8, BATCH>;
         const int grid = group_grid(h, fn, rows, 256);
         if (s.lanes == 4)
-            k_sym_merge<4><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, ufilter, umax,
-                                                 rnnz, info);
+            k_sym_merge<4, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, ufilter, umax, rnnz,
+                                                        info, mp);
         else
-            k_sym_merge<8><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, ufilter, umax,
-                                                 rnnz, info);
+            k_sym_merge<8, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, ufilter, umax, rnnz,
+                                                        info, mp);
         return launch_check("k_sym_merge");
     } else if (s.kind == Kind::Batch) {
-#define X(T, R)                                                                                  \
-    if (s.slots == T && s.lanes == R) {                                                          \
-        const int grid = group_grid(h, (const void*)k_sym_wave<T, R>, rows, 4 * R);             \
-        k_sym_wave<T, R><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, \
-                                                rnnz, info);                                     \
-        return launch_check("k_sym_wave");                                                      \
+#define X(T, R)                                                                                        \
+    if (s.slots == T && s.lanes == R) {                                                                \
+        const int grid = group_grid(h, (const void*)k_sym_wave<T, R, BATCH>, rows, 4 * R);            \
+        k_sym_wave<T, R, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp); \
+        return launch_check("k_sym_wave");                                                            \
     }
         MSP_SYM_BATCH_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Group) {
-#define X(G, T)                                                                                 \
-    if (s.lanes == G && s.slots == T) {                                                         \
-        const int grid = group_grid(h, (const void*)k_sym_group<G, T>, rows, 256 / G);         \
-        k_sym_group<G, T><<<grid, 256, 0, st>>>(rows, perm, m, A->row_ptr, A->col, B->row_ptr, \
-                                                B->col, rnnz, info);                           \
-        return launch_check("k_sym_group");                                                     \
+#define X(G, T)                                                                                       \
+    if (s.lanes == G && s.slots == T) {                                                               \
+        const int grid = group_grid(h, (const void*)k_sym_group<G, T, BATCH>, rows, 256 / G);        \
+        k_sym_group<G, T, BATCH><<<grid, 256, 0, st>>>(wk, (int)op.m, op.arp, op.acol, op.brp, op.bcol, rnnz, \
+                                                       info, mp);                                     \
+        return launch_check("k_sym_group");                                                           \
     }
         MSP_GROUP_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Block) {
         const int grid = std::min(rows, 4 * h->num_cu);
-#define X(BS, T)                                                                                  \
-    if (s.lanes == BS && s.slots == T) {                                                          \
-        k_sym_block<BS, T><<<grid, BS, 0, st>>>(rows, perm, A->row_ptr, A->col, B->row_ptr, B->col, \
-                                                rnnz, info);                                      \
-        return launch_check("k_sym_block");                                                       \
+#define X(BS, T)                                                                                       \
+    if (s.lanes == BS && s.slots == T) {                                                               \
+        k_sym_block<BS, T, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp); \
+        return launch_check("k_sym_block");                                                            \
     }
         MSP_SYM_BLOCK_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Bitmap) {
-        const long long n = B->ncols;
+        const long long n = op.ncols;
         const long long words = (n + 31) / 32;
         const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
         const int grid = std::min(rows, (lds ? 1 : 2) * h->num_cu);
@@ -290,74 +291,75 @@ static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, con
             slab = h->sbm.as<uint32_t>();
         }
         if (lds)
-            k_sym_bitmap<1024, true><<<grid, 1024, words * 4, st>>>(rows, perm, n, A->row_ptr, A->col,
-                                                                    B->row_ptr, B->col, rnnz, slab, info);
+            k_sym_bitmap<1024, true, BATCH><<<grid, 1024, words * 4, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol,
+                                                                           rnnz, slab, info, mp);
         else
-            k_sym_bitmap<1024, false><<<grid, 1024, 0, st>>>(rows, perm, n, A->row_ptr, A->col,
-                                                             B->row_ptr, B->col, rnnz, slab, info);
+            k_sym_bitmap<1024, false, BATCH><<<grid, 1024, 0, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol, rnnz,
+                                                                    slab, info, mp);
         return launch_check("k_sym_bitmap");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no symbolic kernel for bin shape (%d, %d)", s.lanes, s.slots);
 }
 
-template <typename VT>
-static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
-                                   const msp_csr* A, const msp_csr* B, const int64_t* crp,
-                                   int32_t* ccol, VT* cval, int32_t* cnt_out) {
+template <typename VT, bool BATCH>
+static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
+                                   const int64_t* crp, int32_t* ccol, VT* cval, int32_t* cnt_out,
+                                   const RowMap& mp) {
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
-    const VT* av = (const VT*)A->val;
-    const VT* bv = (const VT*)B->val;
+    const VT* av = (const VT*)op.aval;
+    const VT* bv = (const VT*)op.bval;
     if (s.kind == Kind::Merge) {
-        const bool small = B->nnz < INT32_MAX;     // 32-bit positions into B
-#define MSP_MERGE(KK, IT)                                                                             \
-    {                                                                                                 \
-        const int grid = group_grid(h, (const void*)k_num_merge<KK, VT, IT>, rows, 256);             \
-        k_num_merge<KK, VT, IT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
-                                                      B->col, bv, crp, ccol, cval, cnt_out, info);   \
-        return launch_check("k_num_merge");                                                           \
+        const bool small = op.bnnz < INT32_MAX;     // 32-bit positions into B
+#define MSP_MERGE(KK, IT)                                                                                \
+    {                                                                                                    \
+        const int grid = group_grid(h, (const void*)k_num_merge<KK, VT, IT, BATCH>, rows, 256);         \
+        k_num_merge<KK, VT, IT, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, \
+                                                             ccol, cval, cnt_out, info, mp);            \
+        return launch_check("k_num_merge");                                                              \
     }
         if (s.lanes == 4) { if (small) MSP_MERGE(4, int) else MSP_MERGE(4, long long) }
         else { if (small) MSP_MERGE(8, int) else MSP_MERGE(8, long long) }
 #undef MSP_MERGE
     } else if (s.kind == Kind::Batch) {
-#define X(T, R)                                                                                    \
-    if (s.slots == T && s.lanes == R) {                                                            \
-        const int grid = group_grid(h, (const void*)k_num_wave<T, R, VT>, rows, 4 * R);           \
-        k_num_wave<T, R, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr,  \
-                                                    B->col, bv, crp, ccol, cval, cnt_out, info);  \
-        return launch_check("k_num_wave");                                                        \
+#define X(T, R)                                                                                          \
+    if (s.slots == T && s.lanes == R) {                                                                  \
+        const int grid = group_grid(h, (const void*)k_num_wave<T, R, VT, BATCH>, rows, 4 * R);          \
+        k_num_wave<T, R, VT, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, \
+                                                          cval, cnt_out, info, mp);                      \
+        return launch_check("k_num_wave");                                                              \
     }
         MSP_NUM_BATCH_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Group) {
-#define X(G, T)                                                                                   \
-    if (s.lanes == G && s.slots == T) {                                                           \
-        const int grid = group_grid(h, (const void*)k_num_group<G, T, VT>, rows, 256 / G);       \
-        k_num_group<G, T, VT><<<grid, 256, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
-                                                    B->col, bv, crp, ccol, cval, cnt_out, info); \
-        return launch_check("k_num_group");                                                       \
+#define X(G, T)                                                                                            \
+    if (s.lanes == G && s.slots == T) {                                                                    \
+        const int grid = group_grid(h, (const void*)k_num_group<G, T, VT, BATCH>, rows, 256 / G);         \
+        k_num_group<G, T, VT, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, \
+                                                           ccol, cval, cnt_out, info, mp);                \
+        return launch_check("k_num_group");                                                                \
     }
         MSP_GROUP_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Block) {
         const int grid = std::min(rows, 4 * h->num_cu);
-#define X(BS, T)                                                                                  \
-    if (s.lanes == BS && s.slots == T) {                                                          \
-        k_num_block<BS, T, VT><<<grid, BS, 0, st>>>(rows, perm, A->row_ptr, A->col, av, B->row_ptr, \
-                                                    B->col, bv, crp, ccol, cval, cnt_out, info); \
-        return launch_check("k_num_block");                                                       \
+#define X(BS, T)                                                                                             \
+    if (s.lanes == BS && s.slots == T) {                                                                     \
+        k_num_block<BS, T, VT, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp,   \
+                                                           ccol, cval, cnt_out, info, mp);                  \
+        return launch_check("k_num_block");                                                                  \
     }
         MSP_NUM_BLOCK_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Dense) {
-        const long long n = B->ncols;
+        const long long n = op.ncols;
         const long long words = (n + 31) / 32;
         const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
         // one slab per resident workgroup; keep the arena under 16 GiB
         long long cap = (16LL << 30) / std::max(1LL, n * 8);
         int nslab = (int)std::max(1LL, std::min<long long>(h->num_cu, cap));
         if (h->dslab_cols != (size_t)n || h->dslab_count < nslab) {
+            if (g_capturing) return fail(MSP_ERR_HIP, "internal: dense slab set-up during graph capture");
             msp_status r = h->dslab.ensure((size_t)nslab * (size_t)n * 8);
             if (r != MSP_OK) return r;
             hipError_t e = hipMemsetAsync(h->dslab.ptr, 0, (size_t)nslab * (size_t)n * 8, st);
@@ -373,25 +375,66 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, int rows, co
         }
         const int grid = std::min(rows, nslab);
         if (lds)
-            k_num_dense<1024, true, VT><<<grid, 1024, words * 4, st>>>(
-                rows, perm, n, A->row_ptr, A->col, av, B->row_ptr, B->col, bv, crp, ccol, cval,
-                h->dslab.as<double>(), nullptr, cnt_out, info);
+            k_num_dense<1024, true, VT, BATCH><<<grid, 1024, words * 4, st>>>(
+                wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->dslab.as<double>(), nullptr,
+                cnt_out, info, mp);
         else
-            k_num_dense<1024, false, VT><<<grid, 1024, 0, st>>>(
-                rows, perm, n, A->row_ptr, A->col, av, B->row_ptr, B->col, bv, crp, ccol, cval,
-                h->dslab.as<double>(), h->gbm.as<uint32_t>(), cnt_out, info);
+            k_num_dense<1024, false, VT, BATCH><<<grid, 1024, 0, st>>>(
+                wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->dslab.as<double>(),
+                h->gbm.as<uint32_t>(), cnt_out, info, mp);
         return launch_check("k_num_dense");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no numeric kernel for bin shape (%d, %d)", s.lanes, s.slots);
 }
 
+template <bool BATCH>
+msp_status launch_symbolic_bin(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
+                               int32_t* rnnz, const RowMap& mp, const int32_t* ufilter, int umax) {
+    return launch_symbolic_t<BATCH>(h, s, wk, rows, op, rnnz, mp, ufilter, umax);
+}
+
+template <bool BATCH>
+msp_status launch_numeric_bin(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
+                              const int64_t* crp, int32_t* ccol, void* cval, int32_t* cnt_out, const RowMap& mp) {
+    if (rows <= 0) return MSP_OK;
+    if (op.dtype == MSP_F64)
+        return launch_numeric_t<double, BATCH>(h, s, wk, rows, op, crp, ccol, (double*)cval, cnt_out, mp);
+    return launch_numeric_t<float, BATCH>(h, s, wk, rows, op, crp, ccol, (float*)cval, cnt_out, mp);
+}
+
+template msp_status launch_symbolic_bin<true>(msp_handle*, const BinSpec&, Work, int, const Operands&, int32_t*,
+                                              const RowMap&, const int32_t*, int);
+template msp_status launch_numeric_bin<true>(msp_handle*, const BinSpec&, Work, int, const Operands&,
+                                             const int64_t*, int32_t*, void*, int32_t*, const RowMap&);
+
+Operands operands_of(const msp_csr* A, const msp_csr* B) {
+    Operands op;
+    op.arp = A->row_ptr;
+    op.acol = A->col;
+    op.aval = A->val;
+    op.brp = B->row_ptr;
+    op.bcol = B->col;
+    op.bval = B->val;
+    op.ncols = B->ncols;
+    op.bnnz = B->nnz;
+    op.m = A->nrows;
+    op.dtype = A->dtype;
+    return op;
+}
+
+// plain product: rows listed in perm (or all rows)
+static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
+                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz,
+                                  const int32_t* ufilter = nullptr, int umax = 0) {
+    return launch_symbolic_t<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), rnnz, RowMap{},
+                                    ufilter, umax);
+}
+
 static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
                                  const msp_csr* A, const msp_csr* B, const int64_t* crp,
                                  int32_t* ccol, void* cval, int32_t* cnt_out) {
-    if (rows <= 0) return MSP_OK;
-    if (A->dtype == MSP_F64)
-        return launch_numeric_t<double>(h, s, rows, perm, A, B, crp, ccol, (double*)cval, cnt_out);
-    return launch_numeric_t<float>(h, s, rows, perm, A, B, crp, ccol, (float*)cval, cnt_out);
+    return launch_numeric_bin<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), crp, ccol, cval,
+                                     cnt_out, RowMap{});
 }
 
 // ---------------------------------------------------------------------------
@@ -430,11 +473,11 @@ msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, cons
     if (feat)
         k_row_stats<true><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                       h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
-                                                      plan.table, h->info.as<DevInfo>(), feat, lo_out);
+                                                      plan.table, h->info.as<DevInfo>(), feat, lo_out, RowMap{});
     else
         k_row_stats<false><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                        h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
-                                                       plan.table, h->info.as<DevInfo>(), nullptr, nullptr);
+                                                       plan.table, h->info.as<DevInfo>(), nullptr, nullptr, RowMap{});
     return launch_check("k_row_stats");
 }
 

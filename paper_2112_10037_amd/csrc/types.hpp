@@ -15,6 +15,8 @@ constexpr int kErrProbe = 1;      // a hash probe sequence exceeded the table (b
 constexpr int kErrUnsorted = 2;   // input columns not strictly increasing
 constexpr int kErrRange = 4;      // input index out of range / row_ptr not monotone
 constexpr int kErrCount = 8;      // numeric count disagrees with the symbolic count
+constexpr int kErrPlan = 16;      // batch replay: a row fell in a bin the plan has no kernel for
+constexpr int kErrCapacity = 32;  // batch replay: the output outgrew the plan's arena
 
 // Predictor features 0..5 are log2(1 + x) scaled by this factor so that
 // every network input is of order one.
@@ -44,6 +46,51 @@ struct BinTable {
     int nb;
     int umax[kMaxBins];
 };
+
+// The rows one bin kernel processes: perm[0..n) (perm null: rows 0..n-1).
+// Kernels queued before the bin sizes reach the host (captured batch graphs)
+// read n and perm's offset from device memory instead: dev[0], dev[1].
+struct Work {
+    const int32_t* perm;
+    int n;
+    const int* dev;
+};
+
+__device__ __forceinline__ void work_rows(const Work& w, int* n, const int32_t** perm) {
+    if (w.dev) {
+        *n = w.dev[0];
+        *perm = w.perm ? w.perm + w.dev[1] : nullptr;
+    } else {
+        *n = w.n;
+        *perm = w.perm;
+    }
+}
+
+// Batched inputs in packed form.  Problem p owns the global rows
+// [row_start[p], row_start[p+1]) of the packed A (one row_ptr array with
+// global offsets into one col/val array).  Its column indices are local:
+// column k of problem p is row boff[p] + k of the packed B, and its output
+// columns are B's local columns (< ncols[p]).  tile_prob[t] is the problem
+// of global row 64 t.
+struct RowMap {
+    const int32_t* tile_prob;
+    const int64_t* row_start;
+    const int64_t* boff;
+    const int64_t* ncols;
+};
+
+__device__ __forceinline__ int map_prob(const RowMap& mp, long long g) {
+    int p = mp.tile_prob[g >> 6];
+    while (g >= mp.row_start[p + 1]) ++p;      // skip problems that end inside the tile
+    return p;
+}
+
+// offset of the B rows of global row g's problem (0 when not batched)
+template <bool BATCH>
+__device__ __forceinline__ long long row_boff(const RowMap& mp, long long g) {
+    if constexpr (BATCH) return mp.boff[map_prob(mp, g)];
+    else return 0;
+}
 
 __device__ __forceinline__ int bin_of(const BinTable& t, long long u) {
     if (u <= 0) return 0;

@@ -42,3 +42,19 @@ def test_status_strings_and_null_handle():
     assert b"null handle" in lib.msp_last_error()
     assert lib.msp_destroy(None) == 0
     assert lib.msp_set_tuning(None, None) == 1
+
+
+def test_tuning_json_roundtrip_and_rejects():
+    from paper_2112_10037_amd import binding
+    for t in [(1, 0, 4096, 128, 8), (2, 2, 256, 32, -1), (1, 1, 1024, 64, 4)]:
+        js = binding.tuning_to_json(t)
+        assert binding.tuning_from_json(js) == t
+    # field order and spacing are free
+    assert binding.tuning_from_json('{"merge_k":4,"block_rows":64,"spill_nnz":512,'
+                                    '"group_scale":1,"hash_scale":2}') == (2, 1, 512, 64, 4)
+    import pytest
+    with pytest.raises(binding.MspError):
+        binding.tuning_from_json('{"hash_scale": 1}')
+    with pytest.raises(binding.MspError):
+        binding.tuning_from_json('{"hash_scale": 9, "group_scale": 0, "spill_nnz": 4096, '
+                                 '"block_rows": 128, "merge_k": 8}')
