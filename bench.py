@@ -1,20 +1,31 @@
 #!/usr/bin/env python3
-"""Benchmark of the plain two-phase SpGEMM C = A*A on one MI355X.
+"""Benchmark of the SpGEMM library on one MI355X.
 
-Default workload: A = 2D 5-point Laplacian on a 1024 x 1024 grid (1,048,576
-rows, 5,238,784 nonzeros, FP64), C = A*A (26,177,544 intermediate products,
-13,611,012 nonzeros).  Inputs are generated on the host, copied to HBM once,
-and every timed step is one full msp_spgemm call (statistics, binning,
-symbolic pass, prefix sum, allocation of C, numeric pass with sorted rows).
+Main line (the `value`): the plain two-phase product C = A*A with A the 2D
+5-point Laplacian on a 1024 x 1024 grid (1,048,576 rows, 5,238,784
+nonzeros, FP64; 26,177,544 intermediate products, nnz(C) = 13,611,012).
+Inputs are copied to HBM once; every timed step is one whole msp_spgemm
+call (statistics, binning, symbolic pass, prefix sum, allocation of C,
+numeric pass with sorted rows).  GFLOP/s = 2 x products / time.
 
-Prints ONE JSON line with the whole-job throughput (GFLOP/s = 2 x products /
-time), the HBM roofline of the dominant kernel (the numeric pass, timed with
-HIP events on the library's stream), and the CPU oracle timed on the host.
+Also reported on the same line:
+  * roofline: the numeric kernel's algorithmic bytes over its average
+    launch time (HIP events on the library's stream), against 8 TB/s;
+  * cpu_baseline: the C oracle on the host cores, on the same workload;
+  * learned_vs_plain: the one-pass learned product against the plain one on
+    the 16 held-out members of a 64-matrix mixed suite (27-point stencils,
+    Erdos-Renyi with 4..32 nonzeros per row, R-MAT with degree 8..32; FP64),
+    the network trained on the GPU on the other 48;
+  * batched_vs_plain: 512 Galerkin products R (A P) (7-point Laplacians with
+    sides n ~ U{16..64}, 2x2x2 aggregation) in one graph replay against the
+    1,024 plain calls they amount to.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -26,17 +37,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 
-# FETCH_SIZE / WRITE_SIZE of the numeric kernel on the default workload,
-# from two rocprofv3 --pmc passes scaled by a plain copy kernel (see
-# profiles/); None until measured for the current kernel.
-MEASURED_TRAFFIC_BYTES = None
+# HBM bytes per launch of the numeric kernel on the main workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors
+# read off a 1 GiB copy kernel), valid for the kernel sources whose hash is
+# given; any other source state reports null.
+MEASURED_TRAFFIC = {"sources_sha256": None, "bytes": None}
+KERNEL_SOURCES = ["kernels.hpp", "types.hpp", "spgemm.hip"]
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_10037_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def workload(name: str):
     from paper_2112_10037_amd import gen
     if name == "laplacian2d_1024":
-        return ("2D 5-point Laplacian 1024x1024, C = A*A, FP64",
-                gen.laplacian_2d(1024))
+        return ("2D 5-point Laplacian 1024x1024, C = A*A, FP64", gen.laplacian_2d(1024))
     if name == "er4096":
         return ("Erdos-Renyi 4096x4096, 8 nnz/row, FP64 U[-1,1], seed 0, C = A*A",
                 gen.erdos_renyi(4096, 4096, 8, seed=0))
@@ -55,6 +75,10 @@ def algorithmic_bytes(A, nnz_c: int) -> int:
     return 2 * a + c
 
 
+def csr_bytes(nrows: int, nnz: int, vb: int = 8) -> int:
+    return (nrows + 1) * 8 + nnz * (4 + vb)
+
+
 def cpu_baseline(A, products: int, budget_s: float) -> dict:
     import oracle
     cores = oracle.num_threads()
@@ -64,12 +88,197 @@ def cpu_baseline(A, products: int, budget_s: float) -> dict:
         oracle.spgemm(A, A)
         runs += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 200:
+        if el >= budget_s:
             break
     return {"value": round(2.0 * products * runs / el / 1e9, 3), "unit": "GFLOP/s",
             "cores": cores, "kind": "oracle",
-            "sample": f"{runs} full products of the same workload in {el:.1f} s "
+            "sample": f"{runs} full products of the main workload in {el:.1f} s "
                       f"(C oracle, FP64 dense accumulator, OpenMP over rows)"}
+
+
+# ---------------------------------------------------------------------------
+# host data (built before the GPU is touched: the pool forks)
+# ---------------------------------------------------------------------------
+def _build_member(m):
+    return m.index, m.build()
+
+
+def build_suite(workers: int):
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2112_10037_amd import gen
+    suite = gen.learned_suite()
+    mats = {}
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for i, M in ex.map(_build_member, suite):
+            mats[i] = M
+    return suite, mats
+
+
+def timed(fn, reps: int):
+    """Median wall time (s) of fn() over reps calls after one warm call; fn
+    waits for its own result."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def geomean(x):
+    return float(math.exp(np.mean(np.log(np.asarray(x, dtype=np.float64)))))
+
+
+# ---------------------------------------------------------------------------
+# legs
+# ---------------------------------------------------------------------------
+def learned_leg(h, suite, mats, reps: int, steps: int) -> dict:
+    import torch
+    from paper_2112_10037_amd import binding, learned
+    dev = lambda M: binding.DeviceCSR.from_host(M, "cuda:0")          # noqa: E731
+    t0 = time.perf_counter()
+    train = [m for m in suite if not m.held_out]
+    test = [m for m in suite if m.held_out]
+    prods = []
+    for m in train:
+        d = dev(mats[m.index])
+        prods.append((d, d))
+    feats, targets = learned.training_set(h, prods)
+    del prods
+    t_rows = time.perf_counter() - t0
+    progress(f"learned: {int(feats.shape[0])} training rows in {t_rows:.1f} s")
+    t1 = time.perf_counter()
+    pred, losses, delta = learned.train(h, feats, targets, steps=steps, batch=4096, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    progress(f"learned: trained {steps} steps in {t_train:.1f} s, loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.5f}")
+    upper = binding.Predictor(h, learned.fixed_capacity_params(8.0))
+    lin = binding.Predictor(h, learned.linear_fit_params(feats.cpu().numpy(), targets.cpu().numpy()))
+    lin.calibrate(feats, targets, 0.99)
+    n_train_rows = int(feats.shape[0])
+    del feats, targets
+    torch.cuda.empty_cache()
+
+    rows = []
+    for m in test:
+        M = mats[m.index]
+        dM = dev(M)
+
+        def run_plain():
+            C = h.spgemm(dM, dM)
+            return C
+
+        t_plain = timed(lambda: run_plain(), reps)
+        Cp = run_plain()
+        res = {"index": m.index, "family": m.family, "rows": M.nrows, "nnz_a": M.nnz,
+               "nnz_c": Cp.nnz, "plain_ms": round(t_plain * 1e3, 3)}
+        for name, p in (("learned", pred), ("network_free", upper), ("linear_fit", lin)):
+            st = {}
+
+            def run_l(p=p, st=st):
+                C, s = h.spgemm_learned(p, dM, dM)
+                st.update(s)
+                return C
+
+            t = timed(run_l, reps)
+            C = run_l()
+            same = bool(torch.equal(C.row_ptr, Cp.row_ptr) and torch.equal(C.col, Cp.col))
+            res[name] = {"ms": round(t * 1e3, 3), "speedup": round(t_plain / t, 4),
+                         "overflow_rows": st["overflow_rows"], "sum_cap_over_nnz": round(st["sum_cap"] / max(Cp.nnz, 1), 4),
+                         "structure_identical": same}
+            del C
+        del Cp, dM
+        torch.cuda.empty_cache()
+        rows.append(res)
+        progress(f"learned: held-out {m.index} ({m.family}, {M.nrows} rows): plain {res['plain_ms']} ms, "
+                 f"learned x{res['learned']['speedup']}, network-free x{res['network_free']['speedup']}")
+    out = {"workload": "64-matrix mixed suite (27-point stencils n~U[41,101], ER 2^16..2^20 rows with 4..32 "
+                       "nnz/row, R-MAT 2^16..2^18 rows with degree 8..32; FP64 U[-1,1]; seeds 1000+i), "
+                       "C = A*A; trained on 48, evaluated on the 16 held out (index = 3 mod 4)",
+           "training": {"rows": n_train_rows, "steps": steps, "batch": 4096,
+                        "loss_first": round(float(losses[0]), 6), "loss_last": round(float(np.mean(losses[-20:])), 6),
+                        "delta": round(float(delta), 4), "rows_s": round(t_rows, 2), "train_s": round(t_train, 2)}}
+    for name in ("learned", "network_free", "linear_fit"):
+        total_ovf = sum(r[name]["overflow_rows"] for r in rows)
+        total_rows = sum(r["rows"] for r in rows)
+        out[name] = {"geomean_speedup_vs_plain": round(geomean([r[name]["speedup"] for r in rows]), 4),
+                     "overflow_rate": round(total_ovf / total_rows, 5),
+                     "mean_sum_cap_over_nnz": round(float(np.mean([r[name]["sum_cap_over_nnz"] for r in rows])), 4),
+                     "all_structure_identical": all(r[name]["structure_identical"] for r in rows)}
+    out["per_matrix"] = rows
+    for p in (pred, upper, lin):
+        p.close()
+    return out
+
+
+def batched_leg(h, sides, reps: int, tuning_cache: str) -> dict:
+    import torch
+    from paper_2112_10037_amd import batch, binding, gen
+    t0 = time.perf_counter()
+    pA, pP, pR = batch.galerkin_batch(sides)
+    t_gen = time.perf_counter() - t0
+    progress(f"batched: {len(sides)} problems packed and uploaded in {t_gen:.1f} s")
+    # autotune on a seeded 32-problem subset, cached by the subset's shape
+    sub = np.random.default_rng(5).choice(len(sides), 32, replace=False)
+    sA, sP, sR = batch.galerkin_batch(sides[np.sort(sub)])
+    tuning, tinfo = batch.autotune_cached(h, sA, sP, sR, tuning_cache)
+    del sA, sP, sR
+    t1 = time.perf_counter()
+    plan = binding.Batch(h, pA, pP, pR, tuning=tuning)
+    t_plan = time.perf_counter() - t1
+    info = plan.info()
+    progress(f"batched: tuning {tuning} (cached: {tinfo['cached']}), plan made in {t_plan:.1f} s")
+
+    def replay():
+        plan.execute()
+        plan.sync()
+
+    t_graph = timed(replay, reps)
+    nprob = len(sides)
+
+    def plain_all():
+        for p in range(nprob):
+            AP = h.spgemm(pA.view(p), pP.view(p), check=False)
+            C = h.spgemm(pR.view(p), AP, check=False)
+            del AP, C
+        h.sync()
+        torch.cuda.synchronize()
+
+    progress(f"batched: graph replay {t_graph * 1e3:.2f} ms")
+    t_plain = timed(plain_all, max(1, reps // 5))
+    progress(f"batched: 1,024 plain calls {t_plain * 1e3:.1f} ms")
+    # identical results (integer values) on a few problems
+    same = True
+    for p in (0, nprob // 2, nprob - 1):
+        AP = h.spgemm(pA.view(p), pP.view(p))
+        C = h.spgemm(pR.view(p), AP)
+        Cb = plan.result(p)
+        same = same and bool(torch.equal(C.row_ptr, Cb.row_ptr) and torch.equal(C.col, Cb.col)
+                             and torch.equal(C.val, Cb.val))
+    nnz_a, nnz_ap = pA.nnz, int(info["nnz"][0])
+    nnz_ac = int(info["nnz"][1])
+    products = nnz_a + nnz_ap      # P and R hold one entry per fine row
+    m_a, m_ac = int(pA.row_start[-1]), int(pR.row_start[-1])
+    alg = (csr_bytes(m_a, nnz_a) + csr_bytes(m_a, pP.nnz) + csr_bytes(m_a, nnz_ap)
+           + csr_bytes(m_ac, pR.nnz) + csr_bytes(m_a, nnz_ap) + csr_bytes(m_ac, nnz_ac))
+    plan.close()
+    return {"workload": f"{nprob} Galerkin products R (A P), A = 3D 7-point Laplacian n^3 (n ~ U{{16..64}}, "
+                        f"seed 5), P = 2x2x2 aggregation, FP64",
+            "rows_fine": m_a, "rows_coarse": m_ac, "nnz_a": nnz_a, "nnz_ap": nnz_ap, "nnz_ac": nnz_ac,
+            "products": products, "graph_ms": round(t_graph * 1e3, 3), "plain_1024_calls_ms": round(t_plain * 1e3, 3),
+            "speedup": round(t_plain / t_graph, 3),
+            "graph_gflops": round(2 * products / t_graph / 1e9, 3),
+            "plain_gflops": round(2 * products / t_plain / 1e9, 3),
+            "graph_algorithmic_gbs": round(alg / t_graph / 1e9, 1),
+            "tuning": list(tuning), "tuning_cached": tinfo["cached"],
+            "autotune_median_ms": tinfo.get("median_ms"),
+            "plan": info, "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2),
+            "results_identical_to_plain": same}
 
 
 def main():
@@ -78,23 +287,37 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="laplacian2d_1024")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--legs-reps", type=int, default=5)
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--tuning-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "msp_tuning.json"))
     ap.add_argument("--tuning", default=None,
                     help="hash_scale,group_scale,spill_nnz,block_rows,merge_k (default: library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the product would shard).", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path in this library "
+              "(the design notes describe how the product would shard).", file=sys.stderr)
         sys.exit(2)
+
+    from paper_2112_10037_amd import gen
+    desc, A = workload(args.workload)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    suite = mats = None
+    if not args.no_learned:
+        t0 = time.perf_counter()
+        suite, mats = build_suite(workers)
+        progress(f"suite of {len(mats)} matrices built in {time.perf_counter() - t0:.1f} s")
+    sides = gen.galerkin_sizes(512, 16, 64, seed=5)
 
     import torch
     from paper_2112_10037_amd import binding
     import oracle
 
-    desc, A = workload(args.workload)
     st = oracle.row_stats(A, A)
     products = int(st["prod"].sum())
     dA = binding.DeviceCSR.from_host(A, "cuda:0")
@@ -126,7 +349,10 @@ def main():
     num_avg_s = num_ms / max(num_n, 1) / 1e3
     alg = algorithmic_bytes(A, nnz_c)
     achieved = alg / num_avg_s / 1e9
-    traffic = MEASURED_TRAFFIC_BYTES if args.workload == "laplacian2d_1024" else None
+    traffic = None
+    if (args.workload == "laplacian2d_1024" and MEASURED_TRAFFIC["sources_sha256"]
+            and MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_hash()):
+        traffic = MEASURED_TRAFFIC["bytes"]
 
     out = {
         "metric": "SpGEMM GFLOP/s (2x products/s)",
@@ -142,16 +368,22 @@ def main():
         "dtype": "f64" if A.val.dtype == np.float64 else "f32",
         "data": "synthetic",
         "config": {"workload": desc, "rows": A.nrows, "nnz_a": A.nnz, "products": products,
-                   "nnz_c": nnz_c, "path": "plain two-phase",
-                   "tuning": list(h.get_tuning())},
-        "roofline": {"bound": "hbm", "kernel": "numeric pass",
+                   "nnz_c": nnz_c, "path": "plain two-phase", "tuning": list(h.get_tuning())},
+        "roofline": {"bound": "hbm", "kernel": "numeric pass (k_num_merge)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes": alg,
-                     "avg_launch_ms": round(num_avg_s * 1e3, 5)},
+                     "algorithmic_bytes": alg, "avg_launch_ms": round(num_avg_s * 1e3, 5)},
         "phases_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in prof.items() if v[1]},
         "hbm_gbs_whole_step_algorithmic": round(alg / (el / args.steps) / 1e9, 1),
     }
+    del dA
+    torch.cuda.empty_cache()
+    progress(f"main: {gflops:.1f} GFLOP/s, {ms_step:.4f} ms per step")
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_leg(h, suite, mats, args.legs_reps, args.train_steps)
+        del mats
+    if not args.no_batched:
+        out["batched_vs_plain"] = batched_leg(h, sides, max(args.legs_reps, 10), args.tuning_cache)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, products, args.cpu_seconds)
     if args.calibrate_copy:

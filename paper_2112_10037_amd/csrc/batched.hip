@@ -616,6 +616,11 @@ extern "C" msp_status msp_batch_autotune(msp_handle* h, const msp_batch_csr* R, 
             last_err = s;
         }
         if (b) msp_batch_destroy(b);
+        if (s == MSP_ERR_HIP) {       // the device reported an error: try nothing more on it
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return s;
+        }
         if (times_ms) times_ms[c] = med;
         if (med < best_ms) {
             best_ms = med;

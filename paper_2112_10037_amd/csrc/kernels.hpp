@@ -129,6 +129,14 @@ __device__ __forceinline__ int owner_search(const OffT* off, int n, long long q)
     return lo;
 }
 
+// Length of the run of set bits at the bottom of a lane mask: 64 when every
+// bit is set (count-trailing-zeros of 0 is undefined, so it is not used
+// for that case).
+__device__ __forceinline__ int leading_run(uint64_t m) {
+    const uint64_t z = ~m;
+    return z ? __builtin_ctzll(z) : 64;
+}
+
 // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
 // block b runs on XCD b % 8.  Give XCD x the x-th contiguous eighth of the
 // logical blocks so that neighbouring rows (which share B rows) meet in the
@@ -563,7 +571,7 @@ __device__ __forceinline__ int wave_rows_take(WaveRows<RM>& wr, long long pos, l
     }
     const long long incl = group_incl_scan<64>(len, lane);
     const uint64_t fits = __ballot(lane < ncand && incl <= 64);
-    int nb = __builtin_ctzll(~fits);          // leading run of rows that fit
+    int nb = leading_run(fits);               // leading run of rows that fit
     if (nb == 0) nb = 1;
     if (lane < nb) {
         wr.off[lane] = incl - len;
@@ -880,7 +888,7 @@ k_num_merge(Work wk,
         const long long nn = c1 - c0;           // row's output size (symbolic)
         const long long incl = group_incl_scan<64>(nn, lane);
         const uint64_t fits = __ballot(lane < ncand && incl <= SN);
-        int nb = __builtin_ctzll(~fits);
+        int nb = leading_run(fits);             // all 64 rows may fit
         if (nb == 0) nb = 1;                    // never happens in bins with nnz <= SN
         const bool in = lane < nb;
         if (in) { st_off[w][lane] = (int)(incl - nn); st_c0[w][lane] = c0; }

@@ -202,3 +202,18 @@ def test_autotune_picks_a_candidate(h):
     got = plan.result(i).to_host()
     assert np.array_equal(got.col, ref[1]) and np.array_equal(got.val, ref[2])
     plan.close()
+
+
+def test_batch_full_merge_batches(h):
+    """Four problems of 4,096 rows with at most 4 outputs per row (16,384
+    rows in all): every merge batch takes all 64 of its rows."""
+    rng = np.random.default_rng(31)
+    A = [gen.erdos_renyi(4096, 2048, rng.integers(1, 5, 4096), seed=40 + i) for i in range(4)]
+    P = [gen.aggregation_prolongator(n)[0] for n in (13, 13, 13, 13)]          # 2197 x 343
+    P = [gen.CSR(2048, 343, p.row_ptr[:2049], p.col[:2048], p.val[:2048]) for p in P]
+    pa, pp = binding.PackedBatch.from_host(A), binding.PackedBatch.from_host(P)
+    plan = binding.Batch(h, pa, pp)
+    plan.execute()
+    for i in range(4):
+        _check(plan.result(i), oracle.spgemm(A[i], P[i]), np.float64)
+    plan.close()

@@ -274,3 +274,17 @@ def test_rmat_2p20_fp32_sampled(h):
             idx = torch.searchsorted(rp, bad, right=False)
             assert torch.all(rp[idx] == bad), "a row is not strictly increasing"
     del starts
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_merge_full_batches_of_short_rows(h, dtype):
+    """16,384 rows with at most 4 outputs each: the merge kernel's row
+    ranges hold 64 rows per wave and every 64-row batch fits its staging
+    area (the case where all 64 candidate rows are taken at once)."""
+    m, n = 16384, 4096
+    rng = np.random.default_rng(77)
+    A = gen.erdos_renyi(m, n, rng.integers(1, 5, m), seed=78, dtype=dtype)
+    # one entry per row of B, in a permuted column
+    B = gen.CSR(n, n, np.arange(n + 1, dtype=np.int64), rng.permutation(n).astype(np.int32),
+                rng.uniform(-1, 1, n).astype(dtype))
+    check_full(h, A, B)
