@@ -96,8 +96,12 @@ typedef struct {
     int32_t group_scale;    /* lanes per row = default << group_scale (0..2)      */
     int32_t spill_nnz;      /* numeric rows with more nnz use the global path
                                (a power of two, 256..4096)                       */
-    int32_t block_rows;     /* rows with bound above this (32, 64 or 128) use
-                               one workgroup per row                            */
+    int32_t block_rows;     /* rows with bound above this (a power of two,
+                               32..1024) use one workgroup per row; below it,
+                               merges, lane groups or one wave per row (the
+                               wave tables stop at 2048 symbolic keys and 512
+                               numeric slots, beyond which workgroups take
+                               over)                                            */
     int32_t merge_k;        /* rows with bound <= 32 and at most merge_k A
                                entries use the per-lane merge (4 or 8; -1: off) */
 } msp_tuning;
@@ -340,9 +344,10 @@ typedef struct {
     int64_t count[MSP_NUM_PHASES];   /* number of timed intervals per phase  */
 } msp_profile;
 
-/* Turn per-phase event timing on (1) or off (0); either way the
- * accumulators are reset.  Timing adds two event records per phase. */
-msp_status msp_profile_enable(msp_handle* h, int on);
+/* Per-phase event timing: bit p of phase_mask times phase p (-1: every
+ * phase, 0: off); either way the accumulators are reset.  Each timed
+ * phase adds two event records to the stream. */
+msp_status msp_profile_enable(msp_handle* h, int phase_mask);
 /* Accumulated times of the intervals that have completed so far. */
 msp_status msp_profile_get(msp_handle* h, msp_profile* out);
 

@@ -263,9 +263,13 @@ class Handle:
         except Exception:
             pass
 
-    def profile(self, on: bool = True):
-        """Enable (and reset) per-phase HIP-event timing."""
-        _check(self._lib.msp_profile_enable(self._h, int(bool(on))))
+    def profile(self, on: bool = True, phases=None):
+        """Enable (and reset) per-phase HIP-event timing: every phase, or only
+        the named ones (names as in PHASES)."""
+        mask = 0
+        if on:
+            mask = -1 if phases is None else sum(1 << PHASES.index(p) for p in phases)
+        _check(self._lib.msp_profile_enable(self._h, mask))
 
     def profile_get(self) -> dict:
         """{phase: (total ms, intervals)} for every phase timed so far."""
@@ -275,6 +279,14 @@ class Handle:
 
     def set_tuning(self, tuning):
         _check(self._lib.msp_set_tuning(self._h, ctypes.byref(c_tuning(*tuning))))
+
+    def summary_fallbacks(self) -> int:
+        """Times a pass summary was read from a device copy because the
+        kernel's direct write to host memory had not yet arrived."""
+        f = self._lib.msp_internal_summary_fallbacks
+        f.argtypes = [ctypes.c_void_p]
+        f.restype = ctypes.c_longlong
+        return int(f(self._h))
 
     def get_tuning(self):
         t = c_tuning()

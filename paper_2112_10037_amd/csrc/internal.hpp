@@ -58,6 +58,7 @@ struct ExtraState;                  // learned / batched state (other units)
 // folded into the accumulators once they have completed.
 struct Profiler {
     bool on = false;
+    unsigned mask = ~0u;     // phases timed (bit p: phase p)
     double ms[MSP_NUM_PHASES] = {};
     int64_t count[MSP_NUM_PHASES] = {};
     struct Pending { int phase; hipEvent_t a, b; };
@@ -89,7 +90,12 @@ struct msp_handle {
     int dslab_count = 0;
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
     int* hpending = nullptr;        // pinned: error bits of the last call's numeric
-                                    // kernels, copied back without waiting
+                                    // kernels, forwarded by the next call's first kernel
+    int* dpending = nullptr;        // device address of hpending (null: not forwarded)
+    msp::HostSummary* hsum = nullptr;   // pinned, coherent: summaries the kernels publish
+    msp::HostSummary* dsum = nullptr;   // its device address
+    int sum_seq = 0;                // sequence number of the last summary requested
+    long long summary_fallbacks = 0;    // summaries taken from a device copy instead
     int scan_epoch = 0;             // epoch of the single-pass scan's tile states
     msp::ExtraState* extra = nullptr;
     msp::Profiler prof;
@@ -119,11 +125,15 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill);
 // The plain pipeline pieces, reused by the learned and batched forms.
 msp_status read_info(msp_handle* h);
 msp_status zero_info(msp_handle* h);
+// Wait until the kernel given sequence number `seq` has published its host
+// summary (spinning on pinned memory, checking the stream for errors).
+msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)[kPartStride]);
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                         int64_t* prod_out, float* feat, int32_t* lo_out);
+                         int64_t* prod_out, float* feat, int32_t* lo_out, int publish_seq = 0);
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                              const int* counts_host, int32_t* row_nnz, int done_bin);
-msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan);
+msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan,
+                    int publish_seq = 0);
 msp_status take_pending_error(msp_handle* h);
 msp_status check_pair(const msp_csr* A, const msp_csr* B);
 msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B);

@@ -22,6 +22,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "types.hpp"
@@ -45,6 +46,35 @@ __device__ __forceinline__ double load_coherent(const double* p) {
 }
 __device__ __forceinline__ uint32_t load_coherent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int load_coherent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long load_coherent(const long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// After a pass (kernel boundary: its counters are complete), sum the
+// partitioned bin counters and write the host summary, seq last.
+// One workgroup of 64 threads.
+static __global__ void __launch_bounds__(64)
+k_publish(const DevInfo* info, int numeric, int nb, HostSummary* hs, int seq) {
+    const int t = threadIdx.x;
+    const int* part = numeric ? &info->num_part[0][0] : &info->sym_part[0][0];
+    if (t < kNB) {
+        int c = 0;
+        if (t <= nb)
+            for (int p = 0; p < kParts; ++p) c += part[p * kPartStride + t];
+        hs->counts[t] = c;
+    }
+    __syncthreads();
+    if (t == 0) {
+        hs->nnz = numeric ? info->nnz : 0;
+        hs->err = info->err;
+        hs->neg_count = info->neg_count;
+        __threadfence_system();
+        __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 __device__ __forceinline__ void lds_fence() {
@@ -154,6 +184,20 @@ static __global__ void k_zero_words(int* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// Clear the device info block of a new call; the error bits the previous
+// call's numeric kernels left there go to the host's pending word first
+// (pending may be null).  One workgroup.
+static __global__ void __launch_bounds__(256) k_zero_info(int* p, int n, int* pending) {
+    if (threadIdx.x == 0 && pending) {
+        // only the numeric kernels' bits: input-check bits were reported by
+        // the call that set them
+        const int e = p[offsetof(DevInfo, err) / 4] & (kErrProbe | kErrCount);
+        if (e) __hip_atomic_store(pending, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) p[i] = 0;
+}
+
 // ===========================================================================
 // Per-row statistics and symbolic binning
 // ===========================================================================
@@ -176,6 +220,23 @@ __device__ __forceinline__ int wave_hist_add(int* hist, int b) {
         todo &= ~same;
     }
     return rank;
+}
+
+// As wave_hist_add with a weight per lane (lanes with b < 0 add nothing).
+// Wave-uniform control flow required.
+__device__ __forceinline__ void wave_hist_add_w(int* hist, int b, int w) {
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(b >= 0);
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int bl = __shfl(b, leader);
+        const uint64_t same = __ballot(b == bl);
+        int x = b == bl ? w : 0;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
+        if (lane == leader) atomicAdd(&hist[bl], x);
+        todo &= ~same;
+    }
 }
 
 // One wave per 64 consecutive rows.  The wave walks the A entries of its
@@ -1014,7 +1075,7 @@ k_num_merge(Work wk,
 // Exclusive prefix sum of row_nnz -> row_ptr (int64), fused with the
 // numeric binning histogram
 // ===========================================================================
-constexpr int kScanBS = 1024;
+constexpr int kScanBS = 256;
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kScanBS * kScanPer;
 
@@ -1049,13 +1110,22 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
         return;
     }
     const long long base = (long long)tile * kScanTile + (long long)threadIdx.x * kScanPer;
+    static_assert(kScanPer == 8, "the vector path loads two int4");
     int v[kScanPer];
     long long s = 0;
     int neg = 0;
+    const bool full = base + kScanPer <= m;
+    if (full && ((uintptr_t)cnt & 15) == 0) {
+        const int4 q0 = *reinterpret_cast<const int4*>(cnt + base);
+        const int4 q1 = *reinterpret_cast<const int4*>(cnt + base + 4);
+        v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+        v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) v[i] = base + i < m ? cnt[base + i] : 0;
+    }
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-        const long long r = base + i;
-        v[i] = r < m ? cnt[r] : 0;
         if (v[i] < 0) { ++neg; v[i] = 0; }   // an overflowed row: counted, sums as 0
         s += v[i];
     }
@@ -1114,12 +1184,41 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
     }
     __syncthreads();
     long long run = s_prefix + incl - s;
+    long long rp[kScanPer];
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-        const long long r = base + i;
-        if (r < m && row_ptr) row_ptr[r] = run;
+        rp[i] = run;
         run += v[i];
-        if (bins.nb > 0) wave_hist_add(hist, r < m ? bin_of(bins, v[i]) : -1);
+    }
+    if (row_ptr) {
+        if (full && ((uintptr_t)row_ptr & 15) == 0) {
+#pragma unroll
+            for (int i = 0; i < kScanPer; i += 2)
+                *reinterpret_cast<longlong2*>(row_ptr + base + i) = make_longlong2(rp[i], rp[i + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanPer; ++i)
+                if (base + i < m) row_ptr[base + i] = rp[i];
+        }
+    }
+    if (bins.nb > 0) {
+        // a thread's rows usually share one bin: one weighted add then
+        const int b0 = base < m ? bin_of(bins, v[0]) : -1;
+        int nv = 0;
+        bool same = true;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i)
+            if (base + i < m) {
+                ++nv;
+                same = same && bin_of(bins, v[i]) == b0;
+            }
+        if (__ballot(!same) == 0) {
+            wave_hist_add_w(hist, b0, nv);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanPer; ++i)
+                wave_hist_add(hist, base + i < m ? bin_of(bins, v[i]) : -1);
+        }
     }
     if (m > 0 && base <= m - 1 && m - 1 < base + kScanPer) {
         if (row_ptr) row_ptr[m] = run;     // the thread holding row m-1 closes row_ptr

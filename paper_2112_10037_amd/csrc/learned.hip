@@ -304,41 +304,74 @@ k_patch_overflow(int ns, const int32_t* __restrict__ list, const int64_t* __rest
     src_off[r] = -(crp_sub[j] + 1);              // negative: from the sub-product
 }
 
-// Compaction: a wave copies 64 consecutive rows, whose destination range is
-// contiguous; each destination entry finds its row by binary search over
-// the 65 row pointers in LDS.  A row's source is the padded product at
-// rp_pad[row], or the sub-product when src_off[row] < 0.
+// Compaction into the tight CSR, balanced by output entries: workgroup b
+// writes destination entries [b CH, (b+1) CH) whatever the row lengths, so
+// a hub row is spread over many workgroups.  chunk_row[b] is the row that
+// holds entry b CH.  A row's source is the padded product at rp_pad[row],
+// or the sub-product at -src_off[row]-1 when src_off[row] < 0.
+constexpr int kCompactChunk = 4096;
+constexpr int kCompactRows = 1024;      // rows staged in LDS per chunk
+
+static __global__ void __launch_bounds__(256)
+k_chunk_rows(int m, const int64_t* __restrict__ rp, int32_t* __restrict__ chunk_row) {
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= m) return;
+    const long long d0 = rp[r], d1 = rp[r + 1];
+    for (long long c = (d0 + kCompactChunk - 1) / kCompactChunk; c * kCompactChunk < d1; ++c)
+        chunk_row[c] = (int32_t)r;
+}
+
 template <typename VT>
 __global__ void __launch_bounds__(256)
-k_compact(int m, const int64_t* __restrict__ rp, const int64_t* __restrict__ rp_pad,
-          const int64_t* __restrict__ src_off, const int32_t* __restrict__ pcol, const VT* __restrict__ pval,
-          const int32_t* __restrict__ scol, const VT* __restrict__ sval,
+k_compact(int m, long long nnz, const int32_t* __restrict__ chunk_row, const int64_t* __restrict__ rp,
+          const int64_t* __restrict__ rp_pad, const int64_t* __restrict__ src_off, const int32_t* __restrict__ pcol,
+          const VT* __restrict__ pval, const int32_t* __restrict__ scol, const VT* __restrict__ sval,
           int32_t* __restrict__ ccol, VT* __restrict__ cval) {
-    __shared__ long long s_rp[4][65];
-    __shared__ long long s_src[4][64];
-    __shared__ int s_sub[4][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long r0 = ((long long)blockIdx.x * 4 + w) * 64;
-    if (r0 >= m) return;
-    const int nr = (int)(m - r0 < 64 ? m - r0 : 64);
-    if (lane < nr) {
-        s_rp[w][lane] = rp[r0 + lane];
-        const long long so = src_off ? src_off[r0 + lane] : 0;
-        s_sub[w][lane] = so < 0;
-        s_src[w][lane] = so < 0 ? -so - 1 : rp_pad[r0 + lane];
-    }
-    if (lane == 0) s_rp[w][nr] = rp[r0 + nr];
-    lds_fence();
-    const long long d0 = s_rp[w][0], d1 = s_rp[w][nr];
-    for (long long d = d0 + lane; d < d1; d += 64) {
-        int lo = 0, hi = nr;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_rp[w][mid] <= d) lo = mid; else hi = mid;
+    __shared__ long long s_rp[kCompactRows + 1];
+    __shared__ long long s_src[kCompactRows];
+    const long long nch = (nnz + kCompactChunk - 1) / kCompactChunk;
+    const long long b = blockIdx.x;
+    const long long d0 = b * kCompactChunk;
+    const long long d1 = d0 + kCompactChunk < nnz ? d0 + kCompactChunk : nnz;
+    const int r0 = chunk_row[b];
+    const int r1 = b + 1 < nch ? chunk_row[b + 1] : m - 1;   // rows r0..r1 cover [d0, d1)
+    const int nr = r1 - r0 + 1;
+    // a row's source position of its first entry (negative: from the sub-product)
+    auto src_of = [&](int r) -> long long {
+        const long long so = src_off ? src_off[r] : 0;
+        return so < 0 ? so : rp_pad[r];
+    };
+    if (nr <= kCompactRows) {
+        for (int j = threadIdx.x; j <= nr; j += 256) {
+            s_rp[j] = rp[r0 + j];
+            if (j < nr) s_src[j] = src_of(r0 + j);
         }
-        const long long src = s_src[w][lo] + (d - s_rp[w][lo]);
-        if (s_sub[w][lo]) { ccol[d] = scol[src]; cval[d] = sval[src]; }
-        else { ccol[d] = pcol[src]; cval[d] = pval[src]; }
+        __syncthreads();
+        for (long long d = d0 + threadIdx.x; d < d1; d += 256) {
+            int lo = 0, hi = nr;                       // s_rp[lo] <= d < s_rp[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_rp[mid] <= d) lo = mid; else hi = mid;
+            }
+            const long long so = s_src[lo];
+            const long long k = d - s_rp[lo];
+            if (so < 0) { ccol[d] = scol[-so - 1 + k]; cval[d] = sval[-so - 1 + k]; }
+            else { ccol[d] = pcol[so + k]; cval[d] = pval[so + k]; }
+        }
+    } else {
+        // many short rows: one thread per row, clipped to the chunk
+        for (int j = threadIdx.x; j < nr; j += 256) {
+            const int r = r0 + j;
+            const long long e0 = rp[r], e1 = rp[r + 1];
+            const long long a = e0 > d0 ? e0 : d0, z = e1 < d1 ? e1 : d1;
+            if (a >= z) continue;
+            const long long so = src_of(r);
+            for (long long d = a; d < z; ++d) {
+                const long long k = d - e0;
+                if (so < 0) { ccol[d] = scol[-so - 1 + k]; cval[d] = sval[-so - 1 + k]; }
+                else { ccol[d] = pcol[so + k]; cval[d] = pval[so + k]; }
+            }
+        }
     }
 }
 
@@ -346,7 +379,7 @@ k_compact(int m, const int64_t* __restrict__ rp, const int64_t* __restrict__ rp_
 // predictor object
 // ---------------------------------------------------------------------------
 struct ExtraState {
-    DevBuf feat, lo, cap, rp_pad, cnt, src_off, pad, list, sub_rp, sub_a, sub_c, sub_crp;
+    DevBuf feat, lo, cap, rp_pad, cnt, src_off, pad, list, sub_rp, sub_a, sub_c, sub_crp, chunk;
 };
 
 static ExtraState* extra(msp_handle* h) {
@@ -358,7 +391,7 @@ void release_extra(msp_handle* h) {
     if (!h->extra) return;
     ExtraState* x = h->extra;
     for (DevBuf* b : {&x->feat, &x->lo, &x->cap, &x->rp_pad, &x->cnt, &x->src_off, &x->pad, &x->list, &x->sub_rp,
-                      &x->sub_a, &x->sub_c, &x->sub_crp})
+                      &x->sub_a, &x->sub_c, &x->sub_crp, &x->chunk})
         b->release();
     delete x;
     h->extra = nullptr;
@@ -726,16 +759,22 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
         if (!base) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
         C->col = (int32_t*)base;
         C->val = (char*)base + voff;
+        const long long nch = (nnz + kCompactChunk - 1) / kCompactChunk;
+        if (nch > INT32_MAX) return cleanup(fail(MSP_ERR_INDEX_OVERFLOW, "too many output entries"));
+        if ((s = x->chunk.ensure((size_t)nch * 4)) != MSP_OK) return cleanup(s);
         h->prof.begin(MSP_PHASE_COMPACT, h->stream);
-        const int blocks = (m + 255) / 256;
+        k_chunk_rows<<<(m + 255) / 256, 256, 0, h->stream>>>(m, C->row_ptr, x->chunk.as<int32_t>());
+        if ((s = launch_check2("k_chunk_rows")) != MSP_OK) return cleanup(s);
         if (A->dtype == MSP_F64)
-            k_compact<double><<<blocks, 256, 0, h->stream>>>(m, C->row_ptr, x->rp_pad.as<int64_t>(), src_off, pcol,
-                                                             (const double*)pval, scol, (const double*)sval, C->col,
-                                                             (double*)C->val);
+            k_compact<double><<<(int)nch, 256, 0, h->stream>>>(m, nnz, x->chunk.as<int32_t>(), C->row_ptr,
+                                                              x->rp_pad.as<int64_t>(), src_off, pcol,
+                                                              (const double*)pval, scol, (const double*)sval, C->col,
+                                                              (double*)C->val);
         else
-            k_compact<float><<<blocks, 256, 0, h->stream>>>(m, C->row_ptr, x->rp_pad.as<int64_t>(), src_off, pcol,
-                                                            (const float*)pval, scol, (const float*)sval, C->col,
-                                                            (float*)C->val);
+            k_compact<float><<<(int)nch, 256, 0, h->stream>>>(m, nnz, x->chunk.as<int32_t>(), C->row_ptr,
+                                                             x->rp_pad.as<int64_t>(), src_off, pcol,
+                                                             (const float*)pval, scol, (const float*)sval, C->col,
+                                                             (float*)C->val);
         if ((s = launch_check2("k_compact")) != MSP_OK) return cleanup(s);
         h->prof.end(h->stream);
         hipError_t e2 = hipMemcpyAsync(h->hpending, &h->info.as<DevInfo>()->err, sizeof(int), hipMemcpyDeviceToHost,

@@ -128,14 +128,22 @@ extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
         delete h;
         return hip_fail(e, "hipHostMalloc");
     }
-    if ((e = hipHostMalloc((void**)&h->hpending, sizeof(int), hipHostMallocDefault)) != hipSuccess) {
+    // pending error word and host summaries: coherent, written by kernels
+    if ((e = hipHostMalloc((void**)&h->hpending, sizeof(int), hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&h->hsum, sizeof(HostSummary), hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&h->dpending, h->hpending, 0)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&h->dsum, h->hsum, 0)) != hipSuccess) {
+        if (h->hsum) (void)hipHostFree(h->hsum);
+        if (h->hpending) (void)hipHostFree(h->hpending);
         (void)hipHostFree(h->hinfo);
         h->info.release();
         delete h;
-        return hip_fail(e, "hipHostMalloc");
+        return hip_fail(e, "pinned host memory");
     }
     *h->hpending = 0;
+    memset(h->hsum, 0, sizeof(HostSummary));
     if ((s = configure_kernels(h)) != MSP_OK) {
+        (void)hipHostFree(h->hsum);
         (void)hipHostFree(h->hpending);
         (void)hipHostFree(h->hinfo);
         h->info.release();
@@ -156,6 +164,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     h->prof.release();
     if (h->hinfo) (void)hipHostFree(h->hinfo);
     if (h->hpending) (void)hipHostFree(h->hpending);
+    if (h->hsum) (void)hipHostFree(h->hsum);
     delete h;
     return MSP_OK;
 }
@@ -212,7 +221,7 @@ msp_tuning default_tuning() {
     t.hash_scale = 1;
     t.group_scale = 0;
     t.spill_nnz = 4096;
-    t.block_rows = 128;
+    t.block_rows = 1024;
     t.merge_k = 8;
     return t;
 }
@@ -229,8 +238,8 @@ msp_status check_tuning(msp_tuning* t) {
     if (t->group_scale < 0 || t->group_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.group_scale must be 0..2");
     if (t->spill_nnz < 256 || t->spill_nnz > 4096 || (t->spill_nnz & (t->spill_nnz - 1)))
         return fail(MSP_ERR_INVALID_ARG, "tuning.spill_nnz must be a power of two in 256..4096");
-    if (t->block_rows != 32 && t->block_rows != 64 && t->block_rows != 128)
-        return fail(MSP_ERR_INVALID_ARG, "tuning.block_rows must be 32, 64 or 128");
+    if (t->block_rows < 32 || t->block_rows > 1024 || (t->block_rows & (t->block_rows - 1)))
+        return fail(MSP_ERR_INVALID_ARG, "tuning.block_rows must be a power of two in 32..1024");
     return MSP_OK;
 }
 
@@ -268,6 +277,7 @@ hipEvent_t Profiler::get() {
 void Profiler::begin(int phase, hipStream_t s) {
     if (!on) return;
     if (open_phase >= 0) end(s);
+    if (!((mask >> phase) & 1u)) return;
     open_ev = get();
     if (!open_ev) return;
     open_phase = phase;
@@ -324,13 +334,14 @@ void Profiler::release() {
 
 }  // namespace msp
 
-extern "C" msp_status msp_profile_enable(msp_handle* h, int on) {
+extern "C" msp_status msp_profile_enable(msp_handle* h, int phase_mask) {
     if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
     h->prof.collect();
     h->prof.reset();
-    h->prof.on = on != 0;
+    h->prof.on = phase_mask != 0;
+    h->prof.mask = (unsigned)phase_mask;
     return MSP_OK;
 }
 
@@ -348,5 +359,13 @@ extern "C" msp_status msp_sync(msp_handle* h) {
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (h->prof.on) h->prof.collect();
+    // error bits of the last call's numeric kernels (taken here, so that
+    // the next call does not report them again)
+    int err = 0;
+    DevInfo* info = h->info.as<DevInfo>();
+    e = hipMemcpy(&err, &info->err, sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && err) e = hipMemset(&info->err, 0, sizeof(int));
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(error flags)");
+    if (err & (kErrProbe | kErrCount)) __atomic_fetch_or(h->hpending, err, __ATOMIC_RELAXED);
     return take_pending_error(h);
 }

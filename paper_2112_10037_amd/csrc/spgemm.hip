@@ -25,9 +25,11 @@ static int next_pow2(int x) {
 // ---------------------------------------------------------------------------
 // bin plans
 // ---------------------------------------------------------------------------
-// Sub-wave lane groups cover bounds up to block_rows (16, 32, 64, 128 with
-// 8, 16, 32, 64 lanes, scaled by group_scale); workgroup kernels cover the
-// middle; the last bin is the global path.  Hash tables get
+// Bounds up to block_rows go to the merge kernel (<= 32), wave-local row
+// batches and lane groups (16, 32, 64, 128 with 8, 16, 32, 64 lanes, scaled
+// by group_scale), and whole waves per row with LDS tables of up to 2048
+// keys (symbolic) or 512 (key, value) slots (numeric); workgroup kernels
+// cover the middle; the last bin is the global path.  Hash tables get
 // nextpow2(bound) << hash_scale slots, so they are at most half full.
 
 static void add_bin(BinPlan& p, int umax, BinSpec s) {
@@ -43,8 +45,8 @@ static void add_bin(BinPlan& p, int umax, BinSpec s) {
 static int sym_batch_rows(int T) { return T <= 64 ? 16 : 1024 / T; }
 
 static void add_small_bins(BinPlan& p, const msp_tuning& t, int limit, bool numeric) {
-    static const int umax[4] = {16, 32, 64, 128};
-    static const int g0[4] = {8, 16, 32, 64};
+    static const int umax[7] = {16, 32, 64, 128, 256, 512, 1024};
+    static const int g0[7] = {8, 16, 32, 64, 64, 64, 64};
     int covered = 0;
     // the merge takes row_nnz steps of K comparisons each: worth it for the
     // shortest rows only
@@ -52,19 +54,23 @@ static void add_small_bins(BinPlan& p, const msp_tuning& t, int limit, bool nume
         add_bin(p, 32, BinSpec{Kind::Merge, t.merge_k, kMergeFT});
         covered = 32;
     }
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 7; ++i) {
         if (umax[i] > limit) break;
         if (umax[i] <= covered) continue;
         const int T = next_pow2(umax[i]) << t.hash_scale;
         if (!numeric) {
-            add_bin(p, umax[i], BinSpec{Kind::Batch, sym_batch_rows(T), T});
+            if (T <= 256) add_bin(p, umax[i], BinSpec{Kind::Batch, sym_batch_rows(T), T});
+            else if (T <= 2048) add_bin(p, umax[i], BinSpec{Kind::Group, 64, T});
+            else break;
         } else if (T <= 64) {
             const int R = (T == 32 ? (t.group_scale == 0 ? 12 : 8 >> (t.group_scale - 1)) : 8 >> t.group_scale);
             add_bin(p, umax[i], BinSpec{Kind::Batch, R, T});
-        } else {
+        } else if (T <= 512) {
             int G = std::min(64, g0[i] << t.group_scale);
             G = std::min(G, T / 2);
             add_bin(p, umax[i], BinSpec{Kind::Group, G, T});
+        } else {
+            break;
         }
     }
 }
@@ -122,6 +128,7 @@ constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense ker
 #define MSP_GROUP_SHAPES(X) \
     X(8, 32) X(16, 32) X(8, 64) X(16, 64) X(32, 64) X(16, 128) X(32, 128) X(64, 128) \
     X(32, 256) X(64, 256) X(64, 512)
+#define MSP_SYM_GROUP_SHAPES(X) MSP_GROUP_SHAPES(X) X(64, 1024) X(64, 2048)
 #define MSP_SYM_BATCH_SHAPES(X) X(32, 16) X(64, 16) X(128, 8) X(256, 4) X(512, 2)
 #define MSP_NUM_BATCH_SHAPES(X) X(32, 12) X(32, 8) X(32, 4) X(64, 8) X(64, 4) X(64, 2)
 #define MSP_SYM_BLOCK_SHAPES(X) \
@@ -139,7 +146,7 @@ static bool spec_supported(const BinSpec& sp, bool numeric) {
             return false;
         case Kind::Group:
 #define X(G, T) if (sp.lanes == G && sp.slots == T) return true;
-            MSP_GROUP_SHAPES(X)
+            if (numeric) { MSP_GROUP_SHAPES(X) } else { MSP_SYM_GROUP_SHAPES(X) }
 #undef X
             return false;
         case Kind::Block:
@@ -160,7 +167,7 @@ int count_unsupported_plans(int verbose) {
     for (int hs = 1; hs <= 2; ++hs)
         for (int gs = 0; gs <= 2; ++gs)
             for (int sp : {64, 128, 256, 512, 1024, 2048, 4096})
-                for (int br : {32, 64, 128})
+                for (int br : {32, 64, 128, 256, 512, 1024})
                     for (int fs = 0; fs <= 1; ++fs) {
                       for (int mk : {4, 8, -1}) {
                         msp_tuning t{hs, gs, sp, br, mk};
@@ -268,7 +275,7 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
                                                        info, mp);                                     \
         return launch_check("k_sym_group");                                                           \
     }
-        MSP_GROUP_SHAPES(X)
+        MSP_SYM_GROUP_SHAPES(X)
 #undef X
     } else if (s.kind == Kind::Block) {
         const int grid = std::min(rows, 4 * h->num_cu);
@@ -442,8 +449,46 @@ static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, cons
 // ---------------------------------------------------------------------------
 msp_status zero_info(msp_handle* h) {
     const int words = (int)(sizeof(DevInfo) / 4);
-    k_zero_words<<<1, 256, 0, h->stream>>>((int*)h->info.ptr, words);
-    return launch_check("k_zero_words");
+    k_zero_info<<<1, 256, 0, h->stream>>>((int*)h->info.ptr, words, h->dpending);
+    return launch_check("k_zero_info");
+}
+
+// The summary is a posted write to host memory: the stream can report its
+// work complete a little before that write is visible.  After completion
+// the wait keeps polling for a while, then takes the same figures from a
+// copy of the device info block.
+msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)[kPartStride]) {
+    auto seen = [&] { return __atomic_load_n(&h->hsum->seq, __ATOMIC_ACQUIRE) == seq; };
+    bool ok = false;
+    for (unsigned long long it = 1; !ok; ++it) {
+        if (seen()) { ok = true; break; }
+        if ((it & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(h->stream);
+            if (q == hipSuccess) {
+                for (int k = 0; k < 200000 && !ok; ++k) {
+                    ok = seen();
+                    __builtin_ia32_pause();
+                }
+                break;
+            }
+            if (q != hipErrorNotReady) return hip_fail(q, "hipStreamQuery");
+        }
+        __builtin_ia32_pause();
+    }
+    if (!ok) {
+        ++h->summary_fallbacks;
+        msp_status s = read_info(h);
+        if (s != MSP_OK) return s;
+        const DevInfo* d = h->hinfo;
+        const int(*pp)[kPartStride] = (const int(*)[kPartStride])((const char*)d + ((const char*)part - (const char*)h->info.ptr));
+        h->hsum->nnz = with_nnz ? d->nnz : 0;
+        h->hsum->err = d->err;
+        h->hsum->neg_count = d->neg_count;
+        sum_parts(pp, h->hsum->counts);
+        return MSP_OK;
+    }
+    if (h->prof.on) h->prof.collect();
+    return take_pending_error(h);
 }
 
 msp_status take_pending_error(msp_handle* h) {
@@ -464,7 +509,8 @@ msp_status read_info(msp_handle* h) {
 }
 
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
-                         int64_t* prod_out, float* feat, int32_t* lo_out) {
+                         int64_t* prod_out, float* feat, int32_t* lo_out, int publish_seq) {
+
     const int m = (int)A->nrows;
     msp_status s = h->u.ensure((size_t)std::max(m, 1) * 4);
     if (s != MSP_OK) return s;
@@ -478,7 +524,10 @@ msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, cons
         k_row_stats<false><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                        h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
                                                        plan.table, h->info.as<DevInfo>(), nullptr, nullptr, RowMap{});
-    return launch_check("k_row_stats");
+    msp_status s2 = launch_check("k_row_stats");
+    if (s2 != MSP_OK || !publish_seq) return s2;
+    k_publish<<<1, 64, 0, h->stream>>>(h->info.as<DevInfo>(), 0, plan.table.nb, h->dsum, publish_seq);
+    return launch_check("k_publish");
 }
 
 void sum_parts(const int (*part)[kPartStride], int out[kNB]) {
@@ -544,7 +593,8 @@ msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, 
                     done_bin);
 }
 
-msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan) {
+msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_ptr, const BinPlan* plan,
+                    int publish_seq) {
     const int tiles = std::max(1, (m + kScanTile - 1) / kScanTile);
     const size_t need = (size_t)tiles * 8;
     if (need > h->tiles.bytes || h->scan_epoch == 0 || h->scan_epoch >= 0xffff) {
@@ -561,7 +611,10 @@ msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_p
     if (plan) bt = plan->table;
     k_scan_lookback<<<tiles, kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<unsigned long long>(),
                                                      h->scan_epoch, row_ptr, bt, h->info.as<DevInfo>());
-    return launch_check("k_scan_lookback");
+    msp_status s2 = launch_check("k_scan_lookback");
+    if (s2 != MSP_OK || !publish_seq) return s2;
+    k_publish<<<1, 64, 0, h->stream>>>(h->info.as<DevInfo>(), 1, bt.nb, h->dsum, publish_seq);
+    return launch_check("k_publish");
 }
 
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
@@ -612,7 +665,8 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     const BinPlan sp = symbolic_plan(t, opts && opts->force_spill);
     if ((s = zero_info(h)) != MSP_OK) return s;
     h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
-    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr)) != MSP_OK) return s;
+    const int seq = m > 0 ? ++h->sum_seq : 0;     // the statistics kernel publishes the bin sizes
+    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr, seq)) != MSP_OK) return s;
     h->prof.end(h->stream);
     // The merge bin (bin 1 when enabled) is queued before the bin counts are
     // read back: it picks its rows by their bound, so the GPU keeps working
@@ -625,9 +679,14 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
             return s;
         done_bin = 1;
     }
-    if ((s = read_info(h)) != MSP_OK) return s;
-    int counts[kNB];
-    sum_parts(h->hinfo->sym_part, counts);
+    int counts[kNB] = {};
+    if (m > 0) {
+        if ((s = wait_summary(h, seq, false, h->info.as<DevInfo>()->sym_part)) != MSP_OK) return s;
+        if ((s = device_error(h->hsum->err)) != MSP_OK) return s;
+        for (int b = 0; b < kNB; ++b) counts[b] = h->hsum->counts[b];
+    } else if ((s = take_pending_error(h)) != MSP_OK) {
+        return s;
+    }
     s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), done_bin);
     h->prof.end(h->stream);
     return s;
@@ -671,13 +730,14 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
     if ((s = symbolic_phase(h, A, B, opts, t)) != MSP_OK) return cleanup(s);
     const BinPlan np = numeric_plan(t, opts && opts->force_spill);
     h->prof.begin(MSP_PHASE_SCAN, h->stream);
-    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), C->row_ptr, &np)) != MSP_OK) return cleanup(s);
+    const int seq = ++h->sum_seq;             // the scan publishes nnz(C) and the numeric bin sizes
+    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), C->row_ptr, &np, seq)) != MSP_OK) return cleanup(s);
     h->prof.end(h->stream);
-    if ((s = read_info(h)) != MSP_OK) return cleanup(s);
-    if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
-    const long long nnz = h->hinfo->nnz;
+    if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part)) != MSP_OK) return cleanup(s);
+    if ((s = device_error(h->hsum->err)) != MSP_OK) return cleanup(s);
+    const long long nnz = h->hsum->nnz;
     int counts[kNB];
-    sum_parts(h->hinfo->num_part, counts);
+    for (int b = 0; b < kNB; ++b) counts[b] = h->hsum->counts[b];
     const size_t vsz = A->dtype == MSP_F64 ? 8 : 4;
     C->nrows = m;
     C->ncols = B->ncols;
@@ -695,10 +755,8 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
             return cleanup(s);
         h->prof.end(h->stream);
         C->val = (char*)base + voff;
-        // the numeric kernels' consistency flags come back without a wait
-        hipError_t e2 = hipMemcpyAsync(h->hpending, &h->info.as<DevInfo>()->err, sizeof(int),
-                                       hipMemcpyDeviceToHost, h->stream);
-        if (e2 != hipSuccess) return cleanup(hip_fail(e2, "hipMemcpyAsync(error flags)"));
+        // the numeric kernels' consistency flags reach the host through the
+        // next call's first kernel, or through msp_sync
     }
     return MSP_OK;
 }
@@ -730,10 +788,11 @@ extern "C" msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(row_nnz)");
     }
     // total through the scan (no row_ptr output)
-    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), nullptr, nullptr)) != MSP_OK) return s;
-    if ((s = read_info(h)) != MSP_OK) return s;
-    if ((s = device_error(h->hinfo->err)) != MSP_OK) return s;
-    if (nnz_total) *nnz_total = h->hinfo->nnz;
+    const int seq = ++h->sum_seq;
+    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), nullptr, nullptr, seq)) != MSP_OK) return s;
+    if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part)) != MSP_OK) return s;
+    if ((s = device_error(h->hsum->err)) != MSP_OK) return s;
+    if (nnz_total) *nnz_total = h->hsum->nnz;
     return MSP_OK;
 }
 
@@ -751,5 +810,7 @@ extern "C" msp_status msp_row_features(msp_handle* h, const msp_csr* A, const ms
     if ((s = zero_info(h)) != MSP_OK) return s;
     return run_row_stats(h, A, B, none, prod, features ? features : nullptr, nullptr);
 }
+
+extern "C" long long msp_internal_summary_fallbacks(const msp_handle* h) { return h ? h->summary_fallbacks : -1; }
 
 extern "C" int msp_internal_unsupported_plans(int verbose) { return msp::count_unsupported_plans(verbose); }

@@ -40,6 +40,17 @@ struct DevInfo {
     int cursor[kParts][kPartStride];      // scatter cursors
 };
 
+// What the host needs between passes, written by a one-workgroup kernel
+// straight into pinned host memory (no copy, no stream wait); seq is
+// written last and tells the host that the rest is complete.
+struct HostSummary {
+    long long nnz;
+    int err;
+    int neg_count;
+    int counts[kNB];                      // rows per bin, summed over partitions
+    int seq;
+};
+
 // Bin b (1 <= b < nb) holds rows with umax[b-1] < u <= umax[b]; bin 0 holds
 // u == 0; bin nb holds everything above umax[nb-1] (the global path).
 struct BinTable {

@@ -192,10 +192,23 @@ def test_transpose_identity_structure(h):
     oracle.compare(Ct.row_ptr, Ct.col, Ct.val, ref, 1e-12)
 
 
-@pytest.mark.parametrize("tuning", [(1, 0, 4096, 128, 8), (2, 0, 4096, 128, 4), (1, 1, 1024, 64, -1),
-                                    (2, 2, 256, 32, 8), (1, 2, 512, 128, -1), (2, 1, 2048, 128, 4)])
+TUNINGS = [(1, 0, 4096, 128, 8), (2, 0, 4096, 128, 4), (1, 1, 1024, 64, -1), (2, 2, 256, 32, 8),
+           (1, 2, 512, 128, -1), (2, 1, 2048, 128, 4), (1, 0, 4096, 1024, 8), (2, 0, 4096, 1024, 8),
+           (1, 1, 2048, 512, -1), (2, 2, 1024, 256, 4)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
 def test_tuning_variants_same_result(h, tuning):
     A = gen.rmat(12, 12 << 12, seed=15, dtype=np.float64)
+    check_full(h, A, A, tuning=tuning)
+
+
+@pytest.mark.parametrize("tuning", [(1, 0, 4096, 128, 8), (1, 0, 4096, 1024, 8), (2, 0, 4096, 1024, 8),
+                                    (1, 1, 512, 256, -1)])
+def test_stencil27_bins(h, tuning):
+    """27-point rows: 729 products, 125 outputs (one-wave tables up to 1024
+    bounds, or workgroups)."""
+    A = gen.stencil_27(14, seed=16, dtype=np.float64)
     check_full(h, A, A, tuning=tuning)
 
 
@@ -288,3 +301,20 @@ def test_merge_full_batches_of_short_rows(h, dtype):
     B = gen.CSR(n, n, np.arange(n + 1, dtype=np.int64), rng.permutation(n).astype(np.int32),
                 rng.uniform(-1, 1, n).astype(dtype))
     check_full(h, A, B)
+
+
+def test_pass_summaries_reach_the_host():
+    """The statistics and scan passes publish their summaries straight to
+    pinned host memory; the device-copy fallback is not needed."""
+    hh = binding.Handle(0)
+    try:
+        A = gen.laplacian_2d(200)
+        dA = to_dev(A)
+        for _ in range(5):
+            C = hh.spgemm(dA, dA)
+        ref = oracle.spgemm(A, A)
+        host = C.to_host()
+        assert np.array_equal(host.col, ref[1]) and np.array_equal(host.val, ref[2])
+        assert hh.summary_fallbacks() == 0
+    finally:
+        hh.close()
