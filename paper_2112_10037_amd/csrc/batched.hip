@@ -271,7 +271,7 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
     const int tiles = std::max(1, (M + kScanTile - 1) / kScanTile);
     k_zero_words<<<(2 * tiles + 255) / 256, 256, 0, st>>>((int*)h->tiles.ptr, 2 * tiles);
     k_scan_lookback<<<tiles, kScanBS, 0, st>>>(M, h->rnnz.as<int32_t>(), h->tiles.as<unsigned long long>(), 1,
-                                               S.crp.as<int64_t>(), S.np.table, info);
+                                               S.crp.as<int64_t>(), S.np.table, info, nullptr, 0);
     if ((s = launch_ok("k_scan_lookback")) != MSP_OK) return s;
     if (eager) {
         if ((s = read_info(h)) != MSP_OK) return s;

@@ -823,7 +823,26 @@ k_sym_merge(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             const int32_t* __restrict__ ufilter, int umax,
-            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp,
+            HostSummary* hs = nullptr, int hs_seq = 0, int hs_nb = 0) {
+    // Queued right after the statistics pass, this kernel also publishes
+    // that pass's bin sizes to the host (wave 0 of workgroup 0).
+    if (hs && blockIdx.x == 0 && threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        if (t < kNB) {
+            int c = 0;
+            if (t <= hs_nb)
+                for (int p = 0; p < kParts; ++p) c += info->sym_part[p][t];
+            hs->counts[t] = c;
+        }
+        if (t == 0) {
+            hs->nnz = 0;
+            hs->err = info->err;
+            hs->neg_count = 0;
+            __threadfence_system();
+            __hip_atomic_store(&hs->seq, hs_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
@@ -1075,7 +1094,7 @@ k_num_merge(Work wk,
 // Exclusive prefix sum of row_nnz -> row_ptr (int64), fused with the
 // numeric binning histogram
 // ===========================================================================
-constexpr int kScanBS = 256;
+constexpr int kScanBS = 1024;
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kScanBS * kScanPer;
 
@@ -1096,12 +1115,14 @@ __device__ __forceinline__ unsigned long long scan_word(int flag, int epoch, lon
 
 static __global__ void __launch_bounds__(kScanBS)
 k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile_state, int epoch,
-                int64_t* __restrict__ row_ptr, BinTable bins, DevInfo* info) {
+                int64_t* __restrict__ row_ptr, BinTable bins, DevInfo* info, HostSummary* hs, int seq) {
     __shared__ BlockScanSmem<kScanBS> sm;
     __shared__ int hist[kNB];
     __shared__ int s_tile;
+    __shared__ int s_neg;
     __shared__ long long s_prefix;
     if (threadIdx.x < kNB) hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_neg = 0;
     if (threadIdx.x == 0) s_tile = atomicAdd(&info->scan_ticket, 1);
     __syncthreads();
     const int tile = s_tile;
@@ -1133,14 +1154,38 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
         int wn = neg;
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) wn += __shfl_xor(wn, d);
-        if ((threadIdx.x & 63) == 0 && wn) atomicAdd(&info->neg_count, wn);
+        if ((threadIdx.x & 63) == 0 && wn) atomicAdd(&s_neg, wn);
+    }
+    // the tile's numeric bin histogram (before the tile publishes its state)
+    if (bins.nb > 0) {
+        // a thread's rows usually share one bin: one weighted add then
+        const int b0 = base < m ? bin_of(bins, v[0]) : -1;
+        int nv = 0;
+        bool same = true;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i)
+            if (base + i < m) {
+                ++nv;
+                same = same && bin_of(bins, v[i]) == b0;
+            }
+        if (__ballot(!same) == 0) {
+            wave_hist_add_w(hist, b0, nv);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanPer; ++i)
+                wave_hist_add(hist, base + i < m ? bin_of(bins, v[i]) : -1);
+        }
     }
     long long tot;
-    const long long incl = block_incl_scan<kScanBS>(s, sm, &tot);
+    const long long incl = block_incl_scan<kScanBS>(s, sm, &tot);   // (its barriers complete hist, s_neg)
     if (threadIdx.x < 64) {
-        // wave 0: publish the tile total, then look back over 64 predecessor
-        // states per round trip until an inclusive prefix is found
+        // wave 0: add the tile's bins and overflow count to the global
+        // counters, publish the tile total (the release orders those adds
+        // before it), then look back over 64 predecessor states per round
+        // trip until an inclusive prefix is found
         const int lane = threadIdx.x;
+        if (bins.nb > 0 && lane < kNB && hist[lane]) atomicAdd(&info->num_part[tile % kParts][lane], hist[lane]);
+        if (lane == 0 && s_neg) atomicAdd(&info->neg_count, s_neg);
         if (lane == 0)
             __hip_atomic_store(&tile_state[tile], scan_word(tile == 0 ? kFlagIncl : kFlagAgg, epoch, tot),
                                __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1201,25 +1246,6 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
                 if (base + i < m) row_ptr[base + i] = rp[i];
         }
     }
-    if (bins.nb > 0) {
-        // a thread's rows usually share one bin: one weighted add then
-        const int b0 = base < m ? bin_of(bins, v[0]) : -1;
-        int nv = 0;
-        bool same = true;
-#pragma unroll
-        for (int i = 0; i < kScanPer; ++i)
-            if (base + i < m) {
-                ++nv;
-                same = same && bin_of(bins, v[i]) == b0;
-            }
-        if (__ballot(!same) == 0) {
-            wave_hist_add_w(hist, b0, nv);
-        } else {
-#pragma unroll
-            for (int i = 0; i < kScanPer; ++i)
-                wave_hist_add(hist, base + i < m ? bin_of(bins, v[i]) : -1);
-        }
-    }
     if (m > 0 && base <= m - 1 && m - 1 < base + kScanPer) {
         if (row_ptr) row_ptr[m] = run;     // the thread holding row m-1 closes row_ptr
         info->nnz = run;
@@ -1228,9 +1254,25 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
         if (row_ptr) row_ptr[0] = 0;
         info->nnz = 0;
     }
-    __syncthreads();
-    if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
-        atomicAdd(&info->num_part[tile % kParts][threadIdx.x], hist[threadIdx.x]);
+    // The tile of the last rows has seen every other tile's state (directly
+    // or through an inclusive prefix), so every tile's counters are in: it
+    // publishes the host summary.
+    if (hs && tile == (int)gridDim.x - 1) {
+        if (threadIdx.x < kNB) {
+            int c = 0;
+            if ((int)threadIdx.x <= bins.nb)
+                for (int p = 0; p < kParts; ++p) c += load_coherent(&info->num_part[p][threadIdx.x]);
+            hs->counts[threadIdx.x] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            hs->nnz = s_prefix + tot;
+            hs->err = load_coherent(&info->err);
+            hs->neg_count = load_coherent(&info->neg_count);
+            __threadfence_system();
+            __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 // ===========================================================================

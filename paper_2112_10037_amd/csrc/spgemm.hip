@@ -244,19 +244,20 @@ static msp_status launch_check(const char* what) {
 template <bool BATCH>
 static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
                                     int32_t* rnnz, const RowMap& mp, const int32_t* ufilter = nullptr,
-                                    int umax = 0) {
+                                    int umax = 0, int publish_seq = 0, int publish_nb = 0) {
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
     if (s.kind == Kind::Merge) {
         const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4, BATCH> : (const void*)k_sym_merge<8, BATCH>;
         const int grid = group_grid(h, fn, rows, 256);
+        HostSummary* hs = publish_seq ? h->dsum : nullptr;
         if (s.lanes == 4)
             k_sym_merge<4, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, ufilter, umax, rnnz,
-                                                        info, mp);
+                                                        info, mp, hs, publish_seq, publish_nb);
         else
             k_sym_merge<8, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, ufilter, umax, rnnz,
-                                                        info, mp);
+                                                        info, mp, hs, publish_seq, publish_nb);
         return launch_check("k_sym_merge");
     } else if (s.kind == Kind::Batch) {
 #define X(T, R)                                                                                        \
@@ -432,9 +433,10 @@ Operands operands_of(const msp_csr* A, const msp_csr* B) {
 // plain product: rows listed in perm (or all rows)
 static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
                                   const msp_csr* A, const msp_csr* B, int32_t* rnnz,
-                                  const int32_t* ufilter = nullptr, int umax = 0) {
+                                  const int32_t* ufilter = nullptr, int umax = 0, int publish_seq = 0,
+                                  int publish_nb = 0) {
     return launch_symbolic_t<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), rnnz, RowMap{},
-                                    ufilter, umax);
+                                    ufilter, umax, publish_seq, publish_nb);
 }
 
 static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
@@ -610,11 +612,9 @@ msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_p
     memset(&bt, 0, sizeof(bt));
     if (plan) bt = plan->table;
     k_scan_lookback<<<tiles, kScanBS, 0, h->stream>>>(m, row_nnz, h->tiles.as<unsigned long long>(),
-                                                     h->scan_epoch, row_ptr, bt, h->info.as<DevInfo>());
-    msp_status s2 = launch_check("k_scan_lookback");
-    if (s2 != MSP_OK || !publish_seq) return s2;
-    k_publish<<<1, 64, 0, h->stream>>>(h->info.as<DevInfo>(), 1, bt.nb, h->dsum, publish_seq);
-    return launch_check("k_publish");
+                                                     h->scan_epoch, row_ptr, bt, h->info.as<DevInfo>(),
+                                                     publish_seq ? h->dsum : nullptr, publish_seq);
+    return launch_check("k_scan_lookback");
 }
 
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
@@ -665,17 +665,20 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     const BinPlan sp = symbolic_plan(t, opts && opts->force_spill);
     if ((s = zero_info(h)) != MSP_OK) return s;
     h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
-    const int seq = m > 0 ? ++h->sum_seq : 0;     // the statistics kernel publishes the bin sizes
-    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr, seq)) != MSP_OK) return s;
+    // the bin sizes reach the host through the merge kernel queued next, or
+    // a one-workgroup kernel when there is no merge bin
+    const bool spec = m > 0 && sp.table.nb > 1 && sp.spec[1].kind == Kind::Merge;
+    const int seq = m > 0 ? ++h->sum_seq : 0;
+    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr, spec ? 0 : seq)) != MSP_OK) return s;
     h->prof.end(h->stream);
     // The merge bin (bin 1 when enabled) is queued before the bin counts are
     // read back: it picks its rows by their bound, so the GPU keeps working
     // while the host waits for the counts.
     int done_bin = 0;
     h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
-    if (m > 0 && sp.table.nb > 1 && sp.spec[1].kind == Kind::Merge) {
+    if (spec) {
         if ((s = launch_symbolic(h, sp.spec[1], m, nullptr, A, B, h->rnnz.as<int32_t>(), h->u.as<int32_t>(),
-                                 sp.table.umax[1])) != MSP_OK)
+                                 sp.table.umax[1], seq, sp.table.nb)) != MSP_OK)
             return s;
         done_bin = 1;
     }
