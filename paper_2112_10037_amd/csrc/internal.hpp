@@ -86,6 +86,7 @@ struct msp_handle {
     int lds_per_block = 65536;
     msp_tuning tuning{};
     msp::DevBuf info, u, rnnz, perm, tiles, dslab, gbm, sbm, prod;
+    msp::DevBuf bsum;               // 256-row workgroup totals of the fused symbolic pass
     size_t dslab_cols = 0;          // ncols the dense slabs were zeroed for
     int dslab_count = 0;
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
@@ -127,7 +128,9 @@ msp_status read_info(msp_handle* h);
 msp_status zero_info(msp_handle* h);
 // Wait until the kernel given sequence number `seq` has published its host
 // summary (spinning on pinned memory, checking the stream for errors).
-msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)[kPartStride]);
+// With spec_nb > 0 the summary is a speculative scan's: when it was skipped
+// (nnz = -1) its counts are the symbolic bin sizes.
+msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)[kPartStride], int spec_nb = 0);
 msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                          int64_t* prod_out, float* feat, int32_t* lo_out, int publish_seq = 0);
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,

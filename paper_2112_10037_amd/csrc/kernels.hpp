@@ -923,6 +923,251 @@ k_sym_merge(Work wk,
     if (err) atomicOr(&info->err, kErrProbe);
 }
 
+// Tiles of the single-pass scan: numeric bin counts are kept per
+// partition (tile mod kParts) of kScanTile rows, where the bin scatter
+// looks for them.
+constexpr int kScanBS = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanBS * kScanPer;
+
+// Row statistics fused with the symbolic merge bin, for products whose bin
+// plan starts with a merge bin.  One wave takes 64 consecutive rows.  A row
+// with at most K A entries loads its B-row bounds once: they give its
+// product count, and when the bound u = min(products, ncols) falls in the
+// merge bin (0 < u <= umax) they are the merge's heads, so the row's
+// distinct columns are counted right away.  Rows with more A entries sum
+// their B-row lengths with the whole wave and, in the merge bin, take the
+// hash fallback.  Every row's bound and bin count are recorded as the
+// statistics pass records them; rows of the other bins are left for their
+// own kernels.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
+            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, int32_t* __restrict__ u_out,
+            int32_t* __restrict__ row_nnz, BinTable bins, int umax, DevInfo* info, BinTable nbins,
+            long long* __restrict__ bsum) {
+    __shared__ int hist[kNB];
+    __shared__ int nhist[kNB];
+    __shared__ long long s_sum[4];
+    __shared__ int s_unknown;
+    __shared__ int32_t fb_keys[4][kMergeFT + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < kNB) { hist[threadIdx.x] = 0; nhist[threadIdx.x] = 0; }
+    if (threadIdx.x == 0) s_unknown = 0;
+    __syncthreads();
+    const long long r0 = ((long long)blockIdx.x * 4 + w) * 64;
+    const long long row = r0 + lane;
+    const bool valid = row < m;
+    long long a0 = 0, a1 = 0;
+    if (valid) {
+        a0 = arp[row];
+        a1 = arp[row + 1];
+    }
+    const bool shortrow = valid && a1 - a0 <= K;
+    long long hp[K], he[K];
+    long long prod = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        hp[k] = 0;
+        he[k] = 0;
+        if (shortrow && k < (int)(a1 - a0)) {
+            const long long kk = acol[a0 + k];
+            hp[k] = brp[kk];
+            he[k] = brp[kk + 1];
+            prod += he[k] - hp[k];
+        }
+    }
+    // rows with more than K A entries: the wave sums their B-row lengths
+    uint64_t lr = __ballot(valid && !shortrow);
+    while (lr) {                                       // wave-uniform
+        const int r = __builtin_ctzll(lr);
+        lr &= lr - 1;
+        const long long la0 = __shfl(a0, r), la1 = __shfl(a1, r);
+        long long s = 0;
+        for (long long p = la0 + lane; p < la1; p += 64) {
+            const long long kk = acol[p];
+            s += brp[kk + 1] - brp[kk];
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d);
+        if (lane == r) prod = s;
+    }
+    int bin = -1;
+    bool take = false;
+    long long u = 0;
+    if (valid) {
+        u = prod < ncols ? prod : ncols;
+        u_out[row] = (int32_t)u;
+        if (u == 0) row_nnz[row] = 0;
+        bin = bin_of(bins, u);
+        take = u > 0 && u <= umax;
+    }
+    if (bins.nb > 0) wave_hist_add(hist, bin);
+    int err = 0;
+    int cnt = 0;                                       // the row's count, when counted here
+    if (take && shortrow) {
+        const int len = (int)(a1 - a0);
+        int hk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) hk[k] = k < len && hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+        while (true) {
+            int mn = hk[0];
+#pragma unroll
+            for (int k = 1; k < K; ++k) mn = hk[k] < mn ? hk[k] : mn;
+            if (mn == 0x7fffffff) break;
+            ++cnt;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (hk[k] == mn) {
+                    ++hp[k];
+                    hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                }
+        }
+        row_nnz[row] = cnt;
+    }
+    uint64_t fb = __ballot(take && !shortrow);
+    while (fb) {                                       // wave-uniform
+        const int r = __builtin_ctzll(fb);
+        fb &= fb - 1;
+        const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
+        for (int i = lane; i < kMergeFT; i += 64) fb_keys[w][i] = kEmpty;
+        lds_fence();
+        int c = 0;
+        for (long long p = fa0; p < fa1; ++p) {
+            const long long kk = acol[p];
+            const long long q1 = brp[kk + 1];
+            for (long long q = brp[kk] + lane; q < q1; q += 64)
+                c += hash_insert_key<kMergeFT>(fb_keys[w], bcol[q], &err);
+        }
+        c = group_sum<64>(c);
+        if (lane == r) { row_nnz[row] = c; cnt = c; }
+        lds_fence();
+    }
+    if (err) atomicOr(&info->err, kErrProbe);
+    // Rows of this pass have their final counts: their numeric bins and the
+    // workgroup's total serve the speculative scan (valid when no row of the
+    // whole product was left for another bin).
+    const bool known = !valid || u == 0 || take;
+    if (__ballot(!known) && lane == 0) s_unknown = 1;
+    if (nbins.nb > 0) wave_hist_add(nhist, valid && known ? bin_of(nbins, cnt) : -1);
+    long long ws = known ? cnt : 0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) ws += __shfl_xor(ws, d);
+    if (lane == 0) s_sum[w] = ws;
+    __syncthreads();
+    if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
+        atomicAdd(&info->sym_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
+    if (!s_unknown && nbins.nb > 0 && threadIdx.x < kNB && nhist[threadIdx.x])
+        atomicAdd(&info->num_part[(blockIdx.x / (kScanTile / 256)) % kParts][threadIdx.x], nhist[threadIdx.x]);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+}
+
+// The speculative scan behind k_sym_fused.  When no row was left for a
+// symbolic bin other than the empty and merge bins, every row count is
+// final and the fused pass has stored each 256-row workgroup's total and
+// the numeric bin sizes: a workgroup here adds the totals before its tile
+// and scans its own rows, with no wait on any other workgroup, and the
+// workgroup of the last rows publishes the host summary by itself.
+// Otherwise every workgroup leaves and workgroup 0 publishes the symbolic
+// bin sizes with nnz = -1, so that the host runs the other bins and a full
+// scan.
+constexpr int kWsBS = 1024;
+constexpr int kWsPer = 8;
+constexpr int kWsTile = kWsBS * kWsPer;                // rows per workgroup: 32 fused workgroups
+
+static __global__ void __launch_bounds__(kWsBS)
+k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict__ bsum,
+             int64_t* __restrict__ row_ptr, int spec_nb, DevInfo* info, HostSummary* hs, int seq) {
+    __shared__ BlockScanSmem<kWsBS> sm;
+    __shared__ int s_other;
+    __shared__ int s_counts[kNB];
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        int c = 0;
+        if (t < kNB && t <= spec_nb)
+            for (int p = 0; p < kParts; ++p) c += load_coherent(&info->sym_part[p][t]);
+        const bool other = __ballot(t >= 2 && c > 0) != 0;
+        if (t == 0) s_other = other;
+        if (other && hs && blockIdx.x == 0) {
+            if (t < kNB) hs->counts[t] = c;
+            if (t == 0) {
+                hs->nnz = -1;
+                hs->err = load_coherent(&info->err);
+                hs->neg_count = 0;
+            }
+            __threadfence_system();
+            if (t == 0) __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    __syncthreads();
+    if (s_other) return;
+    const int tile = blockIdx.x;
+    // totals of the fused workgroups before this tile
+    const int nb_before = tile * (kWsTile / 256);
+    long long acc = 0;
+    for (int i = threadIdx.x; i < nb_before; i += kWsBS) acc += bsum[i];
+    long long prefix;
+    block_incl_scan<kWsBS>(acc, sm, &prefix);
+    const long long base = (long long)tile * kWsTile + (long long)threadIdx.x * kWsPer;
+    static_assert(kWsPer == 8, "the vector path loads two int4");
+    int v[kWsPer];
+    const bool full = base + kWsPer <= m;
+    if (full && ((uintptr_t)cnt & 15) == 0) {
+        const int4 q0 = *reinterpret_cast<const int4*>(cnt + base);
+        const int4 q1 = *reinterpret_cast<const int4*>(cnt + base + 4);
+        v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+        v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kWsPer; ++i) v[i] = base + i < m ? cnt[base + i] : 0;
+    }
+    long long s = 0;
+#pragma unroll
+    for (int i = 0; i < kWsPer; ++i) s += v[i];
+    long long tot;
+    const long long incl = block_incl_scan<kWsBS>(s, sm, &tot);
+    long long run = prefix + incl - s;
+    long long rp[kWsPer];
+#pragma unroll
+    for (int i = 0; i < kWsPer; ++i) {
+        rp[i] = run;
+        run += v[i];
+    }
+    if (row_ptr) {
+        if (full && ((uintptr_t)row_ptr & 15) == 0) {
+#pragma unroll
+            for (int i = 0; i < kWsPer; i += 2)
+                *reinterpret_cast<longlong2*>(row_ptr + base + i) = make_longlong2(rp[i], rp[i + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kWsPer; ++i)
+                if (base + i < m) row_ptr[base + i] = rp[i];
+        }
+        if (base <= m - 1 && m - 1 < base + kWsPer) row_ptr[m] = run;
+    }
+    if (tile == (int)gridDim.x - 1) {
+        // the last tile: nnz(C) is its prefix plus its total; the numeric
+        // bin sizes were counted by the fused pass
+        if (threadIdx.x < kNB) {
+            int c = 0;
+            for (int p = 0; p < kParts; ++p) c += load_coherent(&info->num_part[p][threadIdx.x]);
+            s_counts[threadIdx.x] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) info->nnz = prefix + tot;
+        if (hs && threadIdx.x < 64) {
+            if (threadIdx.x < kNB) hs->counts[threadIdx.x] = s_counts[threadIdx.x];
+            if (threadIdx.x == 0) {
+                hs->nnz = prefix + tot;
+                hs->err = load_coherent(&info->err);
+                hs->neg_count = 0;
+            }
+            __threadfence_system();
+            if (threadIdx.x == 0) __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
 // Numeric merge.  A wave takes the longest run of its rows (at most 64)
 // whose outputs fit an LDS staging area of kMergeStage entries; every row's
 // output is merged into its own staging segment (its size is known from the
@@ -1094,9 +1339,6 @@ k_num_merge(Work wk,
 // Exclusive prefix sum of row_nnz -> row_ptr (int64), fused with the
 // numeric binning histogram
 // ===========================================================================
-constexpr int kScanBS = 1024;
-constexpr int kScanPer = 8;
-constexpr int kScanTile = kScanBS * kScanPer;
 
 // Single-pass prefix sum with decoupled look-back (Merrill and Garland,
 // 2016).  Workgroups take tiles in ticket order; each publishes its tile
@@ -1198,7 +1440,7 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
             long long val = 0;                  // before tile 0: an empty inclusive prefix
             if (idx >= 0) {
                 const unsigned long long wd =
-                    __hip_atomic_load(&tile_state[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_load(&tile_state[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 flag = (int)(wd >> 62);
                 ep = (int)((wd >> 46) & 0xffff);
                 val = (long long)(wd & kValMask);
@@ -1220,6 +1462,9 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
             if (first < 64) break;
             p -= 64;
         }
+        // the states read above were published with release stores: this
+        // fence makes the counters added before them visible from here on
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (lane == 0) {
             if (tile > 0)
                 __hip_atomic_store(&tile_state[tile], scan_word(kFlagIncl, epoch, prefix + tot), __ATOMIC_RELEASE,

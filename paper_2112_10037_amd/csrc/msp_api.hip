@@ -123,6 +123,13 @@ extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
     h->tuning = default_tuning();
     msp_status s = h->info.ensure(sizeof(DevInfo));
     if (s != MSP_OK) { delete h; return s; }
+    // the first call forwards the error bits it finds here: start from zero,
+    // not from whatever the reused allocation held
+    if ((e = hipMemset(h->info.ptr, 0, sizeof(DevInfo))) != hipSuccess) {
+        h->info.release();
+        delete h;
+        return hip_fail(e, "hipMemset(info)");
+    }
     if ((e = hipHostMalloc((void**)&h->hinfo, sizeof(DevInfo), hipHostMallocDefault)) != hipSuccess) {
         h->info.release();
         delete h;
@@ -158,7 +165,8 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     if (!h) return MSP_OK;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->dslab, &h->gbm, &h->sbm, &h->prod})
+    for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->dslab, &h->gbm, &h->sbm, &h->prod,
+                      &h->bsum})
         b->release();
     release_extra(h);
     h->prof.release();

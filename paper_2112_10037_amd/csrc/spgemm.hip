@@ -459,7 +459,7 @@ msp_status zero_info(msp_handle* h) {
 // work complete a little before that write is visible.  After completion
 // the wait keeps polling for a while, then takes the same figures from a
 // copy of the device info block.
-msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)[kPartStride]) {
+msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)[kPartStride], int spec_nb) {
     auto seen = [&] { return __atomic_load_n(&h->hsum->seq, __ATOMIC_ACQUIRE) == seq; };
     bool ok = false;
     for (unsigned long long it = 1; !ok; ++it) {
@@ -487,6 +487,18 @@ msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)
         h->hsum->err = d->err;
         h->hsum->neg_count = d->neg_count;
         sum_parts(pp, h->hsum->counts);
+        if (spec_nb > 0) {
+            // the speculative scan left when a symbolic bin other than the
+            // empty and merge bins has rows
+            int sym[kNB];
+            sum_parts(d->sym_part, sym);
+            bool other = false;
+            for (int b = 2; b <= spec_nb && b < kNB; ++b) other = other || sym[b] > 0;
+            if (other) {
+                h->hsum->nnz = -1;
+                for (int b = 0; b < kNB; ++b) h->hsum->counts[b] = b <= spec_nb ? sym[b] : 0;
+            }
+        }
         return MSP_OK;
     }
     if (h->prof.on) h->prof.collect();
@@ -656,18 +668,68 @@ msp_status device_error(int err) {
     return MSP_OK;
 }
 
-// symbolic phase up to row_nnz (shared by msp_spgemm and msp_spgemm_symbolic)
+// symbolic phase up to row_nnz (shared by msp_spgemm and msp_spgemm_symbolic).
+// When the plan starts with a merge bin, the statistics pass and that bin
+// run as one kernel with a speculative scan queued behind it (into
+// `row_ptr`, with the numeric histogram of `np`); if every row was counted
+// there, the scan's summary (nnz and numeric bin sizes) is in h->hsum and
+// *scanned is set.
 static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr* B, const msp_opts* opts,
-                                 const msp_tuning& t) {
+                                 const msp_tuning& t, int64_t* row_ptr, const BinPlan* np, bool* scanned) {
     const int m = (int)A->nrows;
     msp_status s;
+    *scanned = false;
     if ((s = h->rnnz.ensure((size_t)std::max(m, 1) * 4)) != MSP_OK) return s;
     const BinPlan sp = symbolic_plan(t, opts && opts->force_spill);
     if ((s = zero_info(h)) != MSP_OK) return s;
+    const bool merge_first = m > 0 && sp.table.nb > 1 && sp.spec[1].kind == Kind::Merge;
+    if (merge_first) {
+        const int grid = (m + 255) / 256;
+        if ((s = h->u.ensure((size_t)m * 4)) != MSP_OK) return s;
+        if ((s = h->bsum.ensure((size_t)grid * 8)) != MSP_OK) return s;
+        DevInfo* info = h->info.as<DevInfo>();
+        BinTable nt;
+        memset(&nt, 0, sizeof(nt));
+        if (np) nt = np->table;
+        h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
+        if (sp.spec[1].lanes == 4)
+            k_sym_fused<4><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
+                                                       h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,
+                                                       sp.table.umax[1], info, nt, h->bsum.as<long long>());
+        else
+            k_sym_fused<8><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
+                                                       h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,
+                                                       sp.table.umax[1], info, nt, h->bsum.as<long long>());
+        if ((s = launch_check("k_sym_fused")) != MSP_OK) return s;
+        h->prof.end(h->stream);
+        h->prof.begin(MSP_PHASE_SCAN, h->stream);
+        const int seq = ++h->sum_seq;
+        const int tiles = (m + kWsTile - 1) / kWsTile;
+        k_scan_fused<<<tiles, kWsBS, 0, h->stream>>>(m, h->rnnz.as<int32_t>(), h->bsum.as<long long>(), row_ptr,
+                                                     sp.table.nb, info, h->dsum, seq);
+        if ((s = launch_check("k_scan_fused")) != MSP_OK) return s;
+        h->prof.end(h->stream);
+        if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part, sp.table.nb)) != MSP_OK) return s;
+        if ((s = device_error(h->hsum->err)) != MSP_OK) return s;
+        if (h->hsum->nnz >= 0) {
+            *scanned = true;
+            return MSP_OK;
+        }
+        // other symbolic bins have rows: run them (the merge bin is done);
+        // the full scan counts the numeric bins afresh
+        int counts[kNB];
+        for (int b = 0; b < kNB; ++b) counts[b] = h->hsum->counts[b];
+        k_zero_words<<<1, 256, 0, h->stream>>>(&info->num_part[0][0], kParts * kPartStride);
+        if ((s = launch_check("k_zero_words")) != MSP_OK) return s;
+        h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
+        s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), 1);
+        h->prof.end(h->stream);
+        return s;
+    }
     h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
     // the bin sizes reach the host through the merge kernel queued next, or
     // a one-workgroup kernel when there is no merge bin
-    const bool spec = m > 0 && sp.table.nb > 1 && sp.spec[1].kind == Kind::Merge;
+    const bool spec = merge_first;
     const int seq = m > 0 ? ++h->sum_seq : 0;
     if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr, spec ? 0 : seq)) != MSP_OK) return s;
     h->prof.end(h->stream);
@@ -730,14 +792,17 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
         return st;
     };
 
-    if ((s = symbolic_phase(h, A, B, opts, t)) != MSP_OK) return cleanup(s);
     const BinPlan np = numeric_plan(t, opts && opts->force_spill);
-    h->prof.begin(MSP_PHASE_SCAN, h->stream);
-    const int seq = ++h->sum_seq;             // the scan publishes nnz(C) and the numeric bin sizes
-    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), C->row_ptr, &np, seq)) != MSP_OK) return cleanup(s);
-    h->prof.end(h->stream);
-    if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part)) != MSP_OK) return cleanup(s);
-    if ((s = device_error(h->hsum->err)) != MSP_OK) return cleanup(s);
+    bool scanned = false;
+    if ((s = symbolic_phase(h, A, B, opts, t, C->row_ptr, &np, &scanned)) != MSP_OK) return cleanup(s);
+    if (!scanned) {
+        h->prof.begin(MSP_PHASE_SCAN, h->stream);
+        const int seq = ++h->sum_seq;         // the scan publishes nnz(C) and the numeric bin sizes
+        if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), C->row_ptr, &np, seq)) != MSP_OK) return cleanup(s);
+        h->prof.end(h->stream);
+        if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part)) != MSP_OK) return cleanup(s);
+        if ((s = device_error(h->hsum->err)) != MSP_OK) return cleanup(s);
+    }
     const long long nnz = h->hsum->nnz;
     int counts[kNB];
     for (int b = 0; b < kNB; ++b) counts[b] = h->hsum->counts[b];
@@ -784,17 +849,19 @@ extern "C" msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const msp_tuning t = effective_tuning(h, opts);
     if (opts && opts->validate && (s = validate_inputs(h, A, B)) != MSP_OK) return s;
-    if ((s = symbolic_phase(h, A, B, opts, t)) != MSP_OK) return s;
+    bool scanned = false;     // total through the scan (no row_ptr output)
+    if ((s = symbolic_phase(h, A, B, opts, t, nullptr, nullptr, &scanned)) != MSP_OK) return s;
     const int m = (int)A->nrows;
     if (m > 0) {
         e = hipMemcpyAsync(row_nnz, h->rnnz.ptr, (size_t)m * 4, hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(row_nnz)");
     }
-    // total through the scan (no row_ptr output)
-    const int seq = ++h->sum_seq;
-    if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), nullptr, nullptr, seq)) != MSP_OK) return s;
-    if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part)) != MSP_OK) return s;
-    if ((s = device_error(h->hsum->err)) != MSP_OK) return s;
+    if (!scanned) {
+        const int seq = ++h->sum_seq;
+        if ((s = run_scan(h, m, h->rnnz.as<int32_t>(), nullptr, nullptr, seq)) != MSP_OK) return s;
+        if ((s = wait_summary(h, seq, true, h->info.as<DevInfo>()->num_part)) != MSP_OK) return s;
+        if ((s = device_error(h->hsum->err)) != MSP_OK) return s;
+    }
     if (nnz_total) *nnz_total = h->hsum->nnz;
     return MSP_OK;
 }

@@ -318,3 +318,36 @@ def test_pass_summaries_reach_the_host():
         assert hh.summary_fallbacks() == 0
     finally:
         hh.close()
+
+
+def test_fresh_handles_start_clean():
+    """A handle's device info block may reuse memory a destroyed handle
+    filled with row counts; a new handle's first call must still report no
+    error left over from an earlier call."""
+    A = gen.laplacian_2d(150)
+    dA = to_dev(A)
+    ref = oracle.spgemm(A, A)
+    for _ in range(6):
+        hh = binding.Handle(0)
+        try:
+            C = hh.spgemm(dA, dA)
+            host = C.to_host()
+            assert np.array_equal(host.row_ptr, ref[0]) and np.array_equal(host.col, ref[1])
+            hh.sync()
+        finally:
+            hh.close()
+
+
+def test_merge_first_products_over_many_scan_tiles(h):
+    """Every row's bound falls in the merge bin (at most 5 x 6 products), so
+    the fused statistics and merge pass counts all rows and the scan behind
+    it needs no look-back; 60,000 rows span eight scan tiles, and the row
+    counts range over several values per tile."""
+    m = 60000
+    rng = np.random.default_rng(91)
+    A = gen.erdos_renyi(m, m, rng.integers(0, 6, m), seed=92)
+    B = gen.erdos_renyi(m, m, rng.integers(1, 7, m), seed=93)
+    check_full(h, A, B)
+    rn, tot = h.symbolic(to_dev(A), to_dev(B))
+    ref = oracle.row_nnz(A, B)
+    assert np.array_equal(rn.cpu().numpy(), ref) and tot == ref.sum()
