@@ -940,7 +940,7 @@ constexpr int kScanTile = kScanBS * kScanPer;
 // hash fallback.  Every row's bound and bin count are recorded as the
 // statistics pass records them; rows of the other bins are left for their
 // own kernels.
-template <int K>
+template <int K, typename IT>
 __global__ void __launch_bounds__(256)
 k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, int32_t* __restrict__ u_out,
@@ -950,10 +950,11 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     __shared__ int nhist[kNB];
     __shared__ long long s_sum[4];
     __shared__ int s_unknown;
+    __shared__ int s_na;
     __shared__ int32_t fb_keys[4][kMergeFT + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < kNB) { hist[threadIdx.x] = 0; nhist[threadIdx.x] = 0; }
-    if (threadIdx.x == 0) s_unknown = 0;
+    if (threadIdx.x == 0) { s_unknown = 0; s_na = 0; }
     __syncthreads();
     const long long r0 = ((long long)blockIdx.x * 4 + w) * 64;
     const long long row = r0 + lane;
@@ -964,19 +965,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
         a1 = arp[row + 1];
     }
     const bool shortrow = valid && a1 - a0 <= K;
-    long long hp[K], he[K];
     long long prod = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        hp[k] = 0;
-        he[k] = 0;
-        if (shortrow && k < (int)(a1 - a0)) {
-            const long long kk = acol[a0 + k];
-            hp[k] = brp[kk];
-            he[k] = brp[kk + 1];
-            prod += he[k] - hp[k];
-        }
-    }
     // rows with more than K A entries: the wave sums their B-row lengths
     uint64_t lr = __ballot(valid && !shortrow);
     while (lr) {                                       // wave-uniform
@@ -991,6 +980,20 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d);
         if (lane == r) prod = s;
+    }
+    // short rows: B-row bounds, which are also the merge's heads; IT is
+    // int32 when nnz(B) fits
+    IT hp[K], he[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        hp[k] = 0;
+        he[k] = 0;
+        if (shortrow && k < (int)(a1 - a0)) {
+            const long long kk = acol[a0 + k];
+            hp[k] = (IT)brp[kk];
+            he[k] = (IT)brp[kk + 1];
+            prod += (long long)(he[k] - hp[k]);
+        }
     }
     int bin = -1;
     bool take = false;
@@ -1049,6 +1052,10 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     // whole product was left for another bin).
     const bool known = !valid || u == 0 || take;
     if (__ballot(!known) && lane == 0) s_unknown = 1;
+    int na_max = take && shortrow ? (int)(a1 - a0) : 0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) na_max = max(na_max, __shfl_xor(na_max, d));
+    if (lane == 0 && na_max > 0) atomicMax(&s_na, na_max);
     if (nbins.nb > 0) wave_hist_add(nhist, valid && known ? bin_of(nbins, cnt) : -1);
     long long ws = known ? cnt : 0;
 #pragma unroll
@@ -1057,6 +1064,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     __syncthreads();
     if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
         atomicAdd(&info->sym_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x == 64 && s_na > 0) atomicMax(&info->sym_part[blockIdx.x % kParts][kPartMergeNA], s_na);
     if (!s_unknown && nbins.nb > 0 && threadIdx.x < kNB && nhist[threadIdx.x])
         atomicAdd(&info->num_part[(blockIdx.x / (kScanTile / 256)) % kParts][threadIdx.x], nhist[threadIdx.x]);
     if (threadIdx.x == 0) bsum[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
@@ -1080,7 +1088,7 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
              int64_t* __restrict__ row_ptr, int spec_nb, DevInfo* info, HostSummary* hs, int seq) {
     __shared__ BlockScanSmem<kWsBS> sm;
     __shared__ int s_other;
-    __shared__ int s_counts[kNB];
+    __shared__ int s_counts[kNB + 1];
     if (threadIdx.x < 64) {
         const int t = threadIdx.x;
         int c = 0;
@@ -1153,11 +1161,17 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
             for (int p = 0; p < kParts; ++p) c += load_coherent(&info->num_part[p][threadIdx.x]);
             s_counts[threadIdx.x] = c;
         }
+        if (threadIdx.x == kNB) {
+            int mx = 0;
+            for (int p = 0; p < kParts; ++p) mx = max(mx, load_coherent(&info->sym_part[p][kPartMergeNA]));
+            s_counts[kNB] = mx;
+        }
         __syncthreads();
         if (threadIdx.x == 0) info->nnz = prefix + tot;
         if (hs && threadIdx.x < 64) {
             if (threadIdx.x < kNB) hs->counts[threadIdx.x] = s_counts[threadIdx.x];
             if (threadIdx.x == 0) {
+                hs->merge_na = s_counts[kNB];
                 hs->nnz = prefix + tot;
                 hs->err = load_coherent(&info->err);
                 hs->neg_count = 0;

@@ -327,6 +327,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
         return launch_check("k_num_merge");                                                              \
     }
         if (s.lanes == 4) { if (small) MSP_MERGE(4, int) else MSP_MERGE(4, long long) }
+        else if (s.lanes == 6) { if (small) MSP_MERGE(6, int) else MSP_MERGE(6, long long) }
         else { if (small) MSP_MERGE(8, int) else MSP_MERGE(8, long long) }
 #undef MSP_MERGE
     } else if (s.kind == Kind::Batch) {
@@ -487,6 +488,8 @@ msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)
         h->hsum->err = d->err;
         h->hsum->neg_count = d->neg_count;
         sum_parts(pp, h->hsum->counts);
+        h->hsum->merge_na = 0;
+        for (int p = 0; p < kParts; ++p) h->hsum->merge_na = std::max(h->hsum->merge_na, d->sym_part[p][kPartMergeNA]);
         if (spec_nb > 0) {
             // the speculative scan left when a symbolic bin other than the
             // empty and merge bins has rows
@@ -692,14 +695,14 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
         memset(&nt, 0, sizeof(nt));
         if (np) nt = np->table;
         h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
-        if (sp.spec[1].lanes == 4)
-            k_sym_fused<4><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
-                                                       h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,
-                                                       sp.table.umax[1], info, nt, h->bsum.as<long long>());
-        else
-            k_sym_fused<8><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
-                                                       h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,
-                                                       sp.table.umax[1], info, nt, h->bsum.as<long long>());
+        const bool small = B->nnz < INT32_MAX;     // 32-bit positions into B
+#define MSP_FUSED(KK, IT)                                                                                 \
+    k_sym_fused<KK, IT><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,   \
+                                                     h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,  \
+                                                     sp.table.umax[1], info, nt, h->bsum.as<long long>())
+        if (sp.spec[1].lanes == 4) { if (small) MSP_FUSED(4, int); else MSP_FUSED(4, long long); }
+        else { if (small) MSP_FUSED(8, int); else MSP_FUSED(8, long long); }
+#undef MSP_FUSED
         if ((s = launch_check("k_sym_fused")) != MSP_OK) return s;
         h->prof.end(h->stream);
         h->prof.begin(MSP_PHASE_SCAN, h->stream);
@@ -792,9 +795,17 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
         return st;
     };
 
-    const BinPlan np = numeric_plan(t, opts && opts->force_spill);
+    BinPlan np = numeric_plan(t, opts && opts->force_spill);
     bool scanned = false;
     if ((s = symbolic_phase(h, A, B, opts, t, C->row_ptr, &np, &scanned)) != MSP_OK) return cleanup(s);
+    if (scanned && np.table.nb > 1 && np.spec[1].kind == Kind::Merge && np.spec[1].lanes == 8) {
+        // every merge row of this product was seen by the fused pass: the
+        // numeric merge needs no more heads than its longest A row (fewer
+        // heads, fewer registers, more waves in flight)
+        const int na = h->hsum->merge_na;
+        if (na <= 4) np.spec[1].lanes = 4;
+        else if (na <= 6) np.spec[1].lanes = 6;
+    }
     if (!scanned) {
         h->prof.begin(MSP_PHASE_SCAN, h->stream);
         const int seq = ++h->sum_seq;         // the scan publishes nnz(C) and the numeric bin sizes

@@ -48,8 +48,14 @@ struct HostSummary {
     int err;
     int neg_count;
     int counts[kNB];                      // rows per bin, summed over partitions
+    int merge_na;                         // most A entries of a row the fused pass merged
     int seq;
 };
+
+// Spare slot of each symbolic partition row: the largest A-row length among
+// the rows the fused statistics and merge pass counted with the merge.
+constexpr int kPartMergeNA = kPartStride - 1;
+static_assert(kNB < kPartMergeNA, "partition rows hold the bins and one spare slot");
 
 // Bin b (1 <= b < nb) holds rows with umax[b-1] < u <= umax[b]; bin 0 holds
 // u == 0; bin nb holds everything above umax[nb-1] (the global path).
