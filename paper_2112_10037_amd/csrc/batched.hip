@@ -107,6 +107,7 @@ struct BatchStage {
     int sym_rows[kNB] = {}, num_rows[kNB] = {}; // plan-time bin sizes (grid sizes)
     bool sym_merge_all = false;                 // merge bin runs over all rows, filtering by bound
     bool sym_scatter = false;                   // other symbolic bins need the row lists
+    bool sym_fused = false;                     // replays: statistics and merge bin in one kernel
     int num_single = -1;                        // numeric bin that takes all rows in order
     DevBuf crp, cv, wsym, wnum;                 // row pointers, col+val arena, work items
     long long nnz = 0, cap = 0;
@@ -221,10 +222,29 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
         if ((s = S.wnum.ensure((kNB + 1) * 2 * 4)) != MSP_OK) return s;
         const int tiles = std::max(1, (M + kScanTile - 1) / kScanTile);
         if ((s = h->tiles.ensure((size_t)tiles * 8)) != MSP_OK) return s;
+        if ((s = h->bsum.ensure((size_t)std::max((M + 255) / 256, 1) * 8)) != MSP_OK) return s;
     }
     if ((s = zero_info(h)) != MSP_OK) return s;
+    // Replays of a stage whose rows all fell in the merge bin at plan time
+    // run the statistics and that bin as one kernel, with the scan that
+    // needs no look-back behind it; a replay with rows in another bin is
+    // caught by k_bin_work like any other change of structure.
+    const bool fused = !eager && S.sym_fused && M > 0;
+    if (fused) {
+        const bool small = S.op.bnnz < INT32_MAX;
+        const int grid = (M + 255) / 256;
+#define MSP_FUSED(KK, IT)                                                                                  \
+    k_sym_fused<KK, IT, true><<<grid, 256, 0, st>>>(M, S.op.ncols, S.op.arp, S.op.acol, S.op.brp, S.op.bcol, \
+                                                    h->u.as<int32_t>(), h->rnnz.as<int32_t>(), S.sp.table,   \
+                                                    S.sp.table.umax[1], info, S.np.table,                    \
+                                                    h->bsum.as<long long>(), S.mp)
+        if (S.sp.spec[1].lanes == 4) { if (small) MSP_FUSED(4, int); else MSP_FUSED(4, long long); }
+        else { if (small) MSP_FUSED(8, int); else MSP_FUSED(8, long long); }
+#undef MSP_FUSED
+        if ((s = launch_ok("k_sym_fused")) != MSP_OK) return s;
+    }
     // 1. row statistics and the symbolic bin histogram
-    if (M > 0) {
+    if (M > 0 && !fused) {
         k_row_stats<false, true><<<(M + 255) / 256, 256, 0, st>>>(M, S.op.ncols, S.op.arp, S.op.acol, S.op.brp,
                                                                   S.op.bcol, h->u.as<int32_t>(), nullptr,
                                                                   h->rnnz.as<int32_t>(), S.sp.table, info, nullptr,
@@ -243,13 +263,15 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
             if (bn == 1 && S.sp.spec[1].kind == Kind::Merge) S.sym_merge_all = true;
             else S.sym_scatter = true;
         }
+        S.sym_fused = S.sym_merge_all && !S.sym_scatter &&
+                      (S.sp.spec[1].lanes == 4 || S.sp.spec[1].lanes == 8);
     }
     k_bin_work<<<1, 64, 0, st>>>(&info->sym_part[0][0], S.sp.table.nb, S.sym_planned, S.M, nullptr, 0,
                                  S.wsym.as<int>(), flag);
     if ((s = launch_ok("k_bin_work")) != MSP_OK) return s;
     // 2. symbolic pass
     const int* wsym = S.wsym.as<int>();
-    if (S.sym_merge_all)
+    if (S.sym_merge_all && !fused)
         if ((s = launch_symbolic_bin<true>(h, S.sp.spec[1], Work{nullptr, M, wsym + 2 * kNB}, M, S.op,
                                            h->rnnz.as<int32_t>(), S.mp, h->u.as<int32_t>(), S.sp.table.umax[1])) !=
             MSP_OK)
@@ -268,11 +290,18 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
         }
     }
     // 3. prefix sum (fresh tile states every replay) with the numeric histogram
-    const int tiles = std::max(1, (M + kScanTile - 1) / kScanTile);
-    k_zero_words<<<(2 * tiles + 255) / 256, 256, 0, st>>>((int*)h->tiles.ptr, 2 * tiles);
-    k_scan_lookback<<<tiles, kScanBS, 0, st>>>(M, h->rnnz.as<int32_t>(), h->tiles.as<unsigned long long>(), 1,
-                                               S.crp.as<int64_t>(), S.np.table, info, nullptr, 0);
-    if ((s = launch_ok("k_scan_lookback")) != MSP_OK) return s;
+    if (fused) {
+        k_scan_fused<<<(M + kWsTile - 1) / kWsTile, kWsBS, 0, st>>>(M, h->rnnz.as<int32_t>(),
+                                                                   h->bsum.as<long long>(), S.crp.as<int64_t>(),
+                                                                   S.sp.table.nb, info, nullptr, 0);
+        if ((s = launch_ok("k_scan_fused")) != MSP_OK) return s;
+    } else {
+        const int tiles = std::max(1, (M + kScanTile - 1) / kScanTile);
+        k_zero_words<<<(2 * tiles + 255) / 256, 256, 0, st>>>((int*)h->tiles.ptr, 2 * tiles);
+        k_scan_lookback<<<tiles, kScanBS, 0, st>>>(M, h->rnnz.as<int32_t>(), h->tiles.as<unsigned long long>(), 1,
+                                                   S.crp.as<int64_t>(), S.np.table, info, nullptr, 0);
+        if ((s = launch_ok("k_scan_lookback")) != MSP_OK) return s;
+    }
     if (eager) {
         if ((s = read_info(h)) != MSP_OK) return s;
         if ((s = device_error(h->hinfo->err)) != MSP_OK) return s;

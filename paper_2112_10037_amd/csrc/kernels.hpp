@@ -940,12 +940,12 @@ constexpr int kScanTile = kScanBS * kScanPer;
 // hash fallback.  Every row's bound and bin count are recorded as the
 // statistics pass records them; rows of the other bins are left for their
 // own kernels.
-template <int K, typename IT>
+template <int K, typename IT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, int32_t* __restrict__ u_out,
             int32_t* __restrict__ row_nnz, BinTable bins, int umax, DevInfo* info, BinTable nbins,
-            long long* __restrict__ bsum) {
+            long long* __restrict__ bsum, RowMap mp = RowMap{}) {
     __shared__ int hist[kNB];
     __shared__ int nhist[kNB];
     __shared__ long long s_sum[4];
@@ -959,10 +959,15 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     const long long r0 = ((long long)blockIdx.x * 4 + w) * 64;
     const long long row = r0 + lane;
     const bool valid = row < m;
-    long long a0 = 0, a1 = 0;
+    long long a0 = 0, a1 = 0, bo = 0, nc = ncols;
     if (valid) {
         a0 = arp[row];
         a1 = arp[row + 1];
+        if constexpr (BATCH) {                         // the row's problem: B-row offset and width
+            const int pb = map_prob(mp, row);
+            bo = mp.boff[pb];
+            nc = mp.ncols[pb];
+        }
     }
     const bool shortrow = valid && a1 - a0 <= K;
     long long prod = 0;
@@ -971,10 +976,10 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     while (lr) {                                       // wave-uniform
         const int r = __builtin_ctzll(lr);
         lr &= lr - 1;
-        const long long la0 = __shfl(a0, r), la1 = __shfl(a1, r);
+        const long long la0 = __shfl(a0, r), la1 = __shfl(a1, r), lbo = __shfl(bo, r);
         long long s = 0;
         for (long long p = la0 + lane; p < la1; p += 64) {
-            const long long kk = acol[p];
+            const long long kk = acol[p] + lbo;
             s += brp[kk + 1] - brp[kk];
         }
 #pragma unroll
@@ -989,7 +994,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
         hp[k] = 0;
         he[k] = 0;
         if (shortrow && k < (int)(a1 - a0)) {
-            const long long kk = acol[a0 + k];
+            const long long kk = acol[a0 + k] + bo;
             hp[k] = (IT)brp[kk];
             he[k] = (IT)brp[kk + 1];
             prod += (long long)(he[k] - hp[k]);
@@ -999,7 +1004,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     bool take = false;
     long long u = 0;
     if (valid) {
-        u = prod < ncols ? prod : ncols;
+        u = prod < nc ? prod : nc;
         u_out[row] = (int32_t)u;
         if (u == 0) row_nnz[row] = 0;
         bin = bin_of(bins, u);
@@ -1032,12 +1037,12 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     while (fb) {                                       // wave-uniform
         const int r = __builtin_ctzll(fb);
         fb &= fb - 1;
-        const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r);
+        const long long fa0 = __shfl(a0, r), fa1 = __shfl(a1, r), fbo = __shfl(bo, r);
         for (int i = lane; i < kMergeFT; i += 64) fb_keys[w][i] = kEmpty;
         lds_fence();
         int c = 0;
         for (long long p = fa0; p < fa1; ++p) {
-            const long long kk = acol[p];
+            const long long kk = acol[p] + fbo;
             const long long q1 = brp[kk + 1];
             for (long long q = brp[kk] + lane; q < q1; q += 64)
                 c += hash_insert_key<kMergeFT>(fb_keys[w], bcol[q], &err);
