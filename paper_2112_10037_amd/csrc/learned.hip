@@ -81,7 +81,8 @@ k_mlp_predict(long long n, const float* __restrict__ feats, const float* __restr
 // products (cap 0) are in no numeric bin: their count is set to 0 here.
 __global__ void __launch_bounds__(256, 4)
 k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ hi, const int32_t* __restrict__ lo,
-           const float* __restrict__ params, float delta, int32_t* __restrict__ cap, int32_t* __restrict__ cnt) {
+           const float* __restrict__ params, float delta, int32_t* __restrict__ cap, int32_t* __restrict__ cnt,
+           BinTable nt) {
     __shared__ __align__(16) float w[kNParam + 3];
     for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
     __syncthreads();
@@ -95,6 +96,10 @@ k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ h
             const double est = exp2((double)(16.f * y + delta));
             c = est < (double)h ? (int)ceil(est) : h;    // NaN or overflow: the upper bound
             c = c < l ? l : c;
+            // the exact bound costs nothing more when it keeps the row in
+            // the same numeric bin (same kernel, same accumulator): only
+            // unused padding, which the compaction never reads
+            if (nt.nb > 0 && bin_of(nt, c) == bin_of(nt, h)) c = h;
         }
         cap[r] = c;
         if (c == 0) cnt[r] = 0;
@@ -644,17 +649,17 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     if ((s = run_row_stats(h, A, B, none, nullptr, x->feat.as<float>(), x->lo.as<int32_t>())) != MSP_OK)
         return cleanup(s);
     h->prof.end(h->stream);
+    const BinPlan np = numeric_plan(t, opts && opts->force_spill);
     h->prof.begin(MSP_PHASE_PREDICT, h->stream);
     if (m > 0) {
         const int blocks = (m + 255) / 256;
         k_capacity<<<blocks, 256, 0, h->stream>>>(m, x->feat.as<float>(), h->u.as<int32_t>(), x->lo.as<int32_t>(),
                                                   p->params.as<float>(), p->delta, x->cap.as<int32_t>(),
-                                                  x->cnt.as<int32_t>());
+                                                  x->cnt.as<int32_t>(), np.table);
         if ((s = launch_check2("k_capacity")) != MSP_OK) return cleanup(s);
     }
     h->prof.end(h->stream);
     // 3. padded row pointers and bins by capacity
-    const BinPlan np = numeric_plan(t, opts && opts->force_spill);
     h->prof.begin(MSP_PHASE_SCAN, h->stream);
     if ((s = run_scan(h, m, x->cap.as<int32_t>(), x->rp_pad.as<int64_t>(), &np)) != MSP_OK) return cleanup(s);
     h->prof.end(h->stream);
