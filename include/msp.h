@@ -16,7 +16,9 @@
  * ---------------------------------------
  *  - Pointers inside msp_csr / msp_csr_out are DEVICE pointers on the
  *    handle's device.  Scalar sizes are host values.
- *  - row_ptr is int64 with nrows + 1 entries (row_ptr[0] == 0); col is int32
+ *  - row_ptr is int64 with nrows + 1 entries; its values index col and val
+ *    directly and never exceed nnz, the length of those arrays (row_ptr[0]
+ *    may be > 0, e.g. for one matrix's rows inside a larger array); col is int32
  *    (so ncols <= 2^31 - 1); values are FP32 or FP64, the same type for A, B
  *    and C.
  *  - Inputs must be canonical CSR: row_ptr non-decreasing, columns strictly

@@ -231,7 +231,7 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
     // caught by k_bin_work like any other change of structure.
     const bool fused = !eager && S.sym_fused && M > 0;
     if (fused) {
-        const bool small = S.op.bnnz < INT32_MAX;
+        const bool small = narrow_symbolic(S.op);
         const int grid = (M + 255) / 256;
 #define MSP_FUSED(KK, IT)                                                                                  \
     k_sym_fused<KK, IT, true><<<grid, 256, 0, st>>>(M, S.op.ncols, S.op.arp, S.op.acol, S.op.brp, S.op.bcol, \
@@ -454,7 +454,7 @@ extern "C" msp_status msp_batch_create(msp_handle* h, const msp_batch_csr* R, co
     // stage 0: A_p P_p
     BatchStage& S0 = b->st[0];
     S0.op = Operands{A->row_ptr, A->col, A->val, P->row_ptr, P->col, P->val, maxc, P->nnz, A->row_start[A->nprob],
-                     A->dtype};
+                     A->dtype, A->nnz, P->row_start[P->nprob]};
     if ((s = build_map(S0, b->nprob, A->row_start, P->row_start, P->ncols, in->stream)) != MSP_OK) return bail(s);
     S0.sp = symbolic_plan(t, false);
     S0.np = numeric_plan(t, false);
@@ -480,7 +480,8 @@ extern "C" msp_status msp_batch_create(msp_handle* h, const msp_batch_csr* R, co
     if (R) {
         BatchStage& S1 = b->st[1];
         S1.op = Operands{R->row_ptr, R->col, R->val, S0.crp.as<int64_t>(), S0.cv.as<int32_t>(),
-                         (char*)S0.cv.ptr + S0.voff, maxc, S0.cap, R->row_start[R->nprob], A->dtype};
+                         (char*)S0.cv.ptr + S0.voff, maxc, S0.cap, R->row_start[R->nprob], A->dtype, R->nnz,
+                         A->row_start[A->nprob]};
         if ((s = run_stage(b, 1, true)) != MSP_OK) return bail(s);
     }
     if ((e = hipStreamSynchronize(in->stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));

@@ -47,10 +47,19 @@ struct Operands {
     const int32_t* bcol;
     const void* bval;
     long long ncols;       // columns of B
-    long long bnnz;        // entries of B
+    long long bnnz;        // entries of B (length of its col and val arrays)
     long long m;           // rows of A
     msp_dtype dtype;
+    long long annz;        // entries of A (length of its col and val arrays)
+    long long brows;       // rows of B
 };
+
+// The fused symbolic kernel may gather with 32-bit byte offsets when they
+// fit: 4-byte columns of A and B under 2^30 entries, 8-byte row pointers of
+// B under 2^29.
+inline bool narrow_symbolic(const Operands& op) {
+    return op.annz < (1LL << 30) && op.bnnz < (1LL << 30) && op.brows + 1 < (1LL << 29);
+}
 
 struct ExtraState;                  // learned / batched state (other units)
 

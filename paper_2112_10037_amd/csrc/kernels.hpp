@@ -39,6 +39,20 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t key) {
 template <typename VT>
 __device__ __forceinline__ double to_f64(VT v) { return (double)v; }
 
+// Gather p[i].  With a 32-bit index type the caller guarantees that every
+// byte offset i * sizeof(T) fits in 32 bits: the load then takes the array
+// base from scalar registers and a 32-bit offset per lane, which also
+// spares the registers of a 64-bit address per lane.
+template <typename IT, typename T>
+__device__ __forceinline__ T gat(const T* __restrict__ p, IT i) {
+    if constexpr (sizeof(IT) == 4) {
+        const uint32_t off = (uint32_t)i * (uint32_t)sizeof(T);
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (uint64_t)off);
+    } else {
+        return p[i];
+    }
+}
+
 // Loads that must observe device-scope atomics performed by other lanes of
 // the same workgroup (global dense accumulator): bypass the non-coherent L1.
 __device__ __forceinline__ double load_coherent(const double* p) {
@@ -987,16 +1001,16 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
         if (lane == r) prod = s;
     }
     // short rows: B-row bounds, which are also the merge's heads; IT is
-    // int32 when nnz(B) fits
+    // 32-bit when the byte offsets into acol, brp and bcol fit 32 bits
     IT hp[K], he[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         hp[k] = 0;
         he[k] = 0;
         if (shortrow && k < (int)(a1 - a0)) {
-            const long long kk = acol[a0 + k] + bo;
-            hp[k] = (IT)brp[kk];
-            he[k] = (IT)brp[kk + 1];
+            const IT kk = (IT)(gat(acol, (IT)(a0 + k)) + bo);
+            hp[k] = (IT)gat(brp, kk);
+            he[k] = (IT)gat(brp, (IT)(kk + 1));
             prod += (long long)(he[k] - hp[k]);
         }
     }
@@ -1017,7 +1031,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
         const int len = (int)(a1 - a0);
         int hk[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) hk[k] = k < len && hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+        for (int k = 0; k < K; ++k) hk[k] = k < len && hp[k] < he[k] ? gat(bcol, hp[k]) : 0x7fffffff;
         while (true) {
             int mn = hk[0];
 #pragma unroll
@@ -1028,7 +1042,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
             for (int k = 0; k < K; ++k)
                 if (hk[k] == mn) {
                     ++hp[k];
-                    hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                    hk[k] = hp[k] < he[k] ? gat(bcol, hp[k]) : 0x7fffffff;
                 }
         }
         row_nnz[row] = cnt;

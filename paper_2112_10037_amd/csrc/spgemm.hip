@@ -428,6 +428,8 @@ Operands operands_of(const msp_csr* A, const msp_csr* B) {
     op.bnnz = B->nnz;
     op.m = A->nrows;
     op.dtype = A->dtype;
+    op.annz = A->nnz;
+    op.brows = B->nrows;
     return op;
 }
 
@@ -695,7 +697,7 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
         memset(&nt, 0, sizeof(nt));
         if (np) nt = np->table;
         h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
-        const bool small = B->nnz < INT32_MAX;     // 32-bit positions into B
+        const bool small = narrow_symbolic(operands_of(A, B));   // 32-bit positions and offsets
 #define MSP_FUSED(KK, IT)                                                                                 \
     k_sym_fused<KK, IT><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,   \
                                                      h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,  \
