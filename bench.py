@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors
 # read off a 1 GiB copy kernel), valid for the kernel sources whose hash is
 # given; any other source state reports null.
-MEASURED_TRAFFIC = {"sources_sha256": "7233a8d7a24a47042d0f85407b328daab3e9ad64e3a48cd00c5eee47a2afd209",
-                    "bytes": 266304852}
+MEASURED_TRAFFIC = {"sources_sha256": "ff75f51f31e92ca8f96c39241c811c4978df2011b60c6c46e11e83e520855dd4",
+                    "bytes": 270770539}
 KERNEL_SOURCES = ["kernels.hpp", "types.hpp", "spgemm.hip"]
 
 
@@ -81,20 +81,51 @@ def csr_bytes(nrows: int, nnz: int, vb: int = 8) -> int:
 
 
 def cpu_baseline(A, products: int, budget_s: float) -> dict:
+    """The oracle on the host cores: two thirds of the budget on all
+    threads, one third on one thread."""
     import oracle
     cores = oracle.num_threads()
-    t0 = time.perf_counter()
-    runs = 0
-    while True:
-        oracle.spgemm(A, A)
-        runs += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+
+    def rate(seconds):
+        t0 = time.perf_counter()
+        runs = 0
+        while True:
+            oracle.spgemm(A, A)
+            runs += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return runs, el
+
+    runs, el = rate(budget_s * 2 / 3)
+    oracle.set_threads(1)
+    try:
+        runs1, el1 = rate(budget_s / 3)
+    finally:
+        oracle.set_threads(cores)
     return {"value": round(2.0 * products * runs / el / 1e9, 3), "unit": "GFLOP/s",
             "cores": cores, "kind": "oracle",
             "sample": f"{runs} full products of the main workload in {el:.1f} s "
-                      f"(C oracle, FP64 dense accumulator, OpenMP over rows)"}
+                      f"(C oracle, FP64 dense accumulator, OpenMP over rows)",
+            "single_thread": {"value": round(2.0 * products * runs1 / el1 / 1e9, 3), "unit": "GFLOP/s",
+                              "sample": f"{runs1} full products in {el1:.1f} s on one thread"}}
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """GB/s of a plain device-to-device copy (bytes read + written), timed
+    with HIP events: the achievable HBM rate the roofline is also read against."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * nbytes / s / 1e9
 
 
 # ---------------------------------------------------------------------------
@@ -326,6 +357,13 @@ def main():
     if args.tuning:
         h.set_tuning(tuple(int(x) for x in args.tuning.split(",")))
 
+    # the cold first call (workspace allocations, first launches), reported apart
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter()
+    C = h.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t_cold) * 1e3
+    del C
     for _ in range(args.warmup):
         C = h.spgemm(dA, dA)
     h.sync()
@@ -364,6 +402,7 @@ def main():
     if (args.workload == "laplacian2d_1024" and MEASURED_TRAFFIC["sources_sha256"]
             and MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_hash()):
         traffic = MEASURED_TRAFFIC["bytes"]
+    copy_gbs = copy_bandwidth()
 
     out = {
         "metric": "SpGEMM GFLOP/s (2x products/s)",
@@ -383,7 +422,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "numeric pass (k_num_merge)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes": alg, "avg_launch_ms": round(num_avg_s * 1e3, 5)},
+                     "algorithmic_bytes": alg, "avg_launch_ms": round(num_avg_s * 1e3, 5),
+                     "traffic_gbs": round(traffic / num_avg_s / 1e9, 1) if traffic else None,
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "first_call_ms": round(first_ms, 3),
         "phases_ms_per_step_profiled": {k: round(v[0] / nph, 5) for k, v in prof_all.items() if v[1]},
         "hbm_gbs_whole_step_algorithmic": round(alg / (el / args.steps) / 1e9, 1),
         "summary_fallbacks": h.summary_fallbacks(),
