@@ -73,3 +73,35 @@ def autotune_cached(h: binding.Handle, A, P, R, path: str, candidates=CANDIDATES
         with open(path, "w") as f:
             json.dump(cache, f, indent=1)
     return best, {"cached": False, "median_ms": times}
+
+
+def main(argv=None):
+    """Build the Galerkin batch R (A P) of `--problems` problems (sides
+    ~ U{16..64}, seed 5), plan it once and time `--replays` graph replays."""
+    import argparse
+    import time
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--problems", type=int, default=512)
+    ap.add_argument("--replays", type=int, default=6)
+    ap.add_argument("--tuning", default="1,0,4096,128,8",
+                    help="hash_scale,group_scale,spill_nnz,block_rows,merge_k")
+    a = ap.parse_args(argv)
+    tuning = tuple(int(x) for x in a.tuning.split(","))
+    sides = gen.galerkin_sizes(a.problems, 16, 64, seed=5)
+    h = binding.Handle(0)
+    pA, pP, pR = galerkin_batch(sides)
+    plan = binding.Batch(h, pA, pP, pR, tuning=tuning)
+    print("plan", plan.info(), flush=True)
+    for i in range(a.replays):
+        t0 = time.perf_counter()
+        plan.execute()
+        plan.sync()
+        torch.cuda.synchronize()
+        print(f"replay {i}: {(time.perf_counter() - t0) * 1e3:.3f} ms", flush=True)
+    plan.close()
+    h.close()
+
+
+if __name__ == "__main__":
+    main()
