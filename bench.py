@@ -419,7 +419,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "rows": A.nrows, "nnz_a": A.nnz, "products": products,
                    "nnz_c": nnz_c, "path": "plain two-phase", "tuning": list(h.get_tuning())},
-        "roofline": {"bound": "hbm", "kernel": "numeric pass (k_num_merge)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "numeric pass (k_num_merge)" if args.workload == "laplacian2d_1024"
+                     else "numeric pass (every bin kernel)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes": alg, "avg_launch_ms": round(num_avg_s * 1e3, 5),
