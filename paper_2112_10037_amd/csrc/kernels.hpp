@@ -1263,13 +1263,19 @@ k_num_merge(Work wk,
             // heads: column hk at position hp (end he) in B, scale ha; the
             // head's value is loaded when it is consumed.  IT is int32 when
             // nnz(B) fits.
+            // With PRE (K = 8, where the registers are there) a head's value
+            // is loaded with its column, so a step waits on no value load;
+            // otherwise it is loaded when the head is consumed.
+            constexpr bool PRE = K >= 8;
             int hk[K];
             double ha[K];
+            double hv[PRE ? K : 1];
             IT hp[K], he[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 hk[k] = 0x7fffffff;
                 ha[k] = 0.0;
+                if constexpr (PRE) hv[k] = 0.0;
                 hp[k] = 0;
                 he[k] = 0;
                 if (k < (int)(a1 - a0)) {
@@ -1277,7 +1283,10 @@ k_num_merge(Work wk,
                     ha[k] = to_f64(aval[a0 + k]);
                     hp[k] = (IT)brp[kk];
                     he[k] = (IT)brp[kk + 1];
-                    if (hp[k] < he[k]) hk[k] = bcol[hp[k]];
+                    if (hp[k] < he[k]) {
+                        hk[k] = bcol[hp[k]];
+                        if constexpr (PRE) hv[k] = to_f64(bval[hp[k]]);
+                    }
                 }
             }
             const int so = (int)(incl - nn);
@@ -1291,9 +1300,20 @@ k_num_merge(Work wk,
 #pragma unroll
                 for (int k = 0; k < K; ++k)
                     if (hk[k] == m) {
-                        acc += ha[k] * to_f64(bval[hp[k]]);
-                        ++hp[k];
-                        hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                        if constexpr (PRE) {
+                            acc += ha[k] * hv[k];
+                            ++hp[k];
+                            if (hp[k] < he[k]) {
+                                hk[k] = bcol[hp[k]];
+                                hv[k] = to_f64(bval[hp[k]]);
+                            } else {
+                                hk[k] = 0x7fffffff;
+                            }
+                        } else {
+                            acc += ha[k] * to_f64(bval[hp[k]]);
+                            ++hp[k];
+                            hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                        }
                     }
                 if (t < nn) { st_k[w][so + t] = m; st_v[w][so + t] = acc; }
                 ++t;

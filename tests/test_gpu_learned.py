@@ -187,3 +187,25 @@ def test_bad_batch_index_is_an_error(h):
     loss, _ = p.grad(_dev(x), _dev(t), _dev(idx))
     assert np.isfinite(loss)
     p.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_learned_forced_spill_uses_global_bin(h, dtype):
+    """Every row in the global bin (force_spill): the capacity-mode numeric
+    pass runs in the rank-indexed global kernel; with the same-bin rule each
+    capacity is the row's bound, so no row overflows, and the result equals
+    the oracle's."""
+    params = gen.mlp_init(37).astype(np.float32)
+    pred = binding.Predictor(h, params)
+    pred.set(None, 0.25)
+    for M in (gen.rmat(11, 16 << 11, seed=51, dtype=dtype),
+              gen.erdos_renyi(1500, 1700, np.random.default_rng(4).integers(1, 20, 1500), seed=52, dtype=dtype)):
+        dM = to_dev(M)
+        B = M if M.nrows == M.ncols else gen.erdos_renyi(M.ncols, 900, 5, seed=53, dtype=dtype)
+        dB = dM if B is M else to_dev(B)
+        C, st = h.spgemm_learned(pred, dM, dB, force_spill=True)
+        got = C.to_host()
+        ref = oracle.spgemm(M, B)
+        oracle.compare(got.row_ptr, got.col, got.val, ref, TOL[np.dtype(dtype)])
+        assert st["overflow_rows"] == 0 and st["nnz"] == got.nnz
+    pred.close()
