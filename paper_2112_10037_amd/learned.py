@@ -63,3 +63,63 @@ def linear_fit_params(feats_host: np.ndarray, targets_host: np.ndarray) -> np.nd
     p[4736 + 0] = b                         # W3[0]
     p[4800] = a                             # b3
     return p
+
+
+def main(argv=None):
+    """Train the predictor on training members of the mixed suite (by default
+    the full-size members of the held-out member's family), then time that
+    held-out member's one-pass product against the plain product and print
+    the learned-path statistics."""
+    import argparse
+    import time
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--member", type=int, default=23, help="held-out suite index (index = 3 mod 4)")
+    ap.add_argument("--train-members", type=int, default=12, help="first N training members")
+    ap.add_argument("--any-family", action="store_true", help="train on members of every family")
+    ap.add_argument("--scale", type=int, default=0, help="training members built 2^-scale smaller")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args(argv)
+    suite = gen.learned_suite()
+    test = [m for m in suite if m.index == a.member and m.held_out]
+    if not test:
+        raise SystemExit(f"member {a.member} is not a held-out member")
+    h = binding.Handle(0)
+    prods = []
+    pool = [m for m in suite if not m.held_out and (a.any_family or m.family == test[0].family)]
+    for m in pool[:a.train_members]:
+        d = binding.DeviceCSR.from_host(m.build(scale_down=a.scale), "cuda:0")
+        prods.append((d, d))
+    feats, targets = training_set(h, prods)
+    del prods
+    pred, losses, delta = train(h, feats, targets, steps=a.steps, seed=0)
+    print(f"trained on {int(feats.shape[0])} rows: loss {losses[0]:.4f} -> {float(np.mean(losses[-20:])):.5f}, "
+          f"delta {delta:.4f}", flush=True)
+    del feats, targets
+    M = test[0].build()
+    dM = binding.DeviceCSR.from_host(M, "cuda:0")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(a.reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    t_plain = timed(lambda: h.spgemm(dM, dM))
+    t_learn = timed(lambda: h.spgemm_learned(pred, dM, dM))
+    _, st = h.spgemm_learned(pred, dM, dM)
+    print(f"member {a.member} ({test[0].family}, {M.nrows} rows, nnz(A) {M.nnz}): plain {t_plain:.3f} ms, "
+          f"learned {t_learn:.3f} ms ({t_plain / t_learn:.3f}x); overflow rows {st['overflow_rows']}, "
+          f"sum cap / nnz {st['sum_cap'] / max(st['nnz'], 1):.3f}", flush=True)
+    pred.close()
+    h.close()
+
+
+if __name__ == "__main__":
+    main()
