@@ -2094,10 +2094,10 @@ k_validate(long long nrows, long long ncols, long long nnz, const int64_t* __res
            const int32_t* __restrict__ col, DevInfo* info) {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
+    // row_ptr values index col directly: a view of rows inside a larger
+    // array starts above 0 and may end below nnz
     const long long a = rp[r], b = rp[r + 1];
-    if (r == 0 && a != 0) { atomicOr(&info->err, kErrRange); return; }
-    if (b < a || b > nnz) { atomicOr(&info->err, kErrRange); return; }
-    if (r == nrows - 1 && b != nnz) { atomicOr(&info->err, kErrRange); return; }
+    if (a < 0 || b < a || b > nnz) { atomicOr(&info->err, kErrRange); return; }
     int prev = -1;
     for (long long p = a; p < b; ++p) {
         const int c = col[p];

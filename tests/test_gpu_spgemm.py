@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2112_10037_amd import binding, gen
 
-from gpu_util import check_full, check_rows, run, to_dev
+from gpu_util import TOL, check_full, check_rows, run, to_dev
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -351,3 +351,23 @@ def test_merge_first_products_over_many_scan_tiles(h):
     rn, tot = h.symbolic(to_dev(A), to_dev(B))
     ref = oracle.row_nnz(A, B)
     assert np.array_equal(rn.cpu().numpy(), ref) and tot == ref.sum()
+
+
+def test_validation_accepts_views(h):
+    """A problem's view of a packed batch (row_ptr starting above 0 and
+    ending below nnz) passes validation and multiplies like the standalone
+    matrix; a negative row pointer is rejected."""
+    mats = [gen.erdos_renyi(60, 60, 5, seed=61), gen.erdos_renyi(70, 60, 3, seed=62),
+            gen.erdos_renyi(60, 60, 4, seed=63)]
+    pk = binding.PackedBatch.from_host(mats)
+    B = gen.erdos_renyi(60, 50, 4, seed=64)
+    view = pk.view(1)
+    C = h.spgemm(view, to_dev(B), validate=True)
+    ref = oracle.spgemm(mats[1], B)
+    host = C.to_host()
+    oracle.compare(host.row_ptr, host.col, host.val, ref, TOL[np.dtype(np.float64)])
+    bad = binding.DeviceCSR(view.nrows, view.ncols, view.row_ptr.clone(), view.col, view.val)
+    bad.row_ptr[0] = -1
+    with pytest.raises(binding.MspError) as e:
+        h.spgemm(bad, to_dev(B), validate=True)
+    assert e.value.name == "MSP_ERR_INVALID_ARG"
