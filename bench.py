@@ -354,7 +354,9 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="hash_scale,group_scale,spill_nnz,block_rows,merge_k (default: library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration)")
+                    help="also run a plain 1 GiB device copy (counter calibration); implies --no-vendor")
+    ap.add_argument("--no-vendor", action="store_true",
+                    help="skip the same product through torch.sparse.mm (hipSPARSE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: there is no multi-GPU path in this library "
@@ -428,7 +430,8 @@ def main():
             and MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_hash()):
         traffic = MEASURED_TRAFFIC["bytes"]
     copy_gbs = copy_bandwidth()
-    vendor = vendor_spgemm(dA, products, nnz_c)
+    # (not in counter runs: the library's copies would mix with the calibration copy)
+    vendor = None if (args.no_vendor or args.calibrate_copy) else vendor_spgemm(dA, products, nnz_c)
 
     out = {
         "metric": "SpGEMM GFLOP/s (2x products/s)",

@@ -843,26 +843,7 @@ k_sym_merge(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             const int32_t* __restrict__ ufilter, int umax,
-            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp,
-            HostSummary* hs = nullptr, int hs_seq = 0, int hs_nb = 0) {
-    // Queued right after the statistics pass, this kernel also publishes
-    // that pass's bin sizes to the host (wave 0 of workgroup 0).
-    if (hs && blockIdx.x == 0 && threadIdx.x < 64) {
-        const int t = threadIdx.x;
-        if (t < kNB) {
-            int c = 0;
-            if (t <= hs_nb)
-                for (int p = 0; p < kParts; ++p) c += info->sym_part[p][t];
-            hs->counts[t] = c;
-        }
-        if (t == 0) {
-            hs->nnz = 0;
-            hs->err = info->err;
-            hs->neg_count = 0;
-            __threadfence_system();
-            __hip_atomic_store(&hs->seq, hs_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
@@ -1090,6 +1071,7 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
         atomicAdd(&info->sym_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 64 && s_na > 0) atomicMax(&info->sym_part[blockIdx.x % kParts][kPartMergeNA], s_na);
+    if (threadIdx.x == 128 && s_unknown) atomicOr(&info->fused_other, 1);
     if (!s_unknown && nbins.nb > 0 && threadIdx.x < kNB && nhist[threadIdx.x])
         atomicAdd(&info->num_part[(blockIdx.x / (kScanTile / 256)) % kParts][threadIdx.x], nhist[threadIdx.x]);
     if (threadIdx.x == 0) bsum[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
@@ -1115,12 +1097,14 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
     __shared__ int s_other;
     __shared__ int s_counts[kNB + 1];
     if (threadIdx.x < 64) {
+        // one flag raised by the fused pass's workgroups that left rows for
+        // other bins; only workgroup 0 then sums the bin sizes for the host
         const int t = threadIdx.x;
-        int c = 0;
-        if (t < kNB && t <= spec_nb)
-            for (int p = 0; p < kParts; ++p) c += load_coherent(&info->sym_part[p][t]);
-        const bool other = __ballot(t >= 2 && c > 0) != 0;
+        const bool other = load_coherent(&info->fused_other) != 0;
         if (t == 0) s_other = other;
+        int c = 0;
+        if (other && hs && blockIdx.x == 0 && t < kNB && t <= spec_nb)
+            for (int p = 0; p < kParts; ++p) c += load_coherent(&info->sym_part[p][t]);
         if (other && hs && blockIdx.x == 0) {
             if (t < kNB) hs->counts[t] = c;
             if (t == 0) {

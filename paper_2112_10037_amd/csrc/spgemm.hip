@@ -255,20 +255,19 @@ static msp_status launch_check(const char* what) {
 template <bool BATCH>
 static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, int rows, const Operands& op,
                                     int32_t* rnnz, const RowMap& mp, const int32_t* ufilter = nullptr,
-                                    int umax = 0, int publish_seq = 0, int publish_nb = 0) {
+                                    int umax = 0) {
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
     if (s.kind == Kind::Merge) {
         const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4, BATCH> : (const void*)k_sym_merge<8, BATCH>;
         const int grid = group_grid(h, fn, rows, 256);
-        HostSummary* hs = publish_seq ? h->dsum : nullptr;
         if (s.lanes == 4)
             k_sym_merge<4, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, ufilter, umax, rnnz,
-                                                        info, mp, hs, publish_seq, publish_nb);
+                                                        info, mp);
         else
             k_sym_merge<8, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, ufilter, umax, rnnz,
-                                                        info, mp, hs, publish_seq, publish_nb);
+                                                        info, mp);
         return launch_check("k_sym_merge");
     } else if (s.kind == Kind::Batch) {
 #define X(T, R)                                                                                        \
@@ -455,11 +454,8 @@ Operands operands_of(const msp_csr* A, const msp_csr* B) {
 
 // plain product: rows listed in perm (or all rows)
 static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
-                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz,
-                                  const int32_t* ufilter = nullptr, int umax = 0, int publish_seq = 0,
-                                  int publish_nb = 0) {
-    return launch_symbolic_t<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), rnnz, RowMap{},
-                                    ufilter, umax, publish_seq, publish_nb);
+                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz) {
+    return launch_symbolic_t<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), rnnz, RowMap{});
 }
 
 static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
@@ -513,12 +509,11 @@ msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)
         h->hsum->merge_na = 0;
         for (int p = 0; p < kParts; ++p) h->hsum->merge_na = std::max(h->hsum->merge_na, d->sym_part[p][kPartMergeNA]);
         if (spec_nb > 0) {
-            // the speculative scan left when a symbolic bin other than the
-            // empty and merge bins has rows
+            // the speculative scan left when the fused pass left rows for a
+            // symbolic bin other than the empty and merge bins
             int sym[kNB];
             sum_parts(d->sym_part, sym);
-            bool other = false;
-            for (int b = 2; b <= spec_nb && b < kNB; ++b) other = other || sym[b] > 0;
+            const bool other = d->fused_other != 0;
             if (other) {
                 h->hsum->nnz = -1;
                 for (int b = 0; b < kNB; ++b) h->hsum->counts[b] = b <= spec_nb ? sym[b] : 0;
@@ -751,24 +746,13 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
         h->prof.end(h->stream);
         return s;
     }
+    // no merge bin (or no rows): the statistics pass, its bin sizes
+    // (published to the host by a one-workgroup kernel), then the bins
     h->prof.begin(MSP_PHASE_ROW_STATS, h->stream);
-    // the bin sizes reach the host through the merge kernel queued next, or
-    // a one-workgroup kernel when there is no merge bin
-    const bool spec = merge_first;
     const int seq = m > 0 ? ++h->sum_seq : 0;
-    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr, spec ? 0 : seq)) != MSP_OK) return s;
+    if ((s = run_row_stats(h, A, B, sp, nullptr, nullptr, nullptr, seq)) != MSP_OK) return s;
     h->prof.end(h->stream);
-    // The merge bin (bin 1 when enabled) is queued before the bin counts are
-    // read back: it picks its rows by their bound, so the GPU keeps working
-    // while the host waits for the counts.
-    int done_bin = 0;
     h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
-    if (spec) {
-        if ((s = launch_symbolic(h, sp.spec[1], m, nullptr, A, B, h->rnnz.as<int32_t>(), h->u.as<int32_t>(),
-                                 sp.table.umax[1], seq, sp.table.nb)) != MSP_OK)
-            return s;
-        done_bin = 1;
-    }
     int counts[kNB] = {};
     if (m > 0) {
         if ((s = wait_summary(h, seq, false, h->info.as<DevInfo>()->sym_part)) != MSP_OK) return s;
@@ -777,7 +761,7 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     } else if ((s = take_pending_error(h)) != MSP_OK) {
         return s;
     }
-    s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), done_bin);
+    s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), 0);
     h->prof.end(h->stream);
     return s;
 }

@@ -34,7 +34,8 @@ struct DevInfo {
     int err;                              // error bits of the current call
     int scan_ticket;                      // tile tickets of the single-pass scan
     int neg_count;                        // scan inputs < 0 (rows that overflowed)
-    int pad[27];
+    int fused_other;                      // the fused symbolic pass left rows for other bins
+    int pad[26];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
