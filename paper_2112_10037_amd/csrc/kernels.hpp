@@ -1086,45 +1086,42 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
 // Otherwise every workgroup leaves and workgroup 0 publishes the symbolic
 // bin sizes with nnz = -1, so that the host runs the other bins and a full
 // scan.
-constexpr int kWsBS = 1024;
+constexpr int kWsBS = 512;
 constexpr int kWsPer = 8;
-constexpr int kWsTile = kWsBS * kWsPer;                // rows per workgroup: 32 fused workgroups
+constexpr int kWsTile = kWsBS * kWsPer;                // rows per workgroup: 16 fused workgroups
+constexpr int kWsWaves = kWsBS / kWave;
+static_assert(kParts * kPartStride == 2 * kWsBS, "the last tile loads the partition counters two per thread");
+static_assert(kPartStride == 32 && kWave == 64, "a wave holds four partition rows");
 
 static __global__ void __launch_bounds__(kWsBS)
 k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict__ bsum,
              int64_t* __restrict__ row_ptr, int spec_nb, DevInfo* info, HostSummary* hs, int seq) {
-    __shared__ BlockScanSmem<kWsBS> sm;
-    __shared__ int s_other;
-    __shared__ int s_counts[kNB + 1];
-    if (threadIdx.x < 64) {
-        // one flag raised by the fused pass's workgroups that left rows for
-        // other bins; only workgroup 0 then sums the bin sizes for the host
-        const int t = threadIdx.x;
-        const bool other = load_coherent(&info->fused_other) != 0;
-        if (t == 0) s_other = other;
-        int c = 0;
-        if (other && hs && blockIdx.x == 0 && t < kNB && t <= spec_nb)
-            for (int p = 0; p < kParts; ++p) c += load_coherent(&info->sym_part[p][t]);
-        if (other && hs && blockIdx.x == 0) {
-            if (t < kNB) hs->counts[t] = c;
-            if (t == 0) {
-                hs->nnz = -1;
-                hs->err = load_coherent(&info->err);
-                hs->neg_count = 0;
-            }
-            __threadfence_system();
-            if (t == 0) __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
-    __syncthreads();
-    if (s_other) return;
+    __shared__ long long s_pre[kWsWaves], s_own[kWsWaves];
+    __shared__ int s_cnt[kWsWaves][kPartStride];
+    __shared__ int s_na;
     const int tile = blockIdx.x;
-    // totals of the fused workgroups before this tile
-    const int nb_before = tile * (kWsTile / 256);
-    long long acc = 0;
-    for (int i = threadIdx.x; i < nb_before; i += kWsBS) acc += bsum[i];
-    long long prefix;
-    block_incl_scan<kWsBS>(acc, sm, &prefix);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const bool last = tile == (int)gridDim.x - 1;
+    // Every load is issued before the first wait: the flag, the totals of
+    // the fused workgroups before this tile (pairs: their count is a
+    // multiple of 16), this tile's row counts and, in the last tile, the
+    // partitioned numeric bin counters.
+    const bool other = load_coherent(&info->fused_other) != 0;
+    const long long npair = (long long)tile * (kWsTile / 256) / 2;
+    const longlong2* bs2 = reinterpret_cast<const longlong2*>(bsum);
+    long long acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    long long i = threadIdx.x;
+    for (; i + 3 * kWsBS < npair; i += 4 * kWsBS) {
+        const longlong2 q0 = bs2[i], q1 = bs2[i + kWsBS], q2 = bs2[i + 2 * kWsBS], q3 = bs2[i + 3 * kWsBS];
+        acc0 += q0.x + q0.y;
+        acc1 += q1.x + q1.y;
+        acc2 += q2.x + q2.y;
+        acc3 += q3.x + q3.y;
+    }
+    for (; i < npair; i += kWsBS) {
+        const longlong2 q = bs2[i];
+        acc0 += q.x + q.y;
+    }
     const long long base = (long long)tile * kWsTile + (long long)threadIdx.x * kWsPer;
     static_assert(kWsPer == 8, "the vector path loads two int4");
     int v[kWsPer];
@@ -1136,52 +1133,97 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
         v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
     } else {
 #pragma unroll
-        for (int i = 0; i < kWsPer; ++i) v[i] = base + i < m ? cnt[base + i] : 0;
+        for (int j = 0; j < kWsPer; ++j) v[j] = base + j < m ? cnt[base + j] : 0;
     }
+    int2 np2 = make_int2(0, 0);
+    int na = 0;
+    if (last) {
+        np2 = reinterpret_cast<const int2*>(&info->num_part[0][0])[threadIdx.x];
+        if (threadIdx.x < kParts) na = info->sym_part[threadIdx.x][kPartMergeNA];
+    }
+    if (other) {
+        // one flag raised by the fused pass's workgroups that left rows for
+        // other bins; workgroup 0 sums the symbolic bin sizes for the host
+        if (hs && tile == 0 && threadIdx.x < 64) {
+            const int t = threadIdx.x;
+            int c = 0;
+            if (t < kNB && t <= spec_nb)
+                for (int p = 0; p < kParts; ++p) c += load_coherent(&info->sym_part[p][t]);
+            if (t < kNB) hs->counts[t] = c;
+            if (t == 0) {
+                hs->nnz = -1;
+                hs->err = load_coherent(&info->err);
+                hs->neg_count = 0;
+            }
+            __threadfence_system();
+            if (t == 0) __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        return;                                         // uniform: the flag is fixed during this kernel
+    }
+    // one workgroup pass: the sum of the totals before the tile and the
+    // exclusive scan of the tile's rows
+    long long pre = (acc0 + acc1) + (acc2 + acc3);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) pre += __shfl_xor(pre, d);
     long long s = 0;
 #pragma unroll
-    for (int i = 0; i < kWsPer; ++i) s += v[i];
-    long long tot;
-    const long long incl = block_incl_scan<kWsBS>(s, sm, &tot);
-    long long run = prefix + incl - s;
+    for (int j = 0; j < kWsPer; ++j) s += v[j];
+    const long long incl = group_incl_scan<kWave>(s, lane);
+    if (lane == kWave - 1) { s_pre[w] = pre; s_own[w] = incl; }
+    if (last) {
+        // lanes 16q..16q+15 of a wave hold partition 4w+q, two bins a lane
+        int c0 = np2.x, c1 = np2.y;
+        c0 += __shfl_xor(c0, 16); c1 += __shfl_xor(c1, 16);
+        c0 += __shfl_xor(c0, 32); c1 += __shfl_xor(c1, 32);
+        if (lane < 16) { s_cnt[w][2 * lane] = c0; s_cnt[w][2 * lane + 1] = c1; }
+        if (w == 0) {
+#pragma unroll
+            for (int d = 16; d > 0; d >>= 1) na = max(na, __shfl_xor(na, d));
+            if (lane == 0) s_na = na;
+        }
+    }
+    __syncthreads();
+    long long prefix = 0, before = 0, tot = 0;
+#pragma unroll
+    for (int j = 0; j < kWsWaves; ++j) {
+        prefix += s_pre[j];
+        const long long t = s_own[j];
+        if (j < w) before += t;
+        tot += t;
+    }
+    long long run = prefix + before + incl - s;
     long long rp[kWsPer];
 #pragma unroll
-    for (int i = 0; i < kWsPer; ++i) {
-        rp[i] = run;
-        run += v[i];
+    for (int j = 0; j < kWsPer; ++j) {
+        rp[j] = run;
+        run += v[j];
     }
     if (row_ptr) {
         if (full && ((uintptr_t)row_ptr & 15) == 0) {
 #pragma unroll
-            for (int i = 0; i < kWsPer; i += 2)
-                *reinterpret_cast<longlong2*>(row_ptr + base + i) = make_longlong2(rp[i], rp[i + 1]);
+            for (int j = 0; j < kWsPer; j += 2)
+                *reinterpret_cast<longlong2*>(row_ptr + base + j) = make_longlong2(rp[j], rp[j + 1]);
         } else {
 #pragma unroll
-            for (int i = 0; i < kWsPer; ++i)
-                if (base + i < m) row_ptr[base + i] = rp[i];
+            for (int j = 0; j < kWsPer; ++j)
+                if (base + j < m) row_ptr[base + j] = rp[j];
         }
         if (base <= m - 1 && m - 1 < base + kWsPer) row_ptr[m] = run;
     }
-    if (tile == (int)gridDim.x - 1) {
+    if (last && threadIdx.x < 64) {
         // the last tile: nnz(C) is its prefix plus its total; the numeric
         // bin sizes were counted by the fused pass
-        if (threadIdx.x < kNB) {
-            int c = 0;
-            for (int p = 0; p < kParts; ++p) c += load_coherent(&info->num_part[p][threadIdx.x]);
-            s_counts[threadIdx.x] = c;
-        }
-        if (threadIdx.x == kNB) {
-            int mx = 0;
-            for (int p = 0; p < kParts; ++p) mx = max(mx, load_coherent(&info->sym_part[p][kPartMergeNA]));
-            s_counts[kNB] = mx;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) info->nnz = prefix + tot;
-        if (hs && threadIdx.x < 64) {
-            if (threadIdx.x < kNB) hs->counts[threadIdx.x] = s_counts[threadIdx.x];
+        const long long nnz = prefix + tot;
+        int c = 0;
+        if (threadIdx.x < kNB)
+#pragma unroll
+            for (int j = 0; j < kWsWaves; ++j) c += s_cnt[j][threadIdx.x];
+        if (threadIdx.x == 0) info->nnz = nnz;
+        if (hs) {
+            if (threadIdx.x < kNB) hs->counts[threadIdx.x] = c;
             if (threadIdx.x == 0) {
-                hs->merge_na = s_counts[kNB];
-                hs->nnz = prefix + tot;
+                hs->merge_na = s_na;
+                hs->nnz = nnz;
                 hs->err = load_coherent(&info->err);
                 hs->neg_count = 0;
             }
