@@ -1238,7 +1238,13 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
 // output is merged into its own staging segment (its size is known from the
 // symbolic pass) and the whole batch is then copied to C with coalesced
 // stores, so each cache line of C is written once and completely.
-constexpr int kMergeStage = 512;
+// 704 outputs (12 B each) per wave: with the fallback tables a workgroup
+// holds about 40 KB of LDS, four per compute unit, and a wave takes about 54
+// rows of 13 outputs at once.  Measured on the 2D Laplacian product, the
+// numeric pass takes 97-99 us at 704, 108 us at 512 (five workgroups per
+// compute unit, 39 rows a wave), 116 us at 440 and 149 us at 1000 (two
+// workgroups per compute unit).
+constexpr int kMergeStage = 704;
 
 template <int K, typename VT, typename IT, bool BATCH = false>
 __global__ void __launch_bounds__(256)

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <unordered_map>
 
 #include "internal.hpp"
@@ -226,16 +227,21 @@ msp_status configure_kernels(msp_handle* h) {
 // resident (occupancy from the kernel's registers and LDS), a multiple of 8
 // for the XCD-aware order, and no more than the rows need.
 static int group_grid(msp_handle* h, const void* fn, int rows, int rows_per_block) {
+    // shared by every handle, and handles may be used from several threads
+    static std::mutex occ_mutex;
     static std::unordered_map<const void*, int> occ_cache;
     int occ = 0;
-    auto it = occ_cache.find(fn);
-    if (it != occ_cache.end()) {
-        occ = it->second;
-    } else {
+    {
+        std::lock_guard<std::mutex> lock(occ_mutex);
+        auto it = occ_cache.find(fn);
+        if (it != occ_cache.end()) occ = it->second;
+    }
+    if (occ == 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0) != hipSuccess || occ < 1) {
             (void)hipGetLastError();
             occ = 1;
         }
+        std::lock_guard<std::mutex> lock(occ_mutex);
         occ_cache[fn] = occ;
     }
     const int need = (rows + rows_per_block - 1) / rows_per_block;
