@@ -233,11 +233,12 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
     if (fused) {
         const bool small = narrow_symbolic(S.op);
         const int grid = (M + 255) / 256;
+        const long long super_rows = super_tile_rows((M + kWsTile - 1) / kWsTile);
 #define MSP_FUSED(KK, IT)                                                                                  \
     k_sym_fused<KK, IT, true><<<grid, 256, 0, st>>>(M, S.op.ncols, S.op.arp, S.op.acol, S.op.brp, S.op.bcol, \
                                                     h->u.as<int32_t>(), h->rnnz.as<int32_t>(), S.sp.table,   \
                                                     S.sp.table.umax[1], info, S.np.table,                    \
-                                                    h->bsum.as<long long>(), S.mp)
+                                                    h->bsum.as<long long>(), super_rows, S.mp)
         if (S.sp.spec[1].lanes == 4) { if (small) MSP_FUSED(4, int); else MSP_FUSED(4, long long); }
         else { if (small) MSP_FUSED(8, int); else MSP_FUSED(8, long long); }
 #undef MSP_FUSED
@@ -292,7 +293,9 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
     // 3. prefix sum (fresh tile states every replay) with the numeric histogram
     if (fused) {
         k_scan_fused<<<(M + kWsTile - 1) / kWsTile, kWsBS, 0, st>>>(M, h->rnnz.as<int32_t>(),
-                                                                   h->bsum.as<long long>(), S.crp.as<int64_t>(),
+                                                                   h->bsum.as<long long>(),
+                                                                   super_tile_rows((M + kWsTile - 1) / kWsTile),
+                                                                   S.crp.as<int64_t>(),
                                                                    S.sp.table.nb, info, nullptr, 0);
         if ((s = launch_ok("k_scan_fused")) != MSP_OK) return s;
     } else {

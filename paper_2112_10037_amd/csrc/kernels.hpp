@@ -946,7 +946,7 @@ __global__ void __launch_bounds__(256)
 k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, int32_t* __restrict__ u_out,
             int32_t* __restrict__ row_nnz, BinTable bins, int umax, DevInfo* info, BinTable nbins,
-            long long* __restrict__ bsum, RowMap mp = RowMap{}) {
+            long long* __restrict__ bsum, long long super_rows, RowMap mp = RowMap{}) {
     __shared__ int hist[kNB];
     __shared__ int nhist[kNB];
     __shared__ long long s_sum[4];
@@ -1074,7 +1074,13 @@ k_sym_fused(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     if (threadIdx.x == 128 && s_unknown) atomicOr(&info->fused_other, 1);
     if (!s_unknown && nbins.nb > 0 && threadIdx.x < kNB && nhist[threadIdx.x])
         atomicAdd(&info->num_part[(blockIdx.x / (kScanTile / 256)) % kParts][threadIdx.x], nhist[threadIdx.x]);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+    if (threadIdx.x == 0) {
+        const long long tot = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        bsum[blockIdx.x] = tot;
+        if (tot && super_rows)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&info->ssum[(long long)blockIdx.x * 256 / super_rows]),
+                      (unsigned long long)tot);
+    }
 }
 
 // The speculative scan behind k_sym_fused.  When no row was left for a
@@ -1090,11 +1096,21 @@ constexpr int kWsBS = 512;
 constexpr int kWsPer = 8;
 constexpr int kWsTile = kWsBS * kWsPer;                // rows per workgroup: 16 fused workgroups
 constexpr int kWsWaves = kWsBS / kWave;
+
+// Rows per super-tile for a scan of `tiles` tiles: the fewest whole tiles
+// that keep the number of super-tiles within kSupers, or 0 (no super-tiles:
+// each tile sums the block totals before it) up to kDirectTiles tiles,
+// where those reads cost less than the fused pass's device-scope atomics.
+constexpr int kDirectTiles = 512;
+inline long long super_tile_rows(int tiles) {
+    if (tiles <= kDirectTiles) return 0;
+    return ((long long)tiles + kSupers - 1) / kSupers * kWsTile;
+}
 static_assert(kParts * kPartStride == 2 * kWsBS, "the last tile loads the partition counters two per thread");
 static_assert(kPartStride == 32 && kWave == 64, "a wave holds four partition rows");
 
 static __global__ void __launch_bounds__(kWsBS)
-k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict__ bsum,
+k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict__ bsum, long long super_rows,
              int64_t* __restrict__ row_ptr, int spec_nb, DevInfo* info, HostSummary* hs, int seq) {
     __shared__ long long s_pre[kWsWaves], s_own[kWsWaves];
     __shared__ int s_cnt[kWsWaves][kPartStride];
@@ -1102,14 +1118,19 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
     const int tile = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const bool last = tile == (int)gridDim.x - 1;
-    // Every load is issued before the first wait: the flag, the totals of
-    // the fused workgroups before this tile (pairs: their count is a
-    // multiple of 16), this tile's row counts and, in the last tile, the
+    // Every load is issued before the first wait: the flag, the totals
+    // before this tile (the sums of the super-tiles before its own, if there
+    // are super-tiles, then the fused workgroups' totals from the start of
+    // its super-tile, in pairs: both bounds are multiples of 16
+    // workgroups), this tile's row counts and, in the last tile, the
     // partitioned numeric bin counters.
     const bool other = load_coherent(&info->fused_other) != 0;
-    const long long npair = (long long)tile * (kWsTile / 256) / 2;
-    const longlong2* bs2 = reinterpret_cast<const longlong2*>(bsum);
+    const long long sup = super_rows ? (long long)tile * kWsTile / super_rows : 0;
+    const long long b0 = sup * (super_rows / 256);
+    const long long npair = ((long long)tile * (kWsTile / 256) - b0) / 2;
+    const longlong2* bs2 = reinterpret_cast<const longlong2*>(bsum + b0);
     long long acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    for (long long j = threadIdx.x; j < sup; j += kWsBS) acc1 += info->ssum[j];
     long long i = threadIdx.x;
     for (; i + 3 * kWsBS < npair; i += 4 * kWsBS) {
         const longlong2 q0 = bs2[i], q1 = bs2[i + kWsBS], q2 = bs2[i + 2 * kWsBS], q3 = bs2[i + 3 * kWsBS];

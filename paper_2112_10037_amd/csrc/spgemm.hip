@@ -719,10 +719,13 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
         if (np) nt = np->table;
         h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
         const bool small = narrow_symbolic(operands_of(A, B));   // 32-bit positions and offsets
+        const int tiles = (m + kWsTile - 1) / kWsTile;
+        const long long super_rows = super_tile_rows(tiles);
 #define MSP_FUSED(KK, IT)                                                                                 \
     k_sym_fused<KK, IT><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,   \
                                                      h->u.as<int32_t>(), h->rnnz.as<int32_t>(), sp.table,  \
-                                                     sp.table.umax[1], info, nt, h->bsum.as<long long>())
+                                                     sp.table.umax[1], info, nt, h->bsum.as<long long>(),  \
+                                                     super_rows)
         if (sp.spec[1].lanes == 4) { if (small) MSP_FUSED(4, int); else MSP_FUSED(4, long long); }
         else { if (small) MSP_FUSED(8, int); else MSP_FUSED(8, long long); }
 #undef MSP_FUSED
@@ -730,8 +733,8 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
         h->prof.end(h->stream);
         h->prof.begin(MSP_PHASE_SCAN, h->stream);
         const int seq = ++h->sum_seq;
-        const int tiles = (m + kWsTile - 1) / kWsTile;
-        k_scan_fused<<<tiles, kWsBS, 0, h->stream>>>(m, h->rnnz.as<int32_t>(), h->bsum.as<long long>(), row_ptr,
+        k_scan_fused<<<tiles, kWsBS, 0, h->stream>>>(m, h->rnnz.as<int32_t>(), h->bsum.as<long long>(), super_rows,
+                                                     row_ptr,
                                                      sp.table.nb, info, h->dsum, seq);
         if ((s = launch_check("k_scan_fused")) != MSP_OK) return s;
         h->prof.end(h->stream);

@@ -28,6 +28,10 @@ constexpr float kFeatLogScale = 1.0f / 16.0f;
 constexpr int kParts = 32;
 constexpr int kNB = kMaxBins + 1;
 constexpr int kPartStride = 32;    // ints per partition row (128 bytes)
+// On long inputs the fused symbolic pass also adds each workgroup's
+// row-count total into one of at most kSupers super-tile sums, so that a
+// scan tile finds the total before it in a bounded number of reads.
+constexpr int kSupers = 1024;
 
 struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
@@ -39,6 +43,7 @@ struct DevInfo {
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
+    long long ssum[kSupers];              // rows' counts per super-tile of the fused symbolic pass
 };
 
 // What the host needs between passes, written by a one-workgroup kernel

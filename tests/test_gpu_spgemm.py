@@ -353,6 +353,22 @@ def test_merge_first_products_over_many_scan_tiles(h):
     assert np.array_equal(rn.cpu().numpy(), ref) and tot == ref.sum()
 
 
+@pytest.mark.slow
+def test_merge_first_scan_over_super_tiles(h):
+    """8.4 million rows, all in the merge bin: 2,052 scan tiles, more than
+    the 1,024 super-tile sums hold, so a super-tile spans three tiles and a
+    tile adds the sums of the super-tiles before its own and then the block
+    totals of its own super-tile before it."""
+    m = 4096 * 2051 + 1234
+    rng = np.random.default_rng(95)
+    A = gen.erdos_renyi(m, m, rng.integers(0, 4, m), seed=96)
+    B = gen.erdos_renyi(m, m, rng.integers(1, 5, m), seed=97)
+    check_full(h, A, B)
+    rn, tot = h.symbolic(to_dev(A), to_dev(B))
+    ref = oracle.row_nnz(A, B)
+    assert np.array_equal(rn.cpu().numpy(), ref) and tot == ref.sum()
+
+
 def test_validation_accepts_views(h):
     """A problem's view of a packed batch (row_ptr starting above 0 and
     ending below nnz) passes validation and multiplies like the standalone
