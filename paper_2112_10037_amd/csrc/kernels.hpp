@@ -1997,6 +1997,7 @@ k_num_dense(Work wk, long long ncols,
 // over ncols.  The bitmap is then walked in column order and each column
 // goes out with the value at its rank, the accumulator returning to zero.
 constexpr int kRankBS = 512;
+constexpr int kRankUnroll = 4;             // products per thread and round (R-MAT 2^20: 769 -> 741 ms)
 
 template <int BS, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
@@ -2008,6 +2009,7 @@ k_num_rank(Work wk, long long ncols,
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
+    constexpr int RU = kRankUnroll;
     extern __shared__ uint32_t dyn_smem[];      // bitmap words, then the rank table
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -2041,11 +2043,24 @@ k_num_rank(Work wk, long long ncols,
             __syncthreads();
             const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
             int t = -1;                         // owner of q: one search, then it only moves forward
-            for (long long q = tid; q < total; q += BS) {
-                if (t < 0) t = owner_search(s_off, nact, q);
-                else while (s_off[t] <= q) ++t;
-                const int32_t j = bcol[s_bst[t] + q];
-                atomicOr(&bm[j >> 5], 1u << (j & 31));
+            // RU products per thread and round, their loads issued before
+            // any is used: one workgroup per compute unit leaves few waves
+            // to hide the gathers' latency
+            for (long long q0 = tid; q0 < total; q0 += RU * BS) {
+                int32_t j[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const long long q = q0 + (long long)u * BS;
+                    j[u] = -1;
+                    if (q < total) {
+                        if (t < 0) t = owner_search(s_off, nact, q);
+                        else while (s_off[t] <= q) ++t;
+                        j[u] = bcol[s_bst[t] + q];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+                    if (j[u] >= 0) atomicOr(&bm[j[u] >> 5], 1u << (j[u] & 31));
             }
             __syncthreads();
         }
@@ -2083,17 +2098,31 @@ k_num_rank(Work wk, long long ncols,
             __syncthreads();
             const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
             int t = -1;
-            for (long long q = tid; q < total; q += BS) {
-                if (t < 0) t = owner_search(s_off, nact, q);
-                else while (s_off[t] <= q) ++t;
-                const long long bi = s_bst[t] + q;
-                const int32_t j = bcol[bi];
-                const int w = j >> 5;
-                int r = r8[w >> 3];
-                for (int x = w & ~7; x < w; ++x) r += __builtin_popcount(bm[x]);
-                r += __builtin_popcount(bm[w] & ((1u << (j & 31)) - 1u));
-                __hip_atomic_fetch_add(&acc[r], s_a[t] * to_f64(bval[bi]), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (long long q0 = tid; q0 < total; q0 += RU * BS) {
+                int32_t j[RU];
+                double pv[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const long long q = q0 + (long long)u * BS;
+                    j[u] = -1;
+                    pv[u] = 0.0;
+                    if (q < total) {
+                        if (t < 0) t = owner_search(s_off, nact, q);
+                        else while (s_off[t] <= q) ++t;
+                        const long long bi = s_bst[t] + q;
+                        j[u] = bcol[bi];
+                        pv[u] = s_a[t] * to_f64(bval[bi]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    if (j[u] < 0) continue;
+                    const int w = j[u] >> 5;
+                    int r = r8[w >> 3];
+                    for (int x = w & ~7; x < w; ++x) r += __builtin_popcount(bm[x]);
+                    r += __builtin_popcount(bm[w] & ((1u << (j[u] & 31)) - 1u));
+                    __hip_atomic_fetch_add(&acc[r], pv[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
             __syncthreads();
         }
