@@ -123,6 +123,9 @@ typedef struct msp_handle msp_handle;
  * checks that it is gfx950 (MSP_ERR_UNSUPPORTED otherwise). */
 msp_status msp_create(msp_handle** h, int device, void* hip_stream);
 msp_status msp_destroy(msp_handle* h);
+/* Queue the handle's later work on `hip_stream`.  The handle's workspaces
+ * are shared by its calls, so work queued on the new stream first waits for
+ * everything already queued on the old one (an event, no host wait). */
 msp_status msp_set_stream(msp_handle* h, void* hip_stream);
 msp_status msp_set_allocator(msp_handle* h, msp_alloc_fn alloc, msp_free_fn free_fn, void* ctx);
 /* Tuning used when a call's opts->tuning is all zero. */

@@ -237,9 +237,20 @@ class Handle:
                                   device=f"cuda:{self.device}")
         except RuntimeError:
             return None
+        # torch files the block under its current stream; when the library
+        # queues on another one, the block is also marked in use there, so
+        # that it is not handed out again before that stream's work is done
+        if self._torch.cuda.current_stream(self.device).cuda_stream != (stream or 0):
+            t.record_stream(self._stream)
         p = t.data_ptr()
         self._live[p] = t
         return p
+
+    def set_stream(self, stream):
+        """Queue later calls on `stream` (a torch.cuda.Stream); they wait for
+        the handle's work already queued on the old stream."""
+        _check(self._lib.msp_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self._stream = stream
 
     def _free(self, ctx, ptr, stream):
         self._live.pop(ptr, None)

@@ -179,7 +179,20 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
 
 extern "C" msp_status msp_set_stream(msp_handle* h, void* stream) {
     if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
-    h->stream = (hipStream_t)stream;
+    const hipStream_t ns = (hipStream_t)stream;
+    if (ns == h->stream) return MSP_OK;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    // Calls share the handle's workspaces: work queued later on the new
+    // stream waits for everything already queued on the old one.
+    hipEvent_t ev = nullptr;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreateWithFlags");
+    e = hipEventRecord(ev, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ns, ev, 0);
+    (void)hipEventDestroy(ev);                  // the queued wait keeps what it needs
+    if (e != hipSuccess) return hip_fail(e, "ordering the new stream after the old one");
+    h->stream = ns;
     return MSP_OK;
 }
 

@@ -320,6 +320,35 @@ def test_pass_summaries_reach_the_host():
         hh.close()
 
 
+def test_stream_switch_orders_work():
+    """A handle moved to another stream right after a call: the next call
+    clears the shared workspaces only after the first call's kernels, so
+    both products are exact; a call made while torch's current stream is a
+    third one allocates C on the handle's stream as well."""
+    import torch
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    A = gen.laplacian_2d(512)
+    B = gen.erdos_renyi(3000, 3000, 6, seed=71)
+    dA, dB = to_dev(A), to_dev(B)
+    torch.cuda.synchronize()
+    h = binding.Handle(0, stream=s1)
+    try:
+        with torch.cuda.stream(s1):
+            C1 = h.spgemm(dA, dA)
+        h.set_stream(s2)
+        with torch.cuda.stream(s2):
+            C2 = h.spgemm(dB, dB)
+        C3 = h.spgemm(dA, dA)               # torch's current stream is the default one here
+        torch.cuda.synchronize()
+        h.sync()
+        for C, M in ((C1, A), (C2, B), (C3, A)):
+            host = C.to_host()
+            ref = oracle.spgemm(M, M)
+            oracle.compare(host.row_ptr, host.col, host.val, ref, TOL[np.dtype(np.float64)])
+    finally:
+        h.close()
+
+
 def test_fresh_handles_start_clean():
     """A handle's device info block may reuse memory a destroyed handle
     filled with row counts; a new handle's first call must still report no
