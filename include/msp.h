@@ -19,8 +19,10 @@
  *  - row_ptr is int64 with nrows + 1 entries; its values index col and val
  *    directly and never exceed nnz, the length of those arrays (row_ptr[0]
  *    may be > 0, e.g. for one matrix's rows inside a larger array); col is int32
- *    (so ncols <= 2^31 - 1); values are FP32 or FP64, the same type for A, B
- *    and C.
+ *    (so ncols <= 2^31 - 1); nrows <= 2^31 - 8193 (MSP_ERR_INDEX_OVERFLOW
+ *    above: launch grids are rounded up from it in 32-bit arithmetic), and
+ *    the same bound holds for a batch's total rows; values are FP32 or FP64,
+ *    the same type for A, B and C.
  *  - Inputs must be canonical CSR: row_ptr non-decreasing, columns strictly
  *    increasing inside each row and in [0, ncols).  With opts->validate = 1
  *    the library checks this on the device and returns

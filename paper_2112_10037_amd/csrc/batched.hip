@@ -152,8 +152,8 @@ static msp_status check_batch_csr(const msp_batch_csr* M, const char* name) {
         if (M->ncols[p] < 0 || M->ncols[p] > INT32_MAX)
             return fail(MSP_ERR_INVALID_ARG, "%s: problem %d has %lld columns", name, p, (long long)M->ncols[p]);
     }
-    if (M->row_start[M->nprob] >= INT32_MAX)
-        return fail(MSP_ERR_INDEX_OVERFLOW, "%s: the batch's rows must fit int32", name);
+    if (M->row_start[M->nprob] > kMaxRows)
+        return fail(MSP_ERR_INDEX_OVERFLOW, "%s: a batch holds at most %lld rows", name, kMaxRows);
     if (M->dtype != MSP_F32 && M->dtype != MSP_F64) return fail(MSP_ERR_DTYPE, "%s: dtype must be F32 or F64", name);
     if (!M->row_ptr) return fail(MSP_ERR_INVALID_ARG, "%s.row_ptr is NULL", name);
     if (M->nnz < 0 || (M->nnz > 0 && (!M->col || !M->val))) return fail(MSP_ERR_INVALID_ARG, "%s: bad nnz/col/val", name);

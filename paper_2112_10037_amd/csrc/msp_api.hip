@@ -228,9 +228,9 @@ namespace msp {
 msp_status check_csr(const msp_csr* M, const char* name) {
     if (!M) return fail(MSP_ERR_INVALID_ARG, "%s is NULL", name);
     if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0) return fail(MSP_ERR_INVALID_ARG, "%s has a negative size", name);
-    if (M->nrows >= INT32_MAX || M->ncols > INT32_MAX)
-        return fail(MSP_ERR_INDEX_OVERFLOW, "%s: rows and columns must fit int32 (%lld x %lld)", name,
-                    (long long)M->nrows, (long long)M->ncols);
+    if (M->nrows > kMaxRows || M->ncols > INT32_MAX)
+        return fail(MSP_ERR_INDEX_OVERFLOW, "%s: at most %lld rows and 2^31 - 1 columns (%lld x %lld)", name,
+                    kMaxRows, (long long)M->nrows, (long long)M->ncols);
     if (M->dtype != MSP_F32 && M->dtype != MSP_F64) return fail(MSP_ERR_DTYPE, "%s: dtype must be MSP_F32 or MSP_F64", name);
     if (!M->row_ptr) return fail(MSP_ERR_INVALID_ARG, "%s.row_ptr is NULL", name);
     if (M->nnz > 0 && (!M->col || !M->val)) return fail(MSP_ERR_INVALID_ARG, "%s.col/val is NULL with nnz > 0", name);

@@ -525,7 +525,6 @@ msp_status wait_summary(msp_handle* h, int seq, bool with_nnz, const int (*part)
                 for (int b = 0; b < kNB; ++b) h->hsum->counts[b] = b <= spec_nb ? sym[b] : 0;
             }
         }
-        return MSP_OK;
     }
     if (h->prof.on) h->prof.collect();
     return take_pending_error(h);

@@ -7,6 +7,9 @@
 namespace msp {
 
 constexpr int kWave = 64;
+// Most rows of one matrix (or of a whole batch): grid sizes are rounded up
+// from the row count in int arithmetic, with at most 8192 added.
+constexpr long long kMaxRows = 2147483647LL - 8192;
 constexpr int kMaxBins = 16;
 constexpr int32_t kEmpty = -1;
 

@@ -3,6 +3,7 @@
 Structure (row_ptr, col) must be identical; values must satisfy
 |c - o| <= tol * sum_k |a_ik||b_kj| with tol 1e-12 (FP64) or 1e-5 (FP32).
 """
+import ctypes
 import json
 import os
 
@@ -231,6 +232,14 @@ def test_validation_errors(h):
     with pytest.raises(binding.MspError) as e:
         h.spgemm(to_dev(A), to_dev(A.astype(np.float32)))
     assert e.value.name == "MSP_ERR_DTYPE"
+    # more rows than the launch grids can be rounded up from: refused before
+    # anything is read (the row_ptr given is far too short on purpose)
+    dA = to_dev(A)
+    big = binding.c_csr(2**31 - 8192, 50, 0, dA.row_ptr.data_ptr(), None, None, binding.MSP_F64)
+    a = dA.c()
+    out = binding.c_csr_out()
+    st = h._lib.msp_spgemm(h._h, ctypes.byref(big), ctypes.byref(a), ctypes.byref(out), None)
+    assert binding.STATUS[st] == "MSP_ERR_INDEX_OVERFLOW"
     check_full(h, A, A, validate=True)
 
 
