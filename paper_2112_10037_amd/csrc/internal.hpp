@@ -96,6 +96,7 @@ struct msp_handle {
     msp_tuning tuning{};
     msp::DevBuf info, u, rnnz, perm, tiles, dslab, gbm, sbm, prod;
     msp::DevBuf bsum;               // 256-row workgroup totals of the fused symbolic pass
+    msp::DevBuf gsl;                // per-workgroup bitmap copies of the sliced global-bin kernel
     size_t dslab_cols = 0;          // ncols the dense slabs were zeroed for
     int dslab_count = 0;
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info

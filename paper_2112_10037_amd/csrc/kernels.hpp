@@ -2168,6 +2168,266 @@ k_num_rank(Work wk, long long ncols,
     }
 }
 
+// Rows of the global bin whose columns fit an LDS bitmap, accumulated in
+// LDS one column slice at a time.  The bitmap pass sets the row's column
+// bitmap and rank table in LDS (as k_num_rank does) and keeps a copy of the
+// bitmap in the workgroup's global scratch.  The row is then cut at
+// 256-column block boundaries into slices whose bitmap segment, segment
+// rank table and FP64 accumulator (one entry per output of the slice) fit
+// the same LDS together: a block costs 36 bytes plus 8 per output, and a
+// slice takes the blocks whose running cost falls in one budget-sized
+// interval.  For each slice, every A entry's B row is searched for the
+// slice's column range, the products in it add into the accumulator with
+// LDS atomics, and the segment goes out in column order from the slice's
+// first output's position in C.  No atomic leaves LDS.
+constexpr int kSliceMax = 256;               // slices per row
+constexpr int kSliceBlockCost = 8 * 4 + 4 + 8 * 256;   // most bytes one 256-column block can need
+
+__device__ __forceinline__ long long lower_bound_col(const int32_t* __restrict__ col, long long lo, long long hi,
+                                                     long long c) {
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if ((long long)col[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <int BS, typename VT, bool BATCH = false>
+__global__ void __launch_bounds__(BS)
+k_num_slice(Work wk, long long ncols,
+            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
+            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
+            const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
+            uint32_t* __restrict__ gbm, long long lds_bytes, int32_t* __restrict__ cnt_out, DevInfo* info,
+            RowMap mp) {
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
+    constexpr int RU = kRankUnroll;
+    extern __shared__ __align__(16) uint32_t dyn_slice[];   // bitmap and rank table; then a slice's segment and accumulator
+    uint32_t* const dyn_smem = dyn_slice;
+    __shared__ long long s_off[BS];
+    __shared__ long long s_bst[BS];
+    __shared__ double s_a[BS];
+    __shared__ BlockScanSmem<BS> sm;
+    __shared__ int s_sb[kSliceMax + 1];         // first 256-column block of each slice
+    __shared__ int s_sr[kSliceMax];             // rank of each slice's first output
+    __shared__ int s_ns;
+    const int tid = threadIdx.x;
+    const long long words = (ncols + 31) >> 5;
+    const long long nr8 = (words + 7) >> 3;
+    const long long budget = lds_bytes - kSliceBlockCost - 16;   // > kSliceBlockCost (host); 16: alignment pad
+    uint32_t* gb = gbm + (long long)blockIdx.x * words;
+    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+        const int row = perm ? perm[slot] : (int)slot;
+        const long long bo = row_boff<BATCH>(mp, row);
+        uint32_t* bm = dyn_smem;
+        int* r8 = reinterpret_cast<int*>(dyn_smem + words);
+        for (long long w = tid; w < words; w += BS) bm[w] = 0u;
+        __syncthreads();
+        const long long a0 = arp[row], a1 = arp[row + 1];
+        // bitmap pass: the row's columns
+        for (long long c0 = a0; c0 < a1; c0 += BS) {
+            const long long p = c0 + tid;
+            long long len = 0, bst = 0;
+            if (p < a1) {
+                const long long k = acol[p] + bo;
+                bst = brp[k];
+                len = brp[k + 1] - bst;
+            }
+            long long total;
+            const long long incl = block_incl_scan<BS>(len, sm, &total);
+            s_off[tid] = incl;
+            s_bst[tid] = bst - (incl - len);
+            __syncthreads();
+            const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
+            int t = -1;
+            for (long long q0 = tid; q0 < total; q0 += RU * BS) {
+                int32_t j[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const long long q = q0 + (long long)u * BS;
+                    j[u] = -1;
+                    if (q < total) {
+                        if (t < 0) t = owner_search(s_off, nact, q);
+                        else while (s_off[t] <= q) ++t;
+                        j[u] = bcol[s_bst[t] + q];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+                    if (j[u] >= 0) atomicOr(&bm[j[u] >> 5], 1u << (j[u] & 31));
+            }
+            __syncthreads();
+        }
+        // rank table, the bitmap's copy, and the slices
+        long long nrow;
+        {
+            const long long E = (nr8 + BS - 1) / BS;
+            const long long i0 = (long long)tid * E, i1 = i0 + E < nr8 ? i0 + E : nr8;
+            long long loc = 0;
+            for (long long w = 8 * i0; w < 8 * i1 && w < words; ++w) loc += __builtin_popcount(bm[w]);
+            long long tot;
+            long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
+            nrow = tot;
+            long long cost = 0;                         // this thread's blocks: 36 bytes + 8 per output
+            for (long long i = i0; i < i1; ++i) {
+                r8[i] = (int)run;
+                long long c = 0;
+                for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
+                run += c;
+                cost += 36 + 8 * c;
+            }
+            long long ctot;
+            long long pc = block_incl_scan<BS>(cost, sm, &ctot) - cost;   // running cost before block i0
+            for (long long i = i0; i < i1; ++i) {
+                const long long prev = pc;
+                long long c = 0;
+                for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
+                pc += 36 + 8 * c;
+                const long long sid = (pc - 1) / budget;
+                if ((i == 0 || sid != (prev - 1) / budget) && sid < kSliceMax) {
+                    s_sb[sid] = (int)i;
+                    s_sr[sid] = r8[i];
+                }
+            }
+            if (tid == 0) {
+                const long long n = nr8 > 0 ? (ctot - 1) / budget + 1 : 0;
+                s_ns = n <= kSliceMax ? (int)n : -1;
+                if (n <= kSliceMax) s_sb[n] = (int)nr8;
+            }
+            for (long long w = tid; w < words; w += BS) gb[w] = bm[w];
+        }
+        __syncthreads();
+        const int ns = s_ns;
+        const long long rp = crp[row];
+        const long long rend = crp[row + 1];
+        if (ns < 0) {
+            if (tid == 0) {
+                if (cnt_out) cnt_out[row] = -1;
+                else atomicOr(&info->err, kErrCount);
+            }
+            continue;                                  // uniform; the host bounds the slice count
+        }
+        for (int sl = 0; sl < ns; ++sl) {
+            const long long b0 = s_sb[sl], b1 = s_sb[sl + 1];
+            const long long w0 = 8 * b0, w1 = 8 * b1 < words ? 8 * b1 : words;
+            const long long nw = w1 - w0, nb = b1 - b0;
+            const long long c_lo = w0 * 32, c_hi = w1 * 32 < ncols ? w1 * 32 : ncols;
+            uint32_t* sbm = dyn_smem;
+            int* sr8 = reinterpret_cast<int*>(dyn_smem + nw);
+            double* acc = reinterpret_cast<double*>(dyn_smem + ((nw + nb + 1) & ~1LL));
+            __syncthreads();                           // the previous slice (or the full bitmap) is done with LDS
+            for (long long w = tid; w < nw; w += BS) sbm[w] = gb[w0 + w];
+            __syncthreads();
+            long long nout;                            // outputs of the slice
+            {
+                const long long E = (nb + BS - 1) / BS;
+                const long long i0 = (long long)tid * E, i1 = i0 + E < nb ? i0 + E : nb;
+                long long loc = 0;
+                for (long long w = 8 * i0; w < 8 * i1 && w < nw; ++w) loc += __builtin_popcount(sbm[w]);
+                long long tot;
+                long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
+                nout = tot;
+                for (long long i = i0; i < i1; ++i) {
+                    sr8[i] = (int)run;
+                    for (long long w = 8 * i; w < 8 * i + 8 && w < nw; ++w) run += __builtin_popcount(sbm[w]);
+                }
+            }
+            for (long long r = tid; r < nout; r += BS) acc[r] = 0.0;
+            __syncthreads();
+            // the products whose columns fall in [c_lo, c_hi)
+            for (long long c0 = a0; c0 < a1; c0 += BS) {
+                const long long p = c0 + tid;
+                long long len = 0, bst = 0;
+                double a = 0.0;
+                if (p < a1) {
+                    const long long k = acol[p] + bo;
+                    a = to_f64(aval[p]);
+                    long long lo = brp[k], hi = brp[k + 1];
+                    if (ns > 1) {
+                        lo = lower_bound_col(bcol, lo, hi, c_lo);
+                        hi = lower_bound_col(bcol, lo, hi, c_hi);
+                    }
+                    bst = lo;
+                    len = hi - lo;
+                }
+                long long total;
+                const long long incl = block_incl_scan<BS>(len, sm, &total);
+                s_off[tid] = incl;
+                s_bst[tid] = bst - (incl - len);
+                s_a[tid] = a;
+                __syncthreads();
+                const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
+                int t = -1;
+                for (long long q0 = tid; q0 < total; q0 += RU * BS) {
+                    int32_t j[RU];
+                    double pv[RU];
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const long long q = q0 + (long long)u * BS;
+                        j[u] = -1;
+                        pv[u] = 0.0;
+                        if (q < total) {
+                            if (t < 0) t = owner_search(s_off, nact, q);
+                            else while (s_off[t] <= q) ++t;
+                            const long long bi = s_bst[t] + q;
+                            j[u] = (int32_t)(bcol[bi] - c_lo);
+                            pv[u] = s_a[t] * to_f64(bval[bi]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        if (j[u] < 0) continue;
+                        const int w = j[u] >> 5;
+                        int r = sr8[w >> 3];
+                        for (int x = w & ~7; x < w; ++x) r += __builtin_popcount(sbm[x]);
+                        r += __builtin_popcount(sbm[w] & ((1u << (j[u] & 31)) - 1u));
+                        atomicAdd(&acc[r], pv[u]);
+                    }
+                }
+                __syncthreads();
+            }
+            // the slice in column order: wave wv walks the segment words [wv WS, wv WS + WS)
+            const long long base = rp + s_sr[sl];
+            constexpr int NW = BS / 64;
+            const int wv = tid >> 6, ln = tid & 63;
+            const long long WS = (nw + NW - 1) / NW;
+            const long long wb = (long long)wv * WS, we = wb + WS < nw ? wb + WS : nw;
+            long long wc = 0;
+            for (long long w = wb + ln; w < we; w += 64) wc += __builtin_popcount(sbm[w]);
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) wc += __shfl_xor(wc, d);
+            long long run;
+            const long long wincl = block_incl_scan<BS>(ln == 0 ? wc : 0, sm, &run);
+            long long r0 = __shfl(wincl, 0) - wc;      // rank in the slice of the wave's first column
+            for (long long x0 = wb; x0 < we; x0 += 64) {
+                const long long w = x0 + ln;
+                uint32_t bits = w < we ? sbm[w] : 0u;
+                const long long c = __builtin_popcount(bits);
+                const long long incl = group_incl_scan<64>(c, ln);
+                long long r = r0 + incl - c;
+                r0 += __shfl(incl, 63);
+                while (bits) {
+                    const int bt = __builtin_ctz(bits);
+                    bits &= bits - 1;
+                    if (base + r < rend) {
+                        ccol[base + r] = (int32_t)((w0 + w) * 32 + bt);
+                        cval[base + r] = (VT)acc[r];
+                    }
+                    ++r;
+                }
+            }
+        }
+        if (tid == 0) {
+            const long long cap = rend - rp;
+            if (cnt_out) cnt_out[row] = nrow <= cap ? (int)nrow : -1;
+            else if (nrow != cap) atomicOr(&info->err, kErrCount);
+        }
+        __syncthreads();
+    }
+}
+
 // ===========================================================================
 // Input validation (canonical CSR)
 // ===========================================================================

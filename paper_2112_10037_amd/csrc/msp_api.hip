@@ -166,7 +166,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
     for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->dslab, &h->gbm, &h->sbm, &h->prod,
-                      &h->bsum})
+                      &h->bsum, &h->gsl})
         b->release();
     release_extra(h);
     h->prof.release();

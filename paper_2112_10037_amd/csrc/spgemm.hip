@@ -126,6 +126,10 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
 // ---------------------------------------------------------------------------
 constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense kernels
 constexpr int kRankReserve = 13 * 1024;    // static LDS of k_num_rank<kRankBS>
+constexpr int kSliceReserve = 15 * 1024;   // static LDS of k_num_slice<kRankBS>
+#ifndef MSP_NUM_SLICE
+#define MSP_NUM_SLICE 1
+#endif
 
 #define MSP_GROUP_SHAPES(X) \
     X(8, 32) X(16, 32) X(8, 64) X(16, 64) X(32, 64) X(16, 128) X(32, 128) X(64, 128) \
@@ -215,6 +219,16 @@ msp_status configure_kernels(msp_handle* h) {
     }
     for (void* f : rank_fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
+        }
+    }
+    const int dyn_slice = std::max(0, h->lds_per_block - kSliceReserve);
+    void* slice_fns[] = {(void*)k_num_slice<kRankBS, float, false>, (void*)k_num_slice<kRankBS, double, false>,
+                         (void*)k_num_slice<kRankBS, float, true>, (void*)k_num_slice<kRankBS, double, true>};
+    for (void* f : slice_fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_slice);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
@@ -379,6 +393,27 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
     } else if (s.kind == Kind::Dense) {
         const long long n = op.ncols;
         const long long words = (n + 31) / 32;
+#if MSP_NUM_SLICE
+        {
+            // the columns fit an LDS bitmap with its rank table: accumulate
+            // in LDS slice by slice
+            const long long nr8 = (words + 7) / 8;
+            const long long rank_lds = words * 4 + nr8 * 4;
+            const long long avail = h->lds_per_block - kSliceReserve;
+            const long long lds = std::min(avail, rank_lds + 65536);
+            const long long budget = lds - kSliceBlockCost - 16;
+            if (rank_lds <= avail && budget > kSliceBlockCost &&
+                (36 * nr8 + 8 * n) / budget + 1 <= kSliceMax) {
+                const int grid = std::max(1, std::min(rows, h->num_cu));
+                msp_status r = h->gsl.ensure((size_t)grid * (size_t)words * 4);
+                if (r != MSP_OK) return r;
+                k_num_slice<kRankBS, VT, BATCH><<<grid, kRankBS, (size_t)lds, st>>>(
+                    wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->gsl.as<uint32_t>(), lds,
+                    cnt_out, info, mp);
+                return launch_check("k_num_slice");
+            }
+        }
+#endif
         const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
         // one slab per resident workgroup; keep the arena under 16 GiB
         long long cap = (16LL << 30) / std::max(1LL, n * 8);

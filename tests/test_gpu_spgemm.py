@@ -107,6 +107,19 @@ def test_hub_rows_lds_bitmap_and_dense(h):
     check_full(h, A, B)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_global_bin_many_slices(h, dtype):
+    """2^19 columns: the row bitmap and its rank table take 72 KB of LDS, and
+    rows of about 360,000 outputs are accumulated in LDS over about twenty
+    column slices each, every slice found by a binary search in each B row."""
+    n = 1 << 19
+    B = gen.erdos_renyi(4096, n, 300, seed=21, dtype=dtype)
+    k = np.full(32, 5, dtype=np.int64)
+    k[[0, 13, 31]] = [2000, 1200, 2000]
+    A = gen.erdos_renyi(32, 4096, k, seed=22, dtype=dtype)
+    check_full(h, A, B)
+
+
 def test_wide_matrix_global_bitmap(h):
     """ncols = 2^21: the n-bit bitmap no longer fits LDS (global slabs)."""
     n = 1 << 21
