@@ -2309,6 +2309,10 @@ k_num_slice(Work wk, long long ncols,
             }
             continue;                                  // uniform; the host bounds the slice count
         }
+        // a row whose A entries fit one chunk keeps each entry's B-row
+        // position where the previous slice ended: one search per slice
+        const bool one_chunk = a1 - a0 <= BS;
+        long long cur = -1;
         for (int sl = 0; sl < ns; ++sl) {
             const long long b0 = s_sb[sl], b1 = s_sb[sl + 1];
             const long long w0 = 8 * b0, w1 = 8 * b1 < words ? 8 * b1 : words;
@@ -2346,8 +2350,10 @@ k_num_slice(Work wk, long long ncols,
                     a = to_f64(aval[p]);
                     long long lo = brp[k], hi = brp[k + 1];
                     if (ns > 1) {
-                        lo = lower_bound_col(bcol, lo, hi, c_lo);
-                        hi = lower_bound_col(bcol, lo, hi, c_hi);
+                        if (one_chunk && cur >= 0) lo = cur;
+                        else lo = lower_bound_col(bcol, lo, hi, c_lo);
+                        hi = sl + 1 < ns ? lower_bound_col(bcol, lo, hi, c_hi) : hi;
+                        if (one_chunk) cur = hi;
                     }
                     bst = lo;
                     len = hi - lo;
