@@ -2172,16 +2172,18 @@ k_num_rank(Work wk, long long ncols,
 // LDS one column slice at a time.  The bitmap pass sets the row's column
 // bitmap and rank table in LDS (as k_num_rank does) and keeps a copy of the
 // bitmap in the workgroup's global scratch.  The row is then cut at
-// 256-column block boundaries into slices whose bitmap segment, segment
-// rank table and FP64 accumulator (one entry per output of the slice) fit
-// the same LDS together: a block costs 36 bytes plus 8 per output, and a
+// 256-column block boundaries into slices whose bitmap segment, rank of
+// every segment word and FP64 accumulator (one entry per output of the
+// slice) fit the same LDS together: a block costs 64 bytes plus 8 per
+// output, and a
 // slice takes the blocks whose running cost falls in one budget-sized
 // interval.  For each slice, every A entry's B row is searched for the
 // slice's column range, the products in it add into the accumulator with
 // LDS atomics, and the segment goes out in column order from the slice's
 // first output's position in C.  No atomic leaves LDS.
 constexpr int kSliceMax = 256;               // slices per row
-constexpr int kSliceBlockCost = 8 * 4 + 4 + 8 * 256;   // most bytes one 256-column block can need
+constexpr int kSliceBlockFixed = 8 * 4 + 8 * 4;          // a 256-column block's bitmap words and word ranks
+constexpr int kSliceBlockCost = kSliceBlockFixed + 8 * 256;   // most bytes one block can need
 
 __device__ __forceinline__ long long lower_bound_col(const int32_t* __restrict__ col, long long lo, long long hi,
                                                      long long c) {
@@ -2270,13 +2272,13 @@ k_num_slice(Work wk, long long ncols,
             long long tot;
             long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
             nrow = tot;
-            long long cost = 0;                         // this thread's blocks: 36 bytes + 8 per output
+            long long cost = 0;                         // this thread's blocks: 64 bytes + 8 per output
             for (long long i = i0; i < i1; ++i) {
                 r8[i] = (int)run;
                 long long c = 0;
                 for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
                 run += c;
-                cost += 36 + 8 * c;
+                cost += kSliceBlockFixed + 8 * c;
             }
             long long ctot;
             long long pc = block_incl_scan<BS>(cost, sm, &ctot) - cost;   // running cost before block i0
@@ -2284,7 +2286,7 @@ k_num_slice(Work wk, long long ncols,
                 const long long prev = pc;
                 long long c = 0;
                 for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
-                pc += 36 + 8 * c;
+                pc += kSliceBlockFixed + 8 * c;
                 const long long sid = (pc - 1) / budget;
                 if ((i == 0 || sid != (prev - 1) / budget) && sid < kSliceMax) {
                     s_sb[sid] = (int)i;
@@ -2316,26 +2318,26 @@ k_num_slice(Work wk, long long ncols,
         for (int sl = 0; sl < ns; ++sl) {
             const long long b0 = s_sb[sl], b1 = s_sb[sl + 1];
             const long long w0 = 8 * b0, w1 = 8 * b1 < words ? 8 * b1 : words;
-            const long long nw = w1 - w0, nb = b1 - b0;
+            const long long nw = w1 - w0;
             const long long c_lo = w0 * 32, c_hi = w1 * 32 < ncols ? w1 * 32 : ncols;
             uint32_t* sbm = dyn_smem;
-            int* sr8 = reinterpret_cast<int*>(dyn_smem + nw);
-            double* acc = reinterpret_cast<double*>(dyn_smem + ((nw + nb + 1) & ~1LL));
+            int* swr = reinterpret_cast<int*>(dyn_smem + nw);          // outputs before each segment word
+            double* acc = reinterpret_cast<double*>(dyn_smem + 2 * nw);
             __syncthreads();                           // the previous slice (or the full bitmap) is done with LDS
             for (long long w = tid; w < nw; w += BS) sbm[w] = gb[w0 + w];
             __syncthreads();
             long long nout;                            // outputs of the slice
             {
-                const long long E = (nb + BS - 1) / BS;
-                const long long i0 = (long long)tid * E, i1 = i0 + E < nb ? i0 + E : nb;
+                const long long E = (nw + BS - 1) / BS;
+                const long long i0 = (long long)tid * E, i1 = i0 + E < nw ? i0 + E : nw;
                 long long loc = 0;
-                for (long long w = 8 * i0; w < 8 * i1 && w < nw; ++w) loc += __builtin_popcount(sbm[w]);
+                for (long long w = i0; w < i1; ++w) loc += __builtin_popcount(sbm[w]);
                 long long tot;
                 long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
                 nout = tot;
-                for (long long i = i0; i < i1; ++i) {
-                    sr8[i] = (int)run;
-                    for (long long w = 8 * i; w < 8 * i + 8 && w < nw; ++w) run += __builtin_popcount(sbm[w]);
+                for (long long w = i0; w < i1; ++w) {
+                    swr[w] = (int)run;
+                    run += __builtin_popcount(sbm[w]);
                 }
             }
             for (long long r = tid; r < nout; r += BS) acc[r] = 0.0;
@@ -2386,9 +2388,7 @@ k_num_slice(Work wk, long long ncols,
                     for (int u = 0; u < RU; ++u) {
                         if (j[u] < 0) continue;
                         const int w = j[u] >> 5;
-                        int r = sr8[w >> 3];
-                        for (int x = w & ~7; x < w; ++x) r += __builtin_popcount(sbm[x]);
-                        r += __builtin_popcount(sbm[w] & ((1u << (j[u] & 31)) - 1u));
+                        const int r = swr[w] + __builtin_popcount(sbm[w] & ((1u << (j[u] & 31)) - 1u));
                         atomicAdd(&acc[r], pv[u]);
                     }
                 }

@@ -403,7 +403,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
             const long long lds = std::min(avail, rank_lds + 65536);
             const long long budget = lds - kSliceBlockCost - 16;
             if (rank_lds <= avail && budget > kSliceBlockCost &&
-                (36 * nr8 + 8 * n) / budget + 1 <= kSliceMax) {
+                (kSliceBlockFixed * nr8 + 8 * n) / budget + 1 <= kSliceMax) {
                 const int grid = std::max(1, std::min(rows, h->num_cu));
                 msp_status r = h->gsl.ensure((size_t)grid * (size_t)words * 4);
                 if (r != MSP_OK) return r;
