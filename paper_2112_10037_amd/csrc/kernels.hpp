@@ -2170,8 +2170,7 @@ k_num_rank(Work wk, long long ncols,
 
 // Rows of the global bin whose columns fit an LDS bitmap, accumulated in
 // LDS one column slice at a time.  The bitmap pass sets the row's column
-// bitmap and rank table in LDS (as k_num_rank does) and keeps a copy of the
-// bitmap in the workgroup's global scratch.  The row is then cut at
+// bitmap in LDS and keeps a copy of it in the workgroup's global scratch.  The row is then cut at
 // 256-column block boundaries into slices whose bitmap segment, rank of
 // every segment word and FP64 accumulator (one entry per output of the
 // slice) fit the same LDS together: a block costs 64 bytes plus 8 per
@@ -2181,6 +2180,7 @@ k_num_rank(Work wk, long long ncols,
 // slice's column range, the products in it add into the accumulator with
 // LDS atomics, and the segment goes out in column order from the slice's
 // first output's position in C.  No atomic leaves LDS.
+constexpr int kSliceBS = 1024;               // threads of the slice kernel
 constexpr int kSliceMax = 256;               // slices per row
 constexpr int kSliceBlockFixed = 8 * 4 + 8 * 4;          // a 256-column block's bitmap words and word ranks
 constexpr int kSliceBlockCost = kSliceBlockFixed + 8 * 256;   // most bytes one block can need
@@ -2217,14 +2217,13 @@ k_num_slice(Work wk, long long ncols,
     __shared__ int s_ns;
     const int tid = threadIdx.x;
     const long long words = (ncols + 31) >> 5;
-    const long long nr8 = (words + 7) >> 3;
+    const long long nr8 = (words + 7) >> 3;                   // 256-column blocks
     const long long budget = lds_bytes - kSliceBlockCost - 16;   // > kSliceBlockCost (host); 16: alignment pad
     uint32_t* gb = gbm + (long long)blockIdx.x * words;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long bo = row_boff<BATCH>(mp, row);
         uint32_t* bm = dyn_smem;
-        int* r8 = reinterpret_cast<int*>(dyn_smem + words);
         for (long long w = tid; w < words; w += BS) bm[w] = 0u;
         __syncthreads();
         const long long a0 = arp[row], a1 = arp[row + 1];
@@ -2262,26 +2261,19 @@ k_num_slice(Work wk, long long ncols,
             }
             __syncthreads();
         }
-        // rank table, the bitmap's copy, and the slices
+        // the bitmap's copy and the slices; a block costs F + 8 c bytes (c
+        // its outputs), so the outputs before block i are (cost before i -
+        // F i) / 8
         long long nrow;
         {
             const long long E = (nr8 + BS - 1) / BS;
             const long long i0 = (long long)tid * E, i1 = i0 + E < nr8 ? i0 + E : nr8;
             long long loc = 0;
             for (long long w = 8 * i0; w < 8 * i1 && w < words; ++w) loc += __builtin_popcount(bm[w]);
-            long long tot;
-            long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
-            nrow = tot;
-            long long cost = 0;                         // this thread's blocks: 64 bytes + 8 per output
-            for (long long i = i0; i < i1; ++i) {
-                r8[i] = (int)run;
-                long long c = 0;
-                for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
-                run += c;
-                cost += kSliceBlockFixed + 8 * c;
-            }
+            const long long cost = kSliceBlockFixed * (i1 > i0 ? i1 - i0 : 0) + 8 * loc;
             long long ctot;
             long long pc = block_incl_scan<BS>(cost, sm, &ctot) - cost;   // running cost before block i0
+            nrow = (ctot - kSliceBlockFixed * nr8) / 8;
             for (long long i = i0; i < i1; ++i) {
                 const long long prev = pc;
                 long long c = 0;
@@ -2290,7 +2282,7 @@ k_num_slice(Work wk, long long ncols,
                 const long long sid = (pc - 1) / budget;
                 if ((i == 0 || sid != (prev - 1) / budget) && sid < kSliceMax) {
                     s_sb[sid] = (int)i;
-                    s_sr[sid] = r8[i];
+                    s_sr[sid] = (int)((prev - kSliceBlockFixed * i) / 8);
                 }
             }
             if (tid == 0) {

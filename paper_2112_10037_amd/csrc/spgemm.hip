@@ -126,7 +126,7 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
 // ---------------------------------------------------------------------------
 constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense kernels
 constexpr int kRankReserve = 13 * 1024;    // static LDS of k_num_rank<kRankBS>
-constexpr int kSliceReserve = 15 * 1024;   // static LDS of k_num_slice<kRankBS>
+constexpr int kSliceReserve = 27 * 1024;   // static LDS of k_num_slice<kSliceBS>
 #ifndef MSP_NUM_SLICE
 #define MSP_NUM_SLICE 1
 #endif
@@ -225,8 +225,8 @@ msp_status configure_kernels(msp_handle* h) {
         }
     }
     const int dyn_slice = std::max(0, h->lds_per_block - kSliceReserve);
-    void* slice_fns[] = {(void*)k_num_slice<kRankBS, float, false>, (void*)k_num_slice<kRankBS, double, false>,
-                         (void*)k_num_slice<kRankBS, float, true>, (void*)k_num_slice<kRankBS, double, true>};
+    void* slice_fns[] = {(void*)k_num_slice<kSliceBS, float, false>, (void*)k_num_slice<kSliceBS, double, false>,
+                         (void*)k_num_slice<kSliceBS, float, true>, (void*)k_num_slice<kSliceBS, double, true>};
     for (void* f : slice_fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_slice);
         if (e != hipSuccess) {
@@ -398,16 +398,16 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
             // the columns fit an LDS bitmap with its rank table: accumulate
             // in LDS slice by slice
             const long long nr8 = (words + 7) / 8;
-            const long long rank_lds = words * 4 + nr8 * 4;
+            const long long bm_lds = words * 4;
             const long long avail = h->lds_per_block - kSliceReserve;
-            const long long lds = std::min(avail, rank_lds + 65536);
+            const long long lds = std::min(avail, bm_lds + 65536);
             const long long budget = lds - kSliceBlockCost - 16;
-            if (rank_lds <= avail && budget > kSliceBlockCost &&
+            if (bm_lds <= avail && budget > kSliceBlockCost &&
                 (kSliceBlockFixed * nr8 + 8 * n) / budget + 1 <= kSliceMax) {
                 const int grid = std::max(1, std::min(rows, h->num_cu));
                 msp_status r = h->gsl.ensure((size_t)grid * (size_t)words * 4);
                 if (r != MSP_OK) return r;
-                k_num_slice<kRankBS, VT, BATCH><<<grid, kRankBS, (size_t)lds, st>>>(
+                k_num_slice<kSliceBS, VT, BATCH><<<grid, kSliceBS, (size_t)lds, st>>>(
                     wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->gsl.as<uint32_t>(), lds,
                     cnt_out, info, mp);
                 return launch_check("k_num_slice");
