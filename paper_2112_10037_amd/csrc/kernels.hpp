@@ -1988,185 +1988,9 @@ k_num_dense(Work wk, long long ncols,
     }
 }
 
-// Rows of the global bin whose columns fit an LDS bitmap: output positions
-// by rank.  Pass 1 sets the row's column bitmap in LDS and a table of set
-// bits before every 8th bitmap word follows.  Pass 2 adds every product at
-// its column's rank in a compact FP64 accumulator, the workgroup's own: the
-// row touches nnz(C row) consecutive entries, all of them used, which the
-// caches keep, where a column-indexed slab would scatter the same atomics
-// over ncols.  The bitmap is then walked in column order and each column
-// goes out with the value at its rank, the accumulator returning to zero.
-constexpr int kRankBS = 512;
-constexpr int kRankUnroll = 4;             // products per thread and round (R-MAT 2^20: 769 -> 741 ms)
-
-template <int BS, typename VT, bool BATCH = false>
-__global__ void __launch_bounds__(BS)
-k_num_rank(Work wk, long long ncols,
-           const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
-           const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
-           const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-           double* dslab, int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
-    int nrows_bin;
-    const int32_t* perm;
-    work_rows(wk, &nrows_bin, &perm);
-    constexpr int RU = kRankUnroll;
-    extern __shared__ uint32_t dyn_smem[];      // bitmap words, then the rank table
-    __shared__ long long s_off[BS];
-    __shared__ long long s_bst[BS];
-    __shared__ double s_a[BS];
-    __shared__ BlockScanSmem<BS> sm;
-    const int tid = threadIdx.x;
-    const long long words = (ncols + 31) >> 5;
-    const long long nr8 = (words + 7) >> 3;
-    uint32_t* bm = dyn_smem;
-    int* r8 = reinterpret_cast<int*>(dyn_smem + words);
-    double* acc = dslab + (long long)blockIdx.x * ncols;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
-        const int row = perm ? perm[slot] : (int)slot;
-        const long long bo = row_boff<BATCH>(mp, row);
-        for (long long w = tid; w < words; w += BS) bm[w] = 0u;
-        __syncthreads();
-        const long long a0 = arp[row], a1 = arp[row + 1];
-        // pass 1: the row's columns
-        for (long long c0 = a0; c0 < a1; c0 += BS) {
-            const long long p = c0 + tid;
-            long long len = 0, bst = 0;
-            if (p < a1) {
-                const long long k = acol[p] + bo;
-                bst = brp[k];
-                len = brp[k + 1] - bst;
-            }
-            long long total;
-            const long long incl = block_incl_scan<BS>(len, sm, &total);
-            s_off[tid] = incl;
-            s_bst[tid] = bst - (incl - len);
-            __syncthreads();
-            const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
-            int t = -1;                         // owner of q: one search, then it only moves forward
-            // RU products per thread and round, their loads issued before
-            // any is used: one workgroup per compute unit leaves few waves
-            // to hide the gathers' latency
-            for (long long q0 = tid; q0 < total; q0 += RU * BS) {
-                int32_t j[RU];
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const long long q = q0 + (long long)u * BS;
-                    j[u] = -1;
-                    if (q < total) {
-                        if (t < 0) t = owner_search(s_off, nact, q);
-                        else while (s_off[t] <= q) ++t;
-                        j[u] = bcol[s_bst[t] + q];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < RU; ++u)
-                    if (j[u] >= 0) atomicOr(&bm[j[u] >> 5], 1u << (j[u] & 31));
-            }
-            __syncthreads();
-        }
-        // rank table: r8[i] = set bits in words [0, 8 i); thread tid takes
-        // the entries [tid E, tid E + E)
-        {
-            const long long E = (nr8 + BS - 1) / BS;
-            const long long i0 = (long long)tid * E, i1 = i0 + E < nr8 ? i0 + E : nr8;
-            long long loc = 0;
-            for (long long w = 8 * i0; w < 8 * i1 && w < words; ++w) loc += __builtin_popcount(bm[w]);
-            long long tot;
-            long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
-            for (long long i = i0; i < i1; ++i) {
-                r8[i] = (int)run;
-                for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) run += __builtin_popcount(bm[w]);
-            }
-        }
-        __syncthreads();
-        // pass 2: every product at its column's rank
-        for (long long c0 = a0; c0 < a1; c0 += BS) {
-            const long long p = c0 + tid;
-            long long len = 0, bst = 0;
-            double a = 0.0;
-            if (p < a1) {
-                const long long k = acol[p] + bo;
-                a = to_f64(aval[p]);
-                bst = brp[k];
-                len = brp[k + 1] - bst;
-            }
-            long long total;
-            const long long incl = block_incl_scan<BS>(len, sm, &total);
-            s_off[tid] = incl;
-            s_bst[tid] = bst - (incl - len);
-            s_a[tid] = a;
-            __syncthreads();
-            const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
-            int t = -1;
-            for (long long q0 = tid; q0 < total; q0 += RU * BS) {
-                int32_t j[RU];
-                double pv[RU];
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const long long q = q0 + (long long)u * BS;
-                    j[u] = -1;
-                    pv[u] = 0.0;
-                    if (q < total) {
-                        if (t < 0) t = owner_search(s_off, nact, q);
-                        else while (s_off[t] <= q) ++t;
-                        const long long bi = s_bst[t] + q;
-                        j[u] = bcol[bi];
-                        pv[u] = s_a[t] * to_f64(bval[bi]);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    if (j[u] < 0) continue;
-                    const int w = j[u] >> 5;
-                    int r = r8[w >> 3];
-                    for (int x = w & ~7; x < w; ++x) r += __builtin_popcount(bm[x]);
-                    r += __builtin_popcount(bm[w] & ((1u << (j[u] & 31)) - 1u));
-                    __hip_atomic_fetch_add(&acc[r], pv[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-            __syncthreads();
-        }
-        // output in column order: wave wv walks the words [wv WS, wv WS + WS)
-        const long long rp = crp[row];
-        const long long rend = crp[row + 1];
-        constexpr int NW = BS / 64;
-        const int wv = tid >> 6, ln = tid & 63;
-        const long long WS = (words + NW - 1) / NW;
-        const long long wb = (long long)wv * WS, we = wb + WS < words ? wb + WS : words;
-        long long wc = 0;
-        for (long long w = wb + ln; w < we; w += 64) wc += __builtin_popcount(bm[w]);
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) wc += __shfl_xor(wc, d);
-        long long run;
-        const long long wincl = block_incl_scan<BS>(ln == 0 ? wc : 0, sm, &run);
-        long long r0 = __shfl(wincl, 0) - wc;          // rank of the wave's first column
-        for (long long w0 = wb; w0 < we; w0 += 64) {
-            const long long w = w0 + ln;
-            uint32_t bits = w < we ? bm[w] : 0u;
-            const long long c = __builtin_popcount(bits);
-            const long long incl = group_incl_scan<64>(c, ln);
-            long long r = r0 + incl - c;
-            r0 += __shfl(incl, 63);
-            while (bits) {
-                const int b = __builtin_ctz(bits);
-                bits &= bits - 1;
-                const double v = __hip_atomic_load(&acc[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (rp + r < rend) {
-                    ccol[rp + r] = (int32_t)(w * 32 + b);
-                    cval[rp + r] = (VT)v;
-                }
-                acc[r] = 0.0;
-                ++r;
-            }
-        }
-        if (tid == 0) {
-            const long long cap = rend - rp;
-            if (cnt_out) cnt_out[row] = run <= cap ? (int)run : -1;
-            else if (run != cap) atomicOr(&info->err, kErrCount);
-        }
-        __syncthreads();
-    }
-}
+// Products each thread of the slice kernel loads before using any: one
+// workgroup per compute unit leaves few waves to hide the gathers.
+constexpr int kProductUnroll = 4;
 
 // Rows of the global bin whose columns fit an LDS bitmap, accumulated in
 // LDS one column slice at a time.  The bitmap pass sets the row's column
@@ -2205,7 +2029,7 @@ k_num_slice(Work wk, long long ncols,
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
-    constexpr int RU = kRankUnroll;
+    constexpr int RU = kProductUnroll;
     extern __shared__ __align__(16) uint32_t dyn_slice[];   // bitmap and rank table; then a slice's segment and accumulator
     uint32_t* const dyn_smem = dyn_slice;
     __shared__ long long s_off[BS];

@@ -125,11 +125,7 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
 // kernel tables
 // ---------------------------------------------------------------------------
 constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense kernels
-constexpr int kRankReserve = 13 * 1024;    // static LDS of k_num_rank<kRankBS>
 constexpr int kSliceReserve = 27 * 1024;   // static LDS of k_num_slice<kSliceBS>
-#ifndef MSP_NUM_SLICE
-#define MSP_NUM_SLICE 1
-#endif
 
 #define MSP_GROUP_SHAPES(X) \
     X(8, 32) X(16, 32) X(8, 64) X(16, 64) X(32, 64) X(16, 128) X(32, 128) X(64, 128) \
@@ -204,21 +200,11 @@ static void* dense_kernel(bool lds) {
 msp_status configure_kernels(msp_handle* h) {
     // allow the bitmap kernels the device's full LDS for their dynamic part
     const int dyn = std::max(0, h->lds_per_block - kLdsReserve);
-    const int dyn_rank = std::max(0, h->lds_per_block - kRankReserve);
     void* fns[] = {(void*)k_sym_bitmap<1024, true, false>, (void*)k_sym_bitmap<1024, true, true>,
                    dense_kernel<float, false>(true), dense_kernel<double, false>(true),
                    dense_kernel<float, true>(true), dense_kernel<double, true>(true)};
-    void* rank_fns[] = {(void*)k_num_rank<kRankBS, float, false>, (void*)k_num_rank<kRankBS, double, false>,
-                        (void*)k_num_rank<kRankBS, float, true>, (void*)k_num_rank<kRankBS, double, true>};
     for (void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
-        }
-    }
-    for (void* f : rank_fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
@@ -393,10 +379,8 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
     } else if (s.kind == Kind::Dense) {
         const long long n = op.ncols;
         const long long words = (n + 31) / 32;
-#if MSP_NUM_SLICE
         {
-            // the columns fit an LDS bitmap with its rank table: accumulate
-            // in LDS slice by slice
+            // the columns fit an LDS bitmap: accumulate in LDS slice by slice
             const long long nr8 = (words + 7) / 8;
             const long long bm_lds = words * 4;
             const long long avail = h->lds_per_block - kSliceReserve;
@@ -413,7 +397,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
                 return launch_check("k_num_slice");
             }
         }
-#endif
+        // too wide for an LDS bitmap beside the slices: per-workgroup FP64 slab
         const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
         // one slab per resident workgroup; keep the arena under 16 GiB
         long long cap = (16LL << 30) / std::max(1LL, n * 8);
@@ -434,15 +418,6 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
             h->dslab_count = nslab;
         }
         const int grid = std::min(rows, nslab);
-        // the columns fit an LDS bitmap with its rank table: compact
-        // accumulator indexed by rank
-        const long long rank_lds = words * 4 + ((words + 7) / 8) * 4;
-        if (rank_lds <= h->lds_per_block - kRankReserve) {
-            k_num_rank<kRankBS, VT, BATCH><<<grid, kRankBS, rank_lds, st>>>(
-                wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->dslab.as<double>(), cnt_out,
-                info, mp);
-            return launch_check("k_num_rank");
-        }
         if (lds)
             k_num_dense<1024, true, VT, BATCH><<<grid, 1024, words * 4, st>>>(
                 wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->dslab.as<double>(), nullptr,
