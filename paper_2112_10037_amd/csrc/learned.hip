@@ -98,8 +98,11 @@ k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ h
             c = c < l ? l : c;
             // the exact bound costs nothing more when it keeps the row in
             // the same numeric bin (same kernel, same accumulator): only
-            // unused padding, which the compaction never reads
-            if (nt.nb > 0 && bin_of(nt, c) == bin_of(nt, h)) c = h;
+            // unused padding, which the compaction never reads; and it
+            // costs at most twice the predicted room when it is within a
+            // factor 2, where a row just above the prediction would
+            // otherwise overflow into the exact recomputation
+            if ((long long)h <= 2LL * c || (nt.nb > 0 && bin_of(nt, c) == bin_of(nt, h))) c = h;
         }
         cap[r] = c;
         if (c == 0) cnt[r] = 0;

@@ -192,7 +192,7 @@ def test_bad_batch_index_is_an_error(h):
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_learned_forced_spill_uses_global_bin(h, dtype):
     """Every row in the global bin (force_spill): the capacity-mode numeric
-    pass runs in the rank-indexed global kernel; with the same-bin rule each
+    pass runs in the sliced global kernel; with the same-bin rule each
     capacity is the row's bound, so no row overflows, and the result equals
     the oracle's."""
     params = gen.mlp_init(37).astype(np.float32)
