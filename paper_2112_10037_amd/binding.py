@@ -226,6 +226,7 @@ class Handle:
         self._stream = s
         _check(self._lib.msp_create(ctypes.byref(self._h), device, ctypes.c_void_p(s.cuda_stream)))
         self._live = {}
+        self._same_stream = None
         self._alloc_cb = ALLOC_FN(self._alloc)
         self._free_cb = FREE_FN(self._free)
         _check(self._lib.msp_set_allocator(self._h, self._alloc_cb, self._free_cb, None))
@@ -240,7 +241,12 @@ class Handle:
         # torch files the block under its current stream; when the library
         # queues on another one, the block is also marked in use there, so
         # that it is not handed out again before that stream's work is done
-        if self._torch.cuda.current_stream(self.device).cuda_stream != (stream or 0):
+        # (the product entry points compare the streams before the call,
+        # while the GPU may still be busy, and leave the answer here)
+        same = self._same_stream
+        if same is None:
+            same = self._torch.cuda.current_stream(self.device).cuda_stream == (stream or 0)
+        if not same:
             t.record_stream(self._stream)
         p = t.data_ptr()
         self._live[p] = t
@@ -254,6 +260,23 @@ class Handle:
 
     def _free(self, ctx, ptr, stream):
         self._live.pop(ptr, None)
+
+    def _begin(self):
+        """Compare torch's current stream with the handle's once per call,
+        before the call (while the GPU may still be busy); every allocation
+        of the call uses the answer."""
+        self._same_stream = (self._torch.cuda.current_stream(self.device).cuda_stream ==
+                             (self._stream.cuda_stream or 0))
+
+    def _end(self):
+        self._same_stream = None
+
+    def _empty(self, shape, dtype):
+        """An output tensor the library writes on the handle's stream."""
+        t = self._torch.empty(shape, dtype=dtype, device=f"cuda:{self.device}")
+        if not self._same_stream:
+            t.record_stream(self._stream)
+        return t
 
     def _take_c(self, ptr, nnz, vdtype):
         """Column and value views of C's single allocation (values start at
@@ -316,12 +339,15 @@ class Handle:
         torch = self._torch
         a, b = A.c(), B.c()
         out = c_csr_out()
-        rp = row_ptr if row_ptr is not None else torch.empty(A.nrows + 1, dtype=torch.int64,
-                                                              device=f"cuda:{self.device}")
-        out.row_ptr = rp.data_ptr()
-        o = _opts(validate, force_spill, tuning)
-        _check(self._lib.msp_spgemm(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(out),
-                                    ctypes.byref(o)))
+        self._begin()
+        try:
+            rp = row_ptr if row_ptr is not None else self._empty(A.nrows + 1, torch.int64)
+            out.row_ptr = rp.data_ptr()
+            o = _opts(validate, force_spill, tuning)
+            _check(self._lib.msp_spgemm(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(out),
+                                        ctypes.byref(o)))
+        finally:
+            self._end()
         nnz = int(out.nnz)
         vdt = torch.float64 if out.dtype == MSP_F64 else torch.float32
         if nnz > 0:
@@ -339,12 +365,16 @@ class Handle:
         torch = self._torch
         a, b = A.c(), B.c()
         out = c_csr_out()
-        rp = torch.empty(A.nrows + 1, dtype=torch.int64, device=f"cuda:{self.device}")
-        out.row_ptr = rp.data_ptr()
-        st = c_learned_stats()
-        o = _opts(validate, force_spill, tuning)
-        _check(self._lib.msp_spgemm_learned(self._h, pred._p, ctypes.byref(a), ctypes.byref(b),
-                                            ctypes.byref(out), ctypes.byref(o), ctypes.byref(st)))
+        self._begin()
+        try:
+            rp = self._empty(A.nrows + 1, torch.int64)
+            out.row_ptr = rp.data_ptr()
+            st = c_learned_stats()
+            o = _opts(validate, force_spill, tuning)
+            _check(self._lib.msp_spgemm_learned(self._h, pred._p, ctypes.byref(a), ctypes.byref(b),
+                                                ctypes.byref(out), ctypes.byref(o), ctypes.byref(st)))
+        finally:
+            self._end()
         nnz = int(out.nnz)
         vdt = torch.float64 if out.dtype == MSP_F64 else torch.float32
         if nnz > 0:
@@ -362,38 +392,50 @@ class Handle:
         into the given tensors (views into a larger training set) if any."""
         torch = self._torch
         m = A.nrows
-        if feats is None:
-            feats = torch.empty((max(m, 1), 8), dtype=torch.float32, device=f"cuda:{self.device}")
-        if targets is None:
-            targets = torch.empty(max(m, 1), dtype=torch.float32, device=f"cuda:{self.device}")
-        a, b = A.c(), B.c()
-        _check(self._lib.msp_training_rows(self._h, ctypes.byref(a), ctypes.byref(b),
-                                           ctypes.c_void_p(feats.data_ptr()),
-                                           ctypes.c_void_p(targets.data_ptr())))
+        self._begin()
+        try:
+            if feats is None:
+                feats = self._empty((max(m, 1), 8), torch.float32)
+            if targets is None:
+                targets = self._empty(max(m, 1), torch.float32)
+            a, b = A.c(), B.c()
+            _check(self._lib.msp_training_rows(self._h, ctypes.byref(a), ctypes.byref(b),
+                                               ctypes.c_void_p(feats.data_ptr()),
+                                               ctypes.c_void_p(targets.data_ptr())))
+        finally:
+            self._end()
         return feats[:m], targets[:m]
 
     def symbolic(self, A: DeviceCSR, B: DeviceCSR, validate=False, force_spill=False, tuning=None):
         """(row_nnz int32 tensor, nnz(C)) from the symbolic pass alone."""
         torch = self._torch
         a, b = A.c(), B.c()
-        rn = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=f"cuda:{self.device}")
-        tot = ctypes.c_int64()
-        o = _opts(validate, force_spill, tuning)
-        _check(self._lib.msp_spgemm_symbolic(self._h, ctypes.byref(a), ctypes.byref(b),
-                                             ctypes.c_void_p(rn.data_ptr()), ctypes.byref(tot),
-                                             ctypes.byref(o)))
+        self._begin()
+        try:
+            rn = self._empty(max(A.nrows, 1), torch.int32)
+            tot = ctypes.c_int64()
+            o = _opts(validate, force_spill, tuning)
+            _check(self._lib.msp_spgemm_symbolic(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                 ctypes.c_void_p(rn.data_ptr()), ctypes.byref(tot),
+                                                 ctypes.byref(o)))
+        finally:
+            self._end()
         return rn[: A.nrows], int(tot.value)
 
     def row_features(self, A: DeviceCSR, B: DeviceCSR):
         """(prod int64 [m], features float32 [m, 8])."""
         torch = self._torch
         m = A.nrows
-        prod = torch.empty(max(m, 1), dtype=torch.int64, device=f"cuda:{self.device}")
-        feat = torch.empty((max(m, 1), 8), dtype=torch.float32, device=f"cuda:{self.device}")
-        a, b = A.c(), B.c()
-        _check(self._lib.msp_row_features(self._h, ctypes.byref(a), ctypes.byref(b),
-                                          ctypes.c_void_p(prod.data_ptr()),
-                                          ctypes.c_void_p(feat.data_ptr())))
+        self._begin()
+        try:
+            prod = self._empty(max(m, 1), torch.int64)
+            feat = self._empty((max(m, 1), 8), torch.float32)
+            a, b = A.c(), B.c()
+            _check(self._lib.msp_row_features(self._h, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.c_void_p(prod.data_ptr()),
+                                              ctypes.c_void_p(feat.data_ptr())))
+        finally:
+            self._end()
         return prod[:m], feat[:m]
 
 
@@ -459,9 +501,13 @@ class Predictor:
 
     def infer(self, feats):
         import torch
-        y = torch.empty(max(feats.shape[0], 1), dtype=torch.float32, device=feats.device)
-        _check(self._lib.msp_predictor_infer(self.h._h, self._p, feats.data_ptr(), feats.shape[0],
-                                             y.data_ptr()))
+        self.h._begin()
+        try:
+            y = self.h._empty(max(feats.shape[0], 1), torch.float32)
+            _check(self._lib.msp_predictor_infer(self.h._h, self._p, feats.data_ptr(), feats.shape[0],
+                                                 y.data_ptr()))
+        finally:
+            self.h._end()
         return y[: feats.shape[0]]
 
     def calibrate(self, feats, targets, q=0.99):
