@@ -591,16 +591,32 @@ k_sym_bitmap(Work wk, long long ncols,
             __syncthreads();
             const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
             int t = -1;                     // owner of q: one search, then it only moves forward
-            for (long long q = tid; q < total; q += BS) {
-                if (t < 0) t = owner_search(s_off, nact, q);
-                else while ((long long)s_off[t] <= q) ++t;
-                const int32_t j = bcol[s_bst[t] + q];
-                const uint32_t bit = 1u << (j & 31);
-                // the slab is this workgroup's own: workgroup scope suffices
-                const uint32_t old = LDSBM ? atomicOr(&bm[j >> 5], bit)
-                                           : __hip_atomic_fetch_or(&bm[j >> 5], bit, __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                cnt += (old & bit) ? 0 : 1;
+            // SU products per thread and round, their loads issued before any
+            // is used: one workgroup per compute unit leaves few waves to hide
+            // the gathers
+            constexpr int SU = 4;
+            for (long long q0 = tid; q0 < total; q0 += SU * BS) {
+                int32_t j[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const long long q = q0 + (long long)u * BS;
+                    j[u] = -1;
+                    if (q < total) {
+                        if (t < 0) t = owner_search(s_off, nact, q);
+                        else while ((long long)s_off[t] <= q) ++t;
+                        j[u] = bcol[s_bst[t] + q];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    if (j[u] < 0) continue;
+                    const uint32_t bit = 1u << (j[u] & 31);
+                    // the slab is this workgroup's own: workgroup scope suffices
+                    const uint32_t old = LDSBM ? atomicOr(&bm[j[u] >> 5], bit)
+                                               : __hip_atomic_fetch_or(&bm[j[u] >> 5], bit, __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                    cnt += (old & bit) ? 0 : 1;
+                }
             }
             __syncthreads();
         }
