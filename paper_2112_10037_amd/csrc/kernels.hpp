@@ -2034,9 +2034,9 @@ __device__ __forceinline__ long long lower_bound_col(const int32_t* __restrict__
     return lo;
 }
 
-template <int BS, typename VT, bool BATCH = false>
+template <int BS, typename VT, bool BATCH = false, bool MULTI = false>
 __global__ void __launch_bounds__(BS)
-k_num_slice(Work wk, long long ncols,
+k_num_slice(Work wk, long long ncols, long long span,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
@@ -2046,7 +2046,7 @@ k_num_slice(Work wk, long long ncols,
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
     constexpr int RU = kProductUnroll;
-    extern __shared__ __align__(16) uint32_t dyn_slice[];   // bitmap and rank table; then a slice's segment and accumulator
+    extern __shared__ __align__(16) uint32_t dyn_slice[];   // bitmap; then a slice's segment and accumulator
     uint32_t* const dyn_smem = dyn_slice;
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -2056,139 +2056,45 @@ k_num_slice(Work wk, long long ncols,
     __shared__ int s_sr[kSliceMax];             // rank of each slice's first output
     __shared__ int s_ns;
     const int tid = threadIdx.x;
-    const long long words = (ncols + 31) >> 5;
-    const long long nr8 = (words + 7) >> 3;                   // 256-column blocks
     const long long budget = lds_bytes - kSliceBlockCost - 16;   // > kSliceBlockCost (host); 16: alignment pad
-    uint32_t* gb = gbm + (long long)blockIdx.x * words;
+    const long long span_words = (span + 31) >> 5;
+    uint32_t* gb = gbm + (long long)blockIdx.x * span_words;
     for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long bo = row_boff<BATCH>(mp, row);
-        uint32_t* bm = dyn_smem;
-        for (long long w = tid; w < words; w += BS) bm[w] = 0u;
-        __syncthreads();
         const long long a0 = arp[row], a1 = arp[row + 1];
-        // bitmap pass: the row's columns
-        for (long long c0 = a0; c0 < a1; c0 += BS) {
-            const long long p = c0 + tid;
-            long long len = 0, bst = 0;
-            if (p < a1) {
-                const long long k = acol[p] + bo;
-                bst = brp[k];
-                len = brp[k + 1] - bst;
-            }
-            long long total;
-            const long long incl = block_incl_scan<BS>(len, sm, &total);
-            s_off[tid] = incl;
-            s_bst[tid] = bst - (incl - len);
-            __syncthreads();
-            const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
-            int t = -1;
-            for (long long q0 = tid; q0 < total; q0 += RU * BS) {
-                int32_t j[RU];
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const long long q = q0 + (long long)u * BS;
-                    j[u] = -1;
-                    if (q < total) {
-                        if (t < 0) t = owner_search(s_off, nact, q);
-                        else while (s_off[t] <= q) ++t;
-                        j[u] = bcol[s_bst[t] + q];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < RU; ++u)
-                    if (j[u] >= 0) atomicOr(&bm[j[u] >> 5], 1u << (j[u] & 31));
-            }
-            __syncthreads();
-        }
-        // the bitmap's copy and the slices; a block costs F + 8 c bytes (c
-        // its outputs), so the outputs before block i are (cost before i -
-        // F i) / 8
-        long long nrow;
-        {
-            const long long E = (nr8 + BS - 1) / BS;
-            const long long i0 = (long long)tid * E, i1 = i0 + E < nr8 ? i0 + E : nr8;
-            long long loc = 0;
-            for (long long w = 8 * i0; w < 8 * i1 && w < words; ++w) loc += __builtin_popcount(bm[w]);
-            const long long cost = kSliceBlockFixed * (i1 > i0 ? i1 - i0 : 0) + 8 * loc;
-            long long ctot;
-            long long pc = block_incl_scan<BS>(cost, sm, &ctot) - cost;   // running cost before block i0
-            nrow = (ctot - kSliceBlockFixed * nr8) / 8;
-            for (long long i = i0; i < i1; ++i) {
-                const long long prev = pc;
-                long long c = 0;
-                for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
-                pc += kSliceBlockFixed + 8 * c;
-                const long long sid = (pc - 1) / budget;
-                if ((i == 0 || sid != (prev - 1) / budget) && sid < kSliceMax) {
-                    s_sb[sid] = (int)i;
-                    s_sr[sid] = (int)((prev - kSliceBlockFixed * i) / 8);
-                }
-            }
-            if (tid == 0) {
-                const long long n = nr8 > 0 ? (ctot - 1) / budget + 1 : 0;
-                s_ns = n <= kSliceMax ? (int)n : -1;
-                if (n <= kSliceMax) s_sb[n] = (int)nr8;
-            }
-            for (long long w = tid; w < words; w += BS) gb[w] = bm[w];
-        }
-        __syncthreads();
-        const int ns = s_ns;
         const long long rp = crp[row];
         const long long rend = crp[row + 1];
-        if (ns < 0) {
-            if (tid == 0) {
-                if (cnt_out) cnt_out[row] = -1;
-                else atomicOr(&info->err, kErrCount);
-            }
-            continue;                                  // uniform; the host bounds the slice count
-        }
-        // a row whose A entries fit one chunk keeps each entry's B-row
-        // position where the previous slice ended: one search per slice
+        // a row whose A entries fit one chunk keeps, per thread, its entry's
+        // B-row range in the current super-range and the position where the
+        // previous slice ended: one search per slice and super-range
         const bool one_chunk = a1 - a0 <= BS;
-        long long cur = -1;
-        for (int sl = 0; sl < ns; ++sl) {
-            const long long b0 = s_sb[sl], b1 = s_sb[sl + 1];
-            const long long w0 = 8 * b0, w1 = 8 * b1 < words ? 8 * b1 : words;
-            const long long nw = w1 - w0;
-            const long long c_lo = w0 * 32, c_hi = w1 * 32 < ncols ? w1 * 32 : ncols;
-            uint32_t* sbm = dyn_smem;
-            int* swr = reinterpret_cast<int*>(dyn_smem + nw);          // outputs before each segment word
-            double* acc = reinterpret_cast<double*>(dyn_smem + 2 * nw);
-            __syncthreads();                           // the previous slice (or the full bitmap) is done with LDS
-            for (long long w = tid; w < nw; w += BS) sbm[w] = gb[w0 + w];
+        long long sr_lo = -1, sr_hi = -1, cur = -1;
+        long long done = 0;                            // outputs of the super-ranges before
+        bool bad = false;
+        // Column super-ranges [C0, C1) whose bitmap fits the LDS; the
+        // instance for ncols <= span (MULTI false) takes all columns at once
+        for (long long C0 = 0; C0 < ncols && !bad; C0 += span) {
+            const long long C1 = MULTI && C0 + span < ncols ? C0 + span : ncols;
+            const bool whole = !MULTI || (C0 == 0 && C1 == ncols);
+            const long long words = (C1 - C0 + 31) >> 5;
+            const long long nr8 = (words + 7) >> 3;    // 256-column blocks
+            uint32_t* bm = dyn_smem;
+            __syncthreads();                           // the previous super-range is done with LDS
+            for (long long w = tid; w < words; w += BS) bm[w] = 0u;
             __syncthreads();
-            long long nout;                            // outputs of the slice
-            {
-                const long long E = (nw + BS - 1) / BS;
-                const long long i0 = (long long)tid * E, i1 = i0 + E < nw ? i0 + E : nw;
-                long long loc = 0;
-                for (long long w = i0; w < i1; ++w) loc += __builtin_popcount(sbm[w]);
-                long long tot;
-                long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
-                nout = tot;
-                for (long long w = i0; w < i1; ++w) {
-                    swr[w] = (int)run;
-                    run += __builtin_popcount(sbm[w]);
-                }
-            }
-            for (long long r = tid; r < nout; r += BS) acc[r] = 0.0;
-            __syncthreads();
-            // the products whose columns fall in [c_lo, c_hi)
+            // bitmap pass: the row's columns in [C0, C1)
             for (long long c0 = a0; c0 < a1; c0 += BS) {
                 const long long p = c0 + tid;
                 long long len = 0, bst = 0;
-                double a = 0.0;
                 if (p < a1) {
                     const long long k = acol[p] + bo;
-                    a = to_f64(aval[p]);
                     long long lo = brp[k], hi = brp[k + 1];
-                    if (ns > 1) {
-                        if (one_chunk && cur >= 0) lo = cur;
-                        else lo = lower_bound_col(bcol, lo, hi, c_lo);
-                        hi = sl + 1 < ns ? lower_bound_col(bcol, lo, hi, c_hi) : hi;
-                        if (one_chunk) cur = hi;
+                    if (!whole) {
+                        lo = one_chunk && sr_hi >= 0 ? sr_hi : lower_bound_col(bcol, lo, hi, C0);
+                        if (C1 < ncols) hi = lower_bound_col(bcol, lo, hi, C1);
                     }
+                    if (one_chunk) { sr_lo = lo; sr_hi = hi; }
                     bst = lo;
                     len = hi - lo;
                 }
@@ -2196,71 +2102,183 @@ k_num_slice(Work wk, long long ncols,
                 const long long incl = block_incl_scan<BS>(len, sm, &total);
                 s_off[tid] = incl;
                 s_bst[tid] = bst - (incl - len);
-                s_a[tid] = a;
                 __syncthreads();
                 const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
                 int t = -1;
                 for (long long q0 = tid; q0 < total; q0 += RU * BS) {
                     int32_t j[RU];
-                    double pv[RU];
 #pragma unroll
                     for (int u = 0; u < RU; ++u) {
                         const long long q = q0 + (long long)u * BS;
                         j[u] = -1;
-                        pv[u] = 0.0;
                         if (q < total) {
                             if (t < 0) t = owner_search(s_off, nact, q);
                             else while (s_off[t] <= q) ++t;
-                            const long long bi = s_bst[t] + q;
-                            j[u] = (int32_t)(bcol[bi] - c_lo);
-                            pv[u] = s_a[t] * to_f64(bval[bi]);
+                            j[u] = (int32_t)(bcol[s_bst[t] + q] - C0);
                         }
                     }
 #pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-                        if (j[u] < 0) continue;
-                        const int w = j[u] >> 5;
-                        const int r = swr[w] + __builtin_popcount(sbm[w] & ((1u << (j[u] & 31)) - 1u));
-                        atomicAdd(&acc[r], pv[u]);
-                    }
+                    for (int u = 0; u < RU; ++u)
+                        if (j[u] >= 0) atomicOr(&bm[j[u] >> 5], 1u << (j[u] & 31));
                 }
                 __syncthreads();
             }
-            // the slice in column order: wave wv walks the segment words [wv WS, wv WS + WS)
-            const long long base = rp + s_sr[sl];
-            constexpr int NW = BS / 64;
-            const int wv = tid >> 6, ln = tid & 63;
-            const long long WS = (nw + NW - 1) / NW;
-            const long long wb = (long long)wv * WS, we = wb + WS < nw ? wb + WS : nw;
-            long long wc = 0;
-            for (long long w = wb + ln; w < we; w += 64) wc += __builtin_popcount(sbm[w]);
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1) wc += __shfl_xor(wc, d);
-            long long run;
-            const long long wincl = block_incl_scan<BS>(ln == 0 ? wc : 0, sm, &run);
-            long long r0 = __shfl(wincl, 0) - wc;      // rank in the slice of the wave's first column
-            for (long long x0 = wb; x0 < we; x0 += 64) {
-                const long long w = x0 + ln;
-                uint32_t bits = w < we ? sbm[w] : 0u;
-                const long long c = __builtin_popcount(bits);
-                const long long incl = group_incl_scan<64>(c, ln);
-                long long r = r0 + incl - c;
-                r0 += __shfl(incl, 63);
-                while (bits) {
-                    const int bt = __builtin_ctz(bits);
-                    bits &= bits - 1;
-                    if (base + r < rend) {
-                        ccol[base + r] = (int32_t)((w0 + w) * 32 + bt);
-                        cval[base + r] = (VT)acc[r];
+            // the bitmap's copy and the slices; a block costs F + 8 c bytes (c
+            // its outputs), so the outputs before block i are (cost before i -
+            // F i) / 8
+            long long nsr;                             // outputs of this super-range
+            {
+                const long long E = (nr8 + BS - 1) / BS;
+                const long long i0 = (long long)tid * E, i1 = i0 + E < nr8 ? i0 + E : nr8;
+                long long loc = 0;
+                for (long long w = 8 * i0; w < 8 * i1 && w < words; ++w) loc += __builtin_popcount(bm[w]);
+                const long long cost = kSliceBlockFixed * (i1 > i0 ? i1 - i0 : 0) + 8 * loc;
+                long long ctot;
+                long long pc = block_incl_scan<BS>(cost, sm, &ctot) - cost;   // running cost before block i0
+                nsr = (ctot - kSliceBlockFixed * nr8) / 8;
+                for (long long i = i0; i < i1; ++i) {
+                    const long long prev = pc;
+                    long long c = 0;
+                    for (long long w = 8 * i; w < 8 * i + 8 && w < words; ++w) c += __builtin_popcount(bm[w]);
+                    pc += kSliceBlockFixed + 8 * c;
+                    const long long sid = (pc - 1) / budget;
+                    if ((i == 0 || sid != (prev - 1) / budget) && sid < kSliceMax) {
+                        s_sb[sid] = (int)i;
+                        s_sr[sid] = (int)((prev - kSliceBlockFixed * i) / 8);
                     }
-                    ++r;
+                }
+                if (tid == 0) {
+                    const long long n = nr8 > 0 ? (ctot - 1) / budget + 1 : 0;
+                    s_ns = n <= kSliceMax ? (int)n : -1;
+                    if (n <= kSliceMax) s_sb[n] = (int)nr8;
+                }
+                for (long long w = tid; w < words; w += BS) gb[w] = bm[w];
+            }
+            __syncthreads();
+            const int ns = s_ns;
+            if (ns < 0) {                              // uniform; the host bounds the slice count
+                bad = true;
+                break;
+            }
+            cur = sr_lo;
+            for (int sl = 0; sl < ns; ++sl) {
+                const long long b0 = s_sb[sl], b1 = s_sb[sl + 1];
+                const long long w0 = 8 * b0, w1 = 8 * b1 < words ? 8 * b1 : words;
+                const long long nw = w1 - w0;
+                const long long c_lo = C0 + w0 * 32, c_hi = C0 + w1 * 32 < C1 ? C0 + w1 * 32 : C1;
+                uint32_t* sbm = dyn_smem;
+                int* swr = reinterpret_cast<int*>(dyn_smem + nw);          // outputs before each segment word
+                double* acc = reinterpret_cast<double*>(dyn_smem + 2 * nw);
+                __syncthreads();                       // the previous slice (or the bitmap) is done with LDS
+                for (long long w = tid; w < nw; w += BS) sbm[w] = gb[w0 + w];
+                __syncthreads();
+                long long nout;                        // outputs of the slice
+                {
+                    const long long E = (nw + BS - 1) / BS;
+                    const long long i0 = (long long)tid * E, i1 = i0 + E < nw ? i0 + E : nw;
+                    long long loc = 0;
+                    for (long long w = i0; w < i1; ++w) loc += __builtin_popcount(sbm[w]);
+                    long long tot;
+                    long long run = block_incl_scan<BS>(loc, sm, &tot) - loc;
+                    nout = tot;
+                    for (long long w = i0; w < i1; ++w) {
+                        swr[w] = (int)run;
+                        run += __builtin_popcount(sbm[w]);
+                    }
+                }
+                for (long long r = tid; r < nout; r += BS) acc[r] = 0.0;
+                __syncthreads();
+                // the products whose columns fall in [c_lo, c_hi)
+                for (long long c0 = a0; c0 < a1; c0 += BS) {
+                    const long long p = c0 + tid;
+                    long long len = 0, bst = 0;
+                    double a = 0.0;
+                    if (p < a1) {
+                        const long long k = acol[p] + bo;
+                        a = to_f64(aval[p]);
+                        long long lo = brp[k], hi = brp[k + 1];
+                        if (ns > 1 || !whole) {
+                            lo = one_chunk ? cur : lower_bound_col(bcol, lo, hi, c_lo);
+                            if (sl + 1 < ns) hi = lower_bound_col(bcol, lo, hi, c_hi);
+                            else if (one_chunk) hi = sr_hi;
+                            else if (C1 < ncols) hi = lower_bound_col(bcol, lo, hi, C1);
+                            if (one_chunk) cur = hi;
+                        }
+                        bst = lo;
+                        len = hi - lo;
+                    }
+                    long long total;
+                    const long long incl = block_incl_scan<BS>(len, sm, &total);
+                    s_off[tid] = incl;
+                    s_bst[tid] = bst - (incl - len);
+                    s_a[tid] = a;
+                    __syncthreads();
+                    const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
+                    int t = -1;
+                    for (long long q0 = tid; q0 < total; q0 += RU * BS) {
+                        int32_t j[RU];
+                        double pv[RU];
+#pragma unroll
+                        for (int u = 0; u < RU; ++u) {
+                            const long long q = q0 + (long long)u * BS;
+                            j[u] = -1;
+                            pv[u] = 0.0;
+                            if (q < total) {
+                                if (t < 0) t = owner_search(s_off, nact, q);
+                                else while (s_off[t] <= q) ++t;
+                                const long long bi = s_bst[t] + q;
+                                j[u] = (int32_t)(bcol[bi] - c_lo);
+                                pv[u] = s_a[t] * to_f64(bval[bi]);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < RU; ++u) {
+                            if (j[u] < 0) continue;
+                            const int w = j[u] >> 5;
+                            const int r = swr[w] + __builtin_popcount(sbm[w] & ((1u << (j[u] & 31)) - 1u));
+                            atomicAdd(&acc[r], pv[u]);
+                        }
+                    }
+                    __syncthreads();
+                }
+                // the slice in column order: wave wv walks the segment words [wv WS, wv WS + WS)
+                const long long base = rp + done + s_sr[sl];
+                constexpr int NW = BS / 64;
+                const int wv = tid >> 6, ln = tid & 63;
+                const long long WS = (nw + NW - 1) / NW;
+                const long long wb = (long long)wv * WS, we = wb + WS < nw ? wb + WS : nw;
+                long long wc = 0;
+                for (long long w = wb + ln; w < we; w += 64) wc += __builtin_popcount(sbm[w]);
+#pragma unroll
+                for (int d = 32; d > 0; d >>= 1) wc += __shfl_xor(wc, d);
+                long long run;
+                const long long wincl = block_incl_scan<BS>(ln == 0 ? wc : 0, sm, &run);
+                long long r0 = __shfl(wincl, 0) - wc;  // rank in the slice of the wave's first column
+                for (long long x0 = wb; x0 < we; x0 += 64) {
+                    const long long w = x0 + ln;
+                    uint32_t bits = w < we ? sbm[w] : 0u;
+                    const long long c = __builtin_popcount(bits);
+                    const long long incl = group_incl_scan<64>(c, ln);
+                    long long r = r0 + incl - c;
+                    r0 += __shfl(incl, 63);
+                    while (bits) {
+                        const int bt = __builtin_ctz(bits);
+                        bits &= bits - 1;
+                        if (base + r < rend) {
+                            ccol[base + r] = (int32_t)(c_lo + w * 32 + bt);
+                            cval[base + r] = (VT)acc[r];
+                        }
+                        ++r;
+                    }
                 }
             }
+            done += nsr;
+            if (!MULTI) break;
         }
         if (tid == 0) {
             const long long cap = rend - rp;
-            if (cnt_out) cnt_out[row] = nrow <= cap ? (int)nrow : -1;
-            else if (nrow != cap) atomicOr(&info->err, kErrCount);
+            if (cnt_out) cnt_out[row] = !bad && done <= cap ? (int)done : -1;
+            else if (bad || done != cap) atomicOr(&info->err, kErrCount);
         }
         __syncthreads();
     }

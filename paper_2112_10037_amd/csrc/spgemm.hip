@@ -211,8 +211,14 @@ msp_status configure_kernels(msp_handle* h) {
         }
     }
     const int dyn_slice = std::max(0, h->lds_per_block - kSliceReserve);
-    void* slice_fns[] = {(void*)k_num_slice<kSliceBS, float, false>, (void*)k_num_slice<kSliceBS, double, false>,
-                         (void*)k_num_slice<kSliceBS, float, true>, (void*)k_num_slice<kSliceBS, double, true>};
+    void* slice_fns[] = {(void*)k_num_slice<kSliceBS, float, false, false>,
+                         (void*)k_num_slice<kSliceBS, double, false, false>,
+                         (void*)k_num_slice<kSliceBS, float, true, false>,
+                         (void*)k_num_slice<kSliceBS, double, true, false>,
+                         (void*)k_num_slice<kSliceBS, float, false, true>,
+                         (void*)k_num_slice<kSliceBS, double, false, true>,
+                         (void*)k_num_slice<kSliceBS, float, true, true>,
+                         (void*)k_num_slice<kSliceBS, double, true, true>};
     for (void* f : slice_fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_slice);
         if (e != hipSuccess) {
@@ -380,24 +386,32 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
         const long long n = op.ncols;
         const long long words = (n + 31) / 32;
         {
-            // the columns fit an LDS bitmap: accumulate in LDS slice by slice
-            const long long nr8 = (words + 7) / 8;
-            const long long bm_lds = words * 4;
+            // accumulate in LDS slice by slice, over column super-ranges whose
+            // bitmap fits the LDS (one when all columns fit)
             const long long avail = h->lds_per_block - kSliceReserve;
-            const long long lds = std::min(avail, bm_lds + 65536);
+            const long long span_max = avail / 32 * 256;              // whole 256-column blocks
+            const long long span = n <= span_max ? std::max(n, 1LL) : span_max;
+            const long long sw = (span + 31) / 32;
+            const long long nr8 = (sw + 7) / 8;
+            const long long lds = std::min(avail, sw * 4 + 65536);
             const long long budget = lds - kSliceBlockCost - 16;
-            if (bm_lds <= avail && budget > kSliceBlockCost &&
-                (kSliceBlockFixed * nr8 + 8 * n) / budget + 1 <= kSliceMax) {
+            if (span_max > 0 && budget > kSliceBlockCost &&
+                (kSliceBlockFixed * nr8 + 8 * span) / budget + 1 <= kSliceMax) {
                 const int grid = std::max(1, std::min(rows, h->num_cu));
-                msp_status r = h->gsl.ensure((size_t)grid * (size_t)words * 4);
+                msp_status r = h->gsl.ensure((size_t)grid * (size_t)sw * 4);
                 if (r != MSP_OK) return r;
-                k_num_slice<kSliceBS, VT, BATCH><<<grid, kSliceBS, (size_t)lds, st>>>(
-                    wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->gsl.as<uint32_t>(), lds,
-                    cnt_out, info, mp);
+                if (n <= span_max)
+                    k_num_slice<kSliceBS, VT, BATCH, false><<<grid, kSliceBS, (size_t)lds, st>>>(
+                        wk, n, span, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval,
+                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp);
+                else
+                    k_num_slice<kSliceBS, VT, BATCH, true><<<grid, kSliceBS, (size_t)lds, st>>>(
+                        wk, n, span, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval,
+                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp);
                 return launch_check("k_num_slice");
             }
         }
-        // too wide for an LDS bitmap beside the slices: per-workgroup FP64 slab
+        // a device with too little LDS for the slices: per-workgroup FP64 slab
         const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
         // one slab per resident workgroup; keep the arena under 16 GiB
         long long cap = (16LL << 30) / std::max(1LL, n * 8);

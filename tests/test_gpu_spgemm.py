@@ -120,13 +120,16 @@ def test_global_bin_many_slices(h, dtype):
     check_full(h, A, B)
 
 
-def test_wide_matrix_global_bitmap(h):
-    """ncols = 2^21: the n-bit bitmap no longer fits LDS (global slabs)."""
-    n = 1 << 21
-    B = gen.erdos_renyi(4000, n, 60, seed=11)
+@pytest.mark.parametrize("n,dtype", [(1 << 21, np.float64), ((1 << 21) + 12345, np.float32)])
+def test_wide_matrix_global_bitmap(h, n, dtype):
+    """ncols above 2^21: the n-bit bitmap no longer fits LDS.  The symbolic
+    pass uses global bitmap slabs; the numeric pass walks two column
+    super-ranges, each with its own LDS bitmap and slices (rows of 900 A
+    entries keep their cursors, rows of 2500 search in every slice)."""
+    B = gen.erdos_renyi(4000, n, 60, seed=11, dtype=dtype)
     k = np.full(16, 5, dtype=np.int64)
     k[[1, 9]] = [900, 2500]
-    A = gen.erdos_renyi(16, 4000, k, seed=12)
+    A = gen.erdos_renyi(16, 4000, k, seed=12, dtype=dtype)
     check_full(h, A, B)
 
 
