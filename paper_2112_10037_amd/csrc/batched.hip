@@ -382,7 +382,7 @@ static void release_batch(msp_batch* b) {
         for (DevBuf* d : {&S.tile_prob, &S.row_start, &S.boff, &S.ncols, &S.crp, &S.cv, &S.wsym, &S.wnum}) d->release();
     for (DevBuf* d : {&b->rp_local, &b->bases, &b->flag}) d->release();
     msp_handle* h = &b->inner;
-    for (DevBuf* d : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->dslab, &h->gbm, &h->sbm, &h->prod,
+    for (DevBuf* d : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod,
                       &h->bsum, &h->gsl})
         d->release();
     if (h->hinfo) (void)hipHostFree(h->hinfo);

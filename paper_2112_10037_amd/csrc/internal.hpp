@@ -94,11 +94,9 @@ struct msp_handle {
     int num_cu = 256;
     int lds_per_block = 65536;
     msp_tuning tuning{};
-    msp::DevBuf info, u, rnnz, perm, tiles, dslab, gbm, sbm, prod;
+    msp::DevBuf info, u, rnnz, perm, tiles, sbm, prod;
     msp::DevBuf bsum;               // 256-row workgroup totals of the fused symbolic pass
     msp::DevBuf gsl;                // per-workgroup bitmap copies of the sliced global-bin kernel
-    size_t dslab_cols = 0;          // ncols the dense slabs were zeroed for
-    int dslab_count = 0;
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
     int* hpending = nullptr;        // pinned: error bits of the last call's numeric
                                     // kernels, forwarded by the next call's first kernel

@@ -1886,123 +1886,8 @@ k_num_block(Work wk,
 }
 
 // ===========================================================================
-// Global spill for rows too large for LDS
+// Global bin: rows too large for the LDS hash bins
 // ===========================================================================
-// Each workgroup owns a dense FP64 slab of ncols values (all zero between
-// rows) and an ncols-bit bitmap (LDS when it fits, else a global slab).
-// Products are added with workgroup-scope FP64 atomics; the bitmap is then
-// scanned in column order, which writes the row already sorted and returns
-// the touched slab entries to zero.
-template <int BS, bool LDSBM, typename VT, bool BATCH = false>
-__global__ void __launch_bounds__(BS)
-k_num_dense(Work wk, long long ncols,
-            const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
-            const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
-            const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            double* dslab, uint32_t* gbm, int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
-    int nrows_bin;
-    const int32_t* perm;
-    work_rows(wk, &nrows_bin, &perm);
-    extern __shared__ uint32_t dyn_smem[];
-    __shared__ long long s_off[BS];
-    __shared__ long long s_bst[BS];
-    __shared__ double s_a[BS];
-    __shared__ BlockScanSmem<BS> sm;
-    const int tid = threadIdx.x;
-    const long long words = (ncols + 31) >> 5;
-    double* dense = dslab + (long long)blockIdx.x * ncols;
-    uint32_t* bm = LDSBM ? dyn_smem : gbm + (long long)blockIdx.x * words;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
-        const int row = perm ? perm[slot] : (int)slot;
-        const long long bo = row_boff<BATCH>(mp, row);
-        if (LDSBM) {
-            for (long long w = tid; w < words; w += BS) bm[w] = 0u;
-        }
-        __syncthreads();
-        const long long a0 = arp[row], a1 = arp[row + 1];
-        for (long long c0 = a0; c0 < a1; c0 += BS) {
-            const long long p = c0 + tid;
-            long long len = 0, bst = 0;
-            double a = 0.0;
-            if (p < a1) {
-                const long long k = acol[p] + bo;
-                a = to_f64(aval[p]);
-                bst = brp[k];
-                len = brp[k + 1] - bst;
-            }
-            long long total;
-            const long long incl = block_incl_scan<BS>(len, sm, &total);
-            s_off[tid] = incl;
-            s_bst[tid] = bst - (incl - len);
-            s_a[tid] = a;
-            __syncthreads();
-            const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
-            int t = -1;                     // owner of q: one search, then it only moves forward
-            for (long long q = tid; q < total; q += BS) {
-                if (t < 0) t = owner_search(s_off, nact, q);
-                else while ((long long)s_off[t] <= q) ++t;
-                const long long bi = s_bst[t] + q;
-                const int32_t j = bcol[bi];
-                const double prod = s_a[t] * to_f64(bval[bi]);
-                // slab and bitmap are this workgroup's own: workgroup-scope
-                // atomics (performed in the L2 of its XCD, no device-wide
-                // coherence traffic) and workgroup barriers order them
-                __hip_atomic_fetch_add(&dense[j], prod, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (LDSBM) atomicOr(&bm[j >> 5], 1u << (j & 31));
-                else __hip_atomic_fetch_or(&bm[j >> 5], 1u << (j & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            __syncthreads();
-        }
-        // ordered extraction (writes stay inside the row's range).  Wave w
-        // takes the words [w WS, (w + 1) WS): it counts them, one block scan
-        // gives every wave its start in C, and the wave then walks its words
-        // 64 at a time (neighbouring lanes on neighbouring words) with a
-        // wave-level scan, so there is a single workgroup scan per row.
-        const long long rp = crp[row];
-        const long long rend = crp[row + 1];
-        constexpr int NW = BS / 64;
-        const int wv = tid >> 6, ln = tid & 63;
-        const long long WS = (words + NW - 1) / NW;
-        const long long wb = (long long)wv * WS, we = wb + WS < words ? wb + WS : words;
-        auto word_at = [&](long long w) -> uint32_t {
-            return LDSBM ? bm[w] : __hip_atomic_load(&bm[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        };
-        long long wc = 0;
-        for (long long w = wb + ln; w < we; w += 64) wc += __builtin_popcount(word_at(w));
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) wc += __shfl_xor(wc, d);
-        long long run;
-        const long long wincl = block_incl_scan<BS>(ln == 0 ? wc : 0, sm, &run);
-        long long pos0 = rp + __shfl(wincl, 0) - wc;      // the wave's first position
-        for (long long w0 = wb; w0 < we; w0 += 64) {
-            const long long w = w0 + ln;
-            uint32_t bits = w < we ? word_at(w) : 0u;
-            const long long c = __builtin_popcount(bits);
-            const long long incl = group_incl_scan<64>(c, ln);
-            long long pos = pos0 + incl - c;
-            pos0 += __shfl(incl, 63);
-            while (bits) {
-                const int b = __builtin_ctz(bits);
-                bits &= bits - 1;
-                const long long col = w * 32 + b;
-                const double v = __hip_atomic_load(&dense[col], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (pos < rend) {
-                    ccol[pos] = (int32_t)col;
-                    cval[pos] = (VT)v;
-                }
-                dense[col] = 0.0;
-                ++pos;
-            }
-            if (w < we && !LDSBM) gbm[(long long)blockIdx.x * words + w] = 0u;
-        }
-        if (tid == 0) {
-            const long long cap = rend - rp;
-            if (cnt_out) cnt_out[row] = run <= cap ? (int)run : -1;
-            else if (run != cap) atomicOr(&info->err, kErrCount);
-        }
-        __syncthreads();
-    }
-}
 
 // Products each thread of the slice kernel loads before using any: one
 // workgroup per compute unit leaves few waves to hide the gathers.

@@ -165,7 +165,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     if (!h) return MSP_OK;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->dslab, &h->gbm, &h->sbm, &h->prod,
+    for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod,
                       &h->bsum, &h->gsl})
         b->release();
     release_extra(h);

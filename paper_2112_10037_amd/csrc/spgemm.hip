@@ -124,7 +124,7 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
 // ---------------------------------------------------------------------------
 // kernel tables
 // ---------------------------------------------------------------------------
-constexpr int kLdsReserve = 26 * 1024;     // static LDS of the bitmap/dense kernels
+constexpr int kLdsReserve = 26 * 1024;     // static LDS of the symbolic bitmap kernel
 constexpr int kSliceReserve = 27 * 1024;   // static LDS of k_num_slice<kSliceBS>
 
 #define MSP_GROUP_SHAPES(X) \
@@ -192,17 +192,10 @@ int count_unsupported_plans(int verbose) {
     return bad;
 }
 
-template <typename VT, bool BATCH>
-static void* dense_kernel(bool lds) {
-    return lds ? (void*)k_num_dense<1024, true, VT, BATCH> : (void*)k_num_dense<1024, false, VT, BATCH>;
-}
-
 msp_status configure_kernels(msp_handle* h) {
     // allow the bitmap kernels the device's full LDS for their dynamic part
     const int dyn = std::max(0, h->lds_per_block - kLdsReserve);
-    void* fns[] = {(void*)k_sym_bitmap<1024, true, false>, (void*)k_sym_bitmap<1024, true, true>,
-                   dense_kernel<float, false>(true), dense_kernel<double, false>(true),
-                   dense_kernel<float, true>(true), dense_kernel<double, true>(true)};
+    void* fns[] = {(void*)k_sym_bitmap<1024, true, false>, (void*)k_sym_bitmap<1024, true, true>};
     for (void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         if (e != hipSuccess) {
@@ -384,7 +377,6 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
 #undef X
     } else if (s.kind == Kind::Dense) {
         const long long n = op.ncols;
-        const long long words = (n + 31) / 32;
         {
             // accumulate in LDS slice by slice, over column super-ranges whose
             // bitmap fits the LDS (one when all columns fit)
@@ -411,36 +403,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
                 return launch_check("k_num_slice");
             }
         }
-        // a device with too little LDS for the slices: per-workgroup FP64 slab
-        const bool lds = words * 4 <= h->lds_per_block - kLdsReserve;
-        // one slab per resident workgroup; keep the arena under 16 GiB
-        long long cap = (16LL << 30) / std::max(1LL, n * 8);
-        int nslab = (int)std::max(1LL, std::min<long long>(h->num_cu, cap));
-        if (h->dslab_cols != (size_t)n || h->dslab_count < nslab) {
-            if (g_capturing) return fail(MSP_ERR_HIP, "internal: dense slab set-up during graph capture");
-            msp_status r = h->dslab.ensure((size_t)nslab * (size_t)n * 8);
-            if (r != MSP_OK) return r;
-            hipError_t e = hipMemsetAsync(h->dslab.ptr, 0, (size_t)nslab * (size_t)n * 8, st);
-            if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(dense slab)");
-            if (!lds) {
-                r = h->gbm.ensure((size_t)nslab * words * 4);
-                if (r != MSP_OK) return r;
-                e = hipMemsetAsync(h->gbm.ptr, 0, (size_t)nslab * words * 4, st);
-                if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(bitmap slab)");
-            }
-            h->dslab_cols = (size_t)n;
-            h->dslab_count = nslab;
-        }
-        const int grid = std::min(rows, nslab);
-        if (lds)
-            k_num_dense<1024, true, VT, BATCH><<<grid, 1024, words * 4, st>>>(
-                wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->dslab.as<double>(), nullptr,
-                cnt_out, info, mp);
-        else
-            k_num_dense<1024, false, VT, BATCH><<<grid, 1024, 0, st>>>(
-                wk, n, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval, h->dslab.as<double>(),
-                h->gbm.as<uint32_t>(), cnt_out, info, mp);
-        return launch_check("k_num_dense");
+        return fail(MSP_ERR_UNSUPPORTED, "internal: the global bin's slices do not fit the LDS");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no numeric kernel for bin shape (%d, %d)", s.lanes, s.slots);
 }
