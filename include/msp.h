@@ -239,10 +239,12 @@ msp_status msp_predictor_calibrate(msp_handle* h, msp_predictor* p, const float*
 /*
  * C = A * B in one pass: per-row capacities
  *     cap_i = clamp(ceil(2^(16 y_i + delta)), max_k nnz(B(k,:)), min(prod_i, n))
- * (rows with min(prod_i, n) <= 32 take that bound without the network, and
- * so does every row whose bound falls in the same numeric bin as cap_i
- * (same kernel, no risk of overflow) or is at most 2 cap_i (at most twice
- * the room, no risk of overflow)), rows binned by capacity, numeric kernels
+ * (when the margin delta alone lifts cap_i past the bound of the numeric
+ * bin of the point prediction ceil(2^(16 y_i)), cap_i is that bound; rows
+ * with min(prod_i, n) <= 32 take that bound without the network, and so does
+ * every row whose bound falls in the same numeric bin as cap_i (same
+ * kernel, no risk of overflow) or is at most 2 cap_i (at most twice the
+ * room, no risk of overflow)), rows binned by capacity, numeric kernels
  * writing into a padded buffer,
  * the rows that did not fit recomputed exactly (two-phase path on their
  * sub-matrix), and a compaction into tight CSR.  The result equals

@@ -96,6 +96,17 @@ k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ h
             const double est = exp2((double)(16.f * y + delta));
             c = est < (double)h ? (int)ceil(est) : h;    // NaN or overflow: the upper bound
             c = c < l ? l : c;
+            if (nt.nb > 0) {
+                // the margin alone lifts the row past the bound of its point
+                // prediction's bin: keep it in that bin, at the bin's bound
+                const double pt = exp2((double)(16.f * y));
+                if (pt < (double)h) {
+                    int cp = (int)ceil(pt);
+                    cp = cp < l ? l : cp;
+                    const int bp = bin_of(nt, cp);
+                    if (bp < nt.nb && bin_of(nt, c) > bp) c = nt.umax[bp];
+                }
+            }
             // the exact bound costs nothing more when it keeps the row in
             // the same numeric bin (same kernel, same accumulator): only
             // unused padding, which the compaction never reads; and it
