@@ -484,8 +484,10 @@ k_sym_group(Work wk, int m,
         s_bst[g][gl] = bst - (incl - len);
         lds_fence();
         const int nact = (int)((a1 - c0) < G ? (a1 - c0) : G);
+        int t = -1;                                  // owner of q: one search, then it only moves forward
         for (long long q = gl; q < total; q += G) {
-            const int t = owner_search(s_off[g], nact, q);
+            if (t < 0) t = owner_search(s_off[g], nact, q);
+            else while (s_off[g][t] <= q) ++t;
             const int32_t j = bcol[s_bst[g][t] + q];
             cnt += hash_insert_key<T>(kt, j, &err);
         }
@@ -1711,8 +1713,10 @@ k_num_group(Work wk,
         s_a[g][gl] = a;
         lds_fence();
         const int nact = (int)((a1 - c0) < G ? (a1 - c0) : G);
+        int t = -1;                                  // owner of q: one search, then it only moves forward
         for (long long q = gl; q < total; q += G) {
-            const int t = owner_search(s_off[g], nact, q);
+            if (t < 0) t = owner_search(s_off[g], nact, q);
+            else while (s_off[g][t] <= q) ++t;
             const long long bi = s_bst[g][t] + q;
             const int32_t j = bcol[bi];
             const double prod = s_a[g][t] * to_f64(bval[bi]);
