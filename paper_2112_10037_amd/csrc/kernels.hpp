@@ -1897,18 +1897,20 @@ k_num_block(Work wk,
 // workgroup per compute unit leaves few waves to hide the gathers.
 constexpr int kProductUnroll = 4;
 
-// Rows of the global bin whose columns fit an LDS bitmap, accumulated in
-// LDS one column slice at a time.  The bitmap pass sets the row's column
-// bitmap in LDS and keeps a copy of it in the workgroup's global scratch.  The row is then cut at
-// 256-column block boundaries into slices whose bitmap segment, rank of
-// every segment word and FP64 accumulator (one entry per output of the
-// slice) fit the same LDS together: a block costs 64 bytes plus 8 per
-// output, and a
-// slice takes the blocks whose running cost falls in one budget-sized
-// interval.  For each slice, every A entry's B row is searched for the
-// slice's column range, the products in it add into the accumulator with
-// LDS atomics, and the segment goes out in column order from the slice's
-// first output's position in C.  No atomic leaves LDS.
+// Rows of the global bin (too large for the LDS hash bins), accumulated in
+// LDS one column slice at a time.  The columns are taken in super-ranges
+// whose bitmap fits the LDS (all of them at once when they fit).  For each
+// super-range, the bitmap pass sets the row's column bitmap in LDS and
+// keeps a copy of it in the workgroup's global scratch.  The super-range is
+// then cut at 256-column block boundaries into slices whose bitmap segment,
+// count of outputs before every segment word and FP64 accumulator (one
+// entry per output of the slice) fit the same LDS together: a block costs
+// 64 bytes plus 8 per output, and a slice takes the blocks whose running
+// cost falls in one budget-sized interval.  For each slice, every A entry's
+// B row is searched for the slice's column range, the products in it add
+// into the accumulator with LDS atomics, and the segment goes out in column
+// order from the slice's first output's position in C.  No accumulator
+// atomic leaves LDS.
 constexpr int kSliceBS = 1024;               // threads of the slice kernel
 constexpr int kSliceMax = 256;               // slices per row
 constexpr int kSliceBlockFixed = 8 * 4 + 8 * 4;          // a 256-column block's bitmap words and word ranks
