@@ -166,6 +166,22 @@ msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B,
  * error the numeric kernels of earlier calls flagged. */
 msp_status msp_sync(msp_handle* h);
 
+/*
+ * Autotuner for one product (it replaces the paper's analytic choice of its
+ * hardware parameters, Sec. IV-B4, Eqs. 2-3, by measurement): runs
+ * msp_spgemm(A, B) with each of the ncand tunings, one warm call and then
+ * `reps` timed calls each (HIP events around the whole call on the
+ * handle's stream, the result waited for and released through the
+ * allocator), and returns in *best the tuning with the smallest median time;
+ * times_ms (ncand doubles, may be NULL) receives each median, or infinity
+ * for a candidate the library rejects.  The handle's own tuning is not
+ * changed (pass *best to msp_set_tuning).  Synchronises.  Errors: a bad
+ * argument; MSP_ERR_HIP at once if the device reports an error; otherwise
+ * the last candidate's error when none ran.
+ */
+msp_status msp_autotune(msp_handle* h, const msp_csr* A, const msp_csr* B, const msp_tuning* cand, int ncand,
+                        int reps, msp_tuning* best, double* times_ms);
+
 /* Only the symbolic part: row_nnz (device, A.nrows int32) and the total.
  * Used to produce training targets for the predictor. */
 msp_status msp_spgemm_symbolic(msp_handle* h, const msp_csr* A, const msp_csr* B,
@@ -211,6 +227,35 @@ msp_status msp_predictor_destroy(msp_predictor* p);
  * margin delta; set them from the host (params NULL keeps them). */
 msp_status msp_predictor_get(msp_handle* h, const msp_predictor* p, float* params, float* delta);
 msp_status msp_predictor_set(msp_handle* h, msp_predictor* p, const float* params, float delta);
+/*
+ * Checkpoint and restore of a predictor as a versioned byte blob of
+ * MSP_PREDICTOR_BLOB_BYTES bytes (little-endian):
+ *     offset 0   "MSPP"                       magic
+ *            4   uint32 version (1)
+ *            8   uint32 parameter count (4801)
+ *           12   float  delta (capacity margin)
+ *           16   int64  Adam steps taken
+ *           24   float  parameters[4801]      (msp_predictor_create order)
+ *                float  Adam first moments[4801]
+ *                float  Adam second moments[4801]
+ *       end - 8  uint64 FNV-1a hash of every byte before it
+ * so that training can resume where it stopped.  msp_predictor_save
+ * writes the blob into the caller's host buffer (cap bytes; *size, when not
+ * NULL, receives the blob size; blob NULL only queries the size) after
+ * copying the state from the device (synchronises).  msp_predictor_load
+ * replaces p's state from a blob: a wrong magic, count, size or hash gives
+ * MSP_ERR_INVALID_ARG, another version MSP_ERR_UNSUPPORTED, and p is left
+ * unchanged on error.  The _pack / _unpack pair does the same on host
+ * arrays only (any of adam_m, adam_v, delta, step may be NULL: packed as
+ * zeros, or not returned) and needs no device.
+ */
+#define MSP_PREDICTOR_BLOB_BYTES 57644
+msp_status msp_predictor_save(msp_handle* h, const msp_predictor* p, void* blob, size_t cap, size_t* size);
+msp_status msp_predictor_load(msp_handle* h, msp_predictor* p, const void* blob, size_t size);
+msp_status msp_predictor_blob_pack(const float* params, const float* adam_m, const float* adam_v, float delta,
+                                   int64_t step, void* blob, size_t cap, size_t* size);
+msp_status msp_predictor_blob_unpack(const void* blob, size_t size, float* params, float* adam_m, float* adam_v,
+                                     float* delta, int64_t* step);
 /* Train with Adam on the mean squared error, `steps` mini-batches of
  * `batch` rows: batch_idx (device, steps x batch int32) names rows of
  * feats (device, n x 8) and targets (device, n).  losses_host (steps

@@ -106,6 +106,15 @@ SIGNATURES = [
     ("msp_predictor_get", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_float)]),
     ("msp_predictor_set", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float]),
+    ("msp_predictor_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    ("msp_predictor_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    ("msp_predictor_blob_pack", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                                               ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+    ("msp_predictor_blob_unpack", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.POINTER(ctypes.c_int64)]),
     ("msp_predictor_train", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(c_train_opts), ctypes.c_void_p]),
@@ -135,6 +144,9 @@ SIGNATURES = [
                                           ctypes.POINTER(c_batch_csr), ctypes.POINTER(c_batch_csr),
                                           ctypes.POINTER(c_tuning), ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(c_tuning), ctypes.POINTER(ctypes.c_double)]),
+    ("msp_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
+                                    ctypes.POINTER(c_tuning), ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(c_tuning), ctypes.POINTER(ctypes.c_double)]),
     ("msp_tuning_to_json", ctypes.c_int, [ctypes.POINTER(c_tuning), ctypes.c_char_p, ctypes.c_size_t]),
     ("msp_tuning_from_json", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(c_tuning)]),
     ("msp_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -422,6 +434,23 @@ class Handle:
             self._end()
         return rn[: A.nrows], int(tot.value)
 
+    def autotune(self, A: DeviceCSR, B: DeviceCSR, candidates, reps: int = 5):
+        """Median time of whole msp_spgemm(A, B) calls under each candidate
+        tuning; returns (best, times_ms).  The handle's tuning is unchanged."""
+        n = len(candidates)
+        arr = (c_tuning * n)(*[c_tuning(*t) for t in candidates])
+        times = (ctypes.c_double * n)()
+        best = c_tuning()
+        a, b = A.c(), B.c()
+        self._begin()
+        try:
+            _check(self._lib.msp_autotune(self._h, ctypes.byref(a), ctypes.byref(b), arr, n, reps,
+                                          ctypes.byref(best), times))
+        finally:
+            self._end()
+        return ((best.hash_scale, best.group_scale, best.spill_nnz, best.block_rows, best.merge_k),
+                [float(t) for t in times])
+
     def row_features(self, A: DeviceCSR, B: DeviceCSR):
         """(prod int64 [m], features float32 [m, 8])."""
         torch = self._torch
@@ -440,6 +469,32 @@ class Handle:
 
 
 NPARAM = 4801
+BLOB_BYTES = 57644          # MSP_PREDICTOR_BLOB_BYTES
+
+
+def blob_pack(params, delta: float = 0.0, adam_m=None, adam_v=None, step: int = 0) -> bytes:
+    """Host-only: the predictor blob of the given state (no device needed)."""
+    lib = load()
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in (params, adam_m, adam_v)]
+    for a in arrs:
+        assert a is None or a.size == NPARAM
+    ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+    buf = ctypes.create_string_buffer(BLOB_BYTES)
+    size = ctypes.c_size_t()
+    _check(lib.msp_predictor_blob_pack(ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]), ctypes.c_float(delta),
+                                       ctypes.c_int64(step), buf, BLOB_BYTES, ctypes.byref(size)))
+    return buf.raw[: size.value]
+
+
+def blob_unpack(blob: bytes):
+    """Host-only: (params, delta, adam_m, adam_v, step) from a blob."""
+    lib = load()
+    out = [np.zeros(NPARAM, dtype=np.float32) for _ in range(3)]
+    d = ctypes.c_float()
+    st = ctypes.c_int64()
+    _check(lib.msp_predictor_blob_unpack(blob, len(blob), *[a.ctypes.data_as(ctypes.c_void_p) for a in out],
+                                         ctypes.byref(d), ctypes.byref(st)))
+    return out[0], float(d.value), out[1], out[2], int(st.value)
 
 
 class Predictor:
@@ -478,6 +533,18 @@ class Predictor:
             p = np.ascontiguousarray(params, dtype=np.float32)
             ptr = p.ctypes.data_as(ctypes.c_void_p)
         _check(self._lib.msp_predictor_set(self.h._h, self._p, ptr, ctypes.c_float(delta)))
+
+    def save(self) -> bytes:
+        """The predictor's state (parameters, delta, Adam moments and step
+        count) as the versioned blob of msp_predictor_save."""
+        buf = ctypes.create_string_buffer(BLOB_BYTES)
+        size = ctypes.c_size_t()
+        _check(self._lib.msp_predictor_save(self.h._h, self._p, buf, BLOB_BYTES, ctypes.byref(size)))
+        return buf.raw[: size.value]
+
+    def load(self, blob: bytes):
+        """Replace the state from a blob written by save()."""
+        _check(self._lib.msp_predictor_load(self.h._h, self._p, blob, len(blob)))
 
     def train(self, feats, targets, batch_idx, lr=1e-3):
         """feats (n x 8), targets (n) float32 and batch_idx (steps x batch)

@@ -490,6 +490,117 @@ extern "C" msp_status msp_predictor_set(msp_handle* h, msp_predictor* p, const f
     return MSP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// serialized form (little-endian): magic "MSPP", u32 version, u32 parameter
+// count, f32 delta, i64 Adam step count, then the parameters and Adam's two
+// moment arrays (f32 each), then a u64 FNV-1a hash of every byte before it
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint32_t kBlobVersion = 1;
+constexpr size_t kBlobHeader = 24;
+constexpr size_t kBlobBytes = kBlobHeader + 3 * (size_t)kNParam * 4 + 8;
+static_assert(kBlobBytes == MSP_PREDICTOR_BLOB_BYTES, "blob layout and its declared size agree");
+
+uint64_t fnv1a64(const unsigned char* p, size_t n) {
+    uint64_t x = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) {
+        x ^= p[i];
+        x *= 0x100000001b3ull;
+    }
+    return x;
+}
+}  // namespace
+
+extern "C" msp_status msp_predictor_blob_pack(const float* params, const float* adam_m, const float* adam_v,
+                                              float delta, int64_t step, void* blob, size_t cap, size_t* size) {
+    if (size) *size = kBlobBytes;
+    if (!blob) return size ? MSP_OK : fail(MSP_ERR_INVALID_ARG, "blob and size are both NULL");
+    if (!params) return fail(MSP_ERR_INVALID_ARG, "params is NULL");
+    if (cap < kBlobBytes) return fail(MSP_ERR_INVALID_ARG, "blob buffer of %zu bytes, %zu needed", cap, kBlobBytes);
+    unsigned char* b = (unsigned char*)blob;
+    const uint32_t np = kNParam;
+    memcpy(b, "MSPP", 4);
+    memcpy(b + 4, &kBlobVersion, 4);
+    memcpy(b + 8, &np, 4);
+    memcpy(b + 12, &delta, 4);
+    memcpy(b + 16, &step, 8);
+    unsigned char* q = b + kBlobHeader;
+    for (const float* a : {params, adam_m, adam_v}) {
+        if (a) memcpy(q, a, (size_t)kNParam * 4);
+        else memset(q, 0, (size_t)kNParam * 4);
+        q += (size_t)kNParam * 4;
+    }
+    const uint64_t hsh = fnv1a64(b, kBlobBytes - 8);
+    memcpy(q, &hsh, 8);
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_blob_unpack(const void* blob, size_t size, float* params, float* adam_m,
+                                                float* adam_v, float* delta, int64_t* step) {
+    if (!blob) return fail(MSP_ERR_INVALID_ARG, "blob is NULL");
+    const unsigned char* b = (const unsigned char*)blob;
+    if (size < kBlobHeader || memcmp(b, "MSPP", 4) != 0)
+        return fail(MSP_ERR_INVALID_ARG, "not a predictor blob (magic)");
+    uint32_t ver = 0, np = 0;
+    memcpy(&ver, b + 4, 4);
+    memcpy(&np, b + 8, 4);
+    if (ver != kBlobVersion)
+        return fail(MSP_ERR_UNSUPPORTED, "predictor blob version %u; this library reads version %u", ver, kBlobVersion);
+    if (np != (uint32_t)kNParam) return fail(MSP_ERR_INVALID_ARG, "predictor blob holds %u parameters, not %d", np, kNParam);
+    if (size != kBlobBytes) return fail(MSP_ERR_INVALID_ARG, "predictor blob of %zu bytes, %zu expected", size, kBlobBytes);
+    uint64_t hsh = 0;
+    memcpy(&hsh, b + kBlobBytes - 8, 8);
+    if (hsh != fnv1a64(b, kBlobBytes - 8)) return fail(MSP_ERR_INVALID_ARG, "predictor blob checksum mismatch");
+    if (delta) memcpy(delta, b + 12, 4);
+    if (step) memcpy(step, b + 16, 8);
+    const unsigned char* q = b + kBlobHeader;
+    for (float* a : {params, adam_m, adam_v}) {
+        if (a) memcpy(a, q, (size_t)kNParam * 4);
+        q += (size_t)kNParam * 4;
+    }
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_predictor_save(msp_handle* h, const msp_predictor* p, void* blob, size_t cap, size_t* size) {
+    if (!h || !p) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    if (size) *size = kBlobBytes;
+    if (!blob) return size ? MSP_OK : fail(MSP_ERR_INVALID_ARG, "blob and size are both NULL");
+    if (cap < kBlobBytes) return fail(MSP_ERR_INVALID_ARG, "blob buffer of %zu bytes, %zu needed", cap, kBlobBytes);
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::vector<float> host(3 * (size_t)kNParam);
+    const DevBuf* src[3] = {&p->params, &p->m, &p->v};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(host.data() + (size_t)i * kNParam, src[i]->ptr, (size_t)kNParam * 4, hipMemcpyDeviceToHost,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(predictor state)");
+    return msp_predictor_blob_pack(host.data(), host.data() + kNParam, host.data() + 2 * kNParam, p->delta, p->step,
+                                   blob, cap, nullptr);
+}
+
+extern "C" msp_status msp_predictor_load(msp_handle* h, msp_predictor* p, const void* blob, size_t size) {
+    if (!h || !p) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    std::vector<float> host(3 * (size_t)kNParam);
+    float delta = 0.f;
+    int64_t step = 0;
+    msp_status s = msp_predictor_blob_unpack(blob, size, host.data(), host.data() + kNParam,
+                                             host.data() + 2 * kNParam, &delta, &step);
+    if (s != MSP_OK) return s;
+    if (step < 0) return fail(MSP_ERR_INVALID_ARG, "predictor blob has a negative step count");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    DevBuf* dst[3] = {&p->params, &p->m, &p->v};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(dst[i]->ptr, host.data() + (size_t)i * kNParam, (size_t)kNParam * 4, hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(predictor state)");
+    p->delta = delta;
+    p->step = step;
+    return MSP_OK;
+}
+
 static msp_status ensure_batch(msp_predictor* p, int batch) {
     if (batch <= p->batch_cap) return MSP_OK;
     msp_status s;

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <functional>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "internal.hpp"
 #include "kernels.hpp"
@@ -896,3 +898,70 @@ extern "C" msp_status msp_row_features(msp_handle* h, const msp_csr* A, const ms
 extern "C" long long msp_internal_summary_fallbacks(const msp_handle* h) { return h ? h->summary_fallbacks : -1; }
 
 extern "C" int msp_internal_unsupported_plans(int verbose) { return msp::count_unsupported_plans(verbose); }
+
+extern "C" msp_status msp_autotune(msp_handle* h, const msp_csr* A, const msp_csr* B, const msp_tuning* cand,
+                                   int ncand, int reps, msp_tuning* best, double* times_ms) {
+    if (!h || !cand || ncand <= 0 || reps <= 0 || !best) return fail(MSP_ERR_INVALID_ARG, "bad argument");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
+    // one product: C's row pointers from the allocator, its columns and
+    // values released through it once the call has completed
+    auto run = [&](const msp_opts* o, bool timed, float* ms) -> msp_status {
+        msp_csr_out C;
+        memset(&C, 0, sizeof(C));
+        hipError_t er;
+        if (timed && (er = hipEventRecord(e0, h->stream)) != hipSuccess) return hip_fail(er, "hipEventRecord");
+        msp_status st = msp_spgemm(h, A, B, &C, o);
+        if (st == MSP_OK && timed && (er = hipEventRecord(e1, h->stream)) != hipSuccess)
+            st = hip_fail(er, "hipEventRecord");
+        const msp_status sy = msp_sync(h);
+        if (st == MSP_OK) st = sy;
+        if (st == MSP_OK && timed && (er = hipEventElapsedTime(ms, e0, e1)) != hipSuccess)
+            st = hip_fail(er, "hipEventElapsedTime");
+        if (C.col) h->free_fn(h->alloc_ctx, C.col, h->stream);
+        if (C.row_ptr) h->free_fn(h->alloc_ctx, C.row_ptr, h->stream);
+        return st;
+    };
+    double best_ms = INFINITY;
+    int best_i = -1;
+    msp_status last_err = MSP_OK;
+    for (int c = 0; c < ncand; ++c) {
+        double med = INFINITY;
+        msp_opts o;
+        memset(&o, 0, sizeof(o));
+        o.tuning = cand[c];
+        s = check_tuning(&o.tuning);
+        if (s == MSP_OK) s = run(&o, false, nullptr);          // warm
+        std::vector<double> ts;
+        for (int r = 0; r < reps && s == MSP_OK; ++r) {
+            float ms = 0.f;
+            if ((s = run(&o, true, &ms)) == MSP_OK) ts.push_back(ms);
+        }
+        if (s == MSP_OK && !ts.empty()) {
+            std::sort(ts.begin(), ts.end());
+            med = ts[ts.size() / 2];
+        } else {
+            last_err = s;
+        }
+        if (s == MSP_ERR_HIP) {        // the device reported an error: try nothing more on it
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return s;
+        }
+        if (times_ms) times_ms[c] = med;
+        if (med < best_ms) {
+            best_ms = med;
+            best_i = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_i < 0) return last_err != MSP_OK ? last_err : fail(MSP_ERR_INVALID_ARG, "no candidate ran");
+    *best = cand[best_i];
+    return check_tuning(best);
+}

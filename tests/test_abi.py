@@ -58,3 +58,51 @@ def test_tuning_json_roundtrip_and_rejects():
     with pytest.raises(binding.MspError):
         binding.tuning_from_json('{"hash_scale": 9, "group_scale": 0, "spill_nnz": 4096, '
                                  '"block_rows": 128, "merge_k": 8}')
+
+
+def test_predictor_blob_roundtrip_and_rejects():
+    """The versioned predictor blob (host arrays only): a round trip keeps
+    every byte of the state; a wrong magic, version, count, size or hash
+    is refused."""
+    import struct
+
+    import numpy as np
+    rng = np.random.default_rng(3)
+    p, m, v = (rng.standard_normal(binding.NPARAM).astype(np.float32) for _ in range(3))
+    blob = binding.blob_pack(p, 0.625, m, v, 1234)
+    assert len(blob) == binding.BLOB_BYTES == 24 + 3 * 4 * binding.NPARAM + 8
+    assert blob[:4] == b"MSPP" and struct.unpack_from("<IIfq", blob, 4) == (1, binding.NPARAM, 0.625, 1234)
+    q, d, qm, qv, st = binding.blob_unpack(blob)
+    assert np.array_equal(q, p) and np.array_equal(qm, m) and np.array_equal(qv, v)
+    assert d == 0.625 and st == 1234
+    # the parameters sit right after the header, in creation order
+    assert np.array_equal(np.frombuffer(blob, np.float32, binding.NPARAM, 24), p)
+    # missing moments pack as zeros
+    _, _, zm, zv, _ = binding.blob_unpack(binding.blob_pack(p))
+    assert not zm.any() and not zv.any()
+
+    def refused(b, name):
+        with pytest.raises(binding.MspError) as e:
+            binding.blob_unpack(b)
+        assert e.value.name == name
+
+    refused(b"XSPP" + blob[4:], "MSP_ERR_INVALID_ARG")
+    refused(blob[:4] + struct.pack("<I", 2) + blob[8:], "MSP_ERR_UNSUPPORTED")
+    refused(blob[:8] + struct.pack("<I", 4800) + blob[12:], "MSP_ERR_INVALID_ARG")
+    refused(blob[:-1], "MSP_ERR_INVALID_ARG")
+    flipped = bytearray(blob)
+    flipped[100] ^= 1                       # one parameter bit: the hash no longer matches
+    refused(bytes(flipped), "MSP_ERR_INVALID_ARG")
+    lib = binding.load()
+    # size query, and a buffer one byte short
+    size = ctypes.c_size_t()
+    assert lib.msp_predictor_blob_pack(p.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.c_float(0),
+                                       0, None, 0, ctypes.byref(size)) == 0 and size.value == binding.BLOB_BYTES
+    buf = ctypes.create_string_buffer(binding.BLOB_BYTES)
+    assert lib.msp_predictor_blob_pack(p.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.c_float(0),
+                                       0, buf, binding.BLOB_BYTES - 1, None) == 1
+
+
+def test_autotune_rejects_bad_arguments_on_the_host():
+    lib = binding.load()
+    assert lib.msp_autotune(None, None, None, None, 0, 1, None, None) == 1

@@ -281,37 +281,81 @@ def test_repeat_calls_deterministic_structure(h):
     assert torch.equal(C1.row_ptr, C2.row_ptr) and torch.equal(C1.col, C2.col)
 
 
+def _row_subset(M, rows):
+    """The rows `rows` of M as a CSR matrix of their own (same columns)."""
+    rp = M.row_ptr
+    lens = rp[rows + 1] - rp[rows]
+    nrp = np.zeros(rows.size + 1, np.int64)
+    np.cumsum(lens, out=nrp[1:])
+    idx = np.repeat(rp[rows] - nrp[:-1], lens) + np.arange(int(nrp[-1]))
+    return gen.CSR(int(rows.size), M.ncols, nrp, M.col[idx], M.val[idx])
+
+
+def _device_rows(C, rows):
+    """(row_ptr from 0, col, val) on the host of the rows `rows` of a device
+    result, gathered on the device."""
+    import torch
+    rp = C.row_ptr
+    r = torch.from_numpy(rows.astype(np.int64)).to(rp.device)
+    starts, lens = rp[r], rp[r + 1] - rp[r]
+    nrp = torch.zeros(rows.size + 1, dtype=torch.int64, device=rp.device)
+    torch.cumsum(lens, 0, out=nrp[1:])
+    idx = torch.repeat_interleave(starts - nrp[:-1], lens) + torch.arange(int(nrp[-1]), device=rp.device)
+    return nrp.cpu().numpy(), C.col[idx].cpu().numpy(), C.val[idx].cpu().numpy()
+
+
+# numeric bins of the default tuning: exact row nnz in (lo, hi]
+NUM_BIN_EDGES = [0, 32, 64, 128, 512, 2048, 4096, 1 << 40]
+
+
 @pytest.mark.slow
-def test_rmat_2p20_fp32_sampled(h):
+def test_rmat_2p20_fp32(h):
     """R-MAT 2^20 vertices, 16 x 2^20 edges, (0.57, 0.19, 0.19, 0.05), FP32
-    (0, 1], seed 1: full-size run, parity on sampled rows (the heaviest rows,
-    random rows, rows straddling the bins) and sortedness of every row."""
+    (0, 1], seed 1 (2.09e10 products, nnz(C) = 9.7e9), C = A*A at full size:
+    row_ptr against the oracle's row counts on all 1,048,576 rows; columns
+    and values, in full, on 2,000+ rows stratified by numeric bin (every
+    bin's boundary rows, lo + 1 and hi outputs, and random rows of each
+    bin) and on the contiguous block of the last 65,536 rows."""
     import torch
     A = gen.rmat(20, 16 << 20, seed=1, dtype=np.float32)
     dA = to_dev(A)
     C = h.spgemm(dA, dA)
     torch.cuda.synchronize()
-    st = oracle.row_stats(A, A)
+    ref_nnz = oracle.row_nnz(A, A)
+    rp = C.row_ptr.cpu().numpy()
+    assert rp[0] == 0 and np.array_equal(np.diff(rp), ref_nnz), "row_ptr differs from the oracle's counts"
+    assert C.nnz == int(ref_nnz.sum())
     rng = np.random.default_rng(0)
-    heavy = np.argsort(st["prod"])[-12:]
-    rows = np.concatenate([heavy, rng.integers(0, A.nrows, 300),
-                           np.nonzero(st["prod"] == 0)[0][:5]])
-    worst = check_rows(C, A, A, rows)
-    print(f"nnz(C) = {C.nnz}, max |c-o|/bound on sampled rows = {worst:.3e}")
-    # every row strictly increasing, checked in chunks on the device
-    rp = C.row_ptr
-    nnz = C.nnz
+    pick = []
+    for lo, hi in zip(NUM_BIN_EDGES[:-1], NUM_BIN_EDGES[1:]):
+        inbin = np.nonzero((ref_nnz > lo) & (ref_nnz <= hi))[0]
+        assert inbin.size, f"no row in bin ({lo}, {hi}]"
+        for edge in (lo + 1, hi):
+            pick.append(np.nonzero(ref_nnz == edge)[0][:8])
+        pick.append(rng.choice(inbin, min(inbin.size, 300), replace=False))
+    pick.append(np.argsort(ref_nnz)[-8:])                 # the largest rows
+    pick.append(np.nonzero(ref_nnz == 0)[0][:8])
+    rows = np.unique(np.concatenate(pick))
+    assert rows.size >= 2000
+    block = np.arange(A.nrows - 65536, A.nrows)
+    tol = TOL[np.dtype(np.float32)]
+    worst = 0.0
+    for sel in (rows, block):
+        ref = oracle.spgemm(_row_subset(A, sel), A)
+        grp, gcol, gval = _device_rows(C, sel)
+        worst = max(worst, oracle.compare(grp, gcol, gval, ref, tol))
+        del ref, grp, gcol, gval
+    # every row strictly increasing (a property at any size), on the device in chunks
+    rpd = C.row_ptr
     step = 1 << 28
-    starts = torch.zeros(nnz, dtype=torch.bool, device=rp.device) if nnz < (1 << 31) else None
-    for s in range(0, nnz - 1, step):
-        e = min(nnz - 1, s + step)
-        d = C.col[s + 1:e + 1].to(torch.int64) - C.col[s:e].to(torch.int64)
-        bad = torch.nonzero(d <= 0).flatten() + s + 1      # positions where col does not increase
+    for s0 in range(0, C.nnz - 1, step):
+        e0 = min(C.nnz - 1, s0 + step)
+        d = C.col[s0 + 1:e0 + 1].to(torch.int64) - C.col[s0:e0].to(torch.int64)
+        bad = torch.nonzero(d <= 0).flatten() + s0 + 1
         if bad.numel():
-            # all such positions must be row starts
-            idx = torch.searchsorted(rp, bad, right=False)
-            assert torch.all(rp[idx] == bad), "a row is not strictly increasing"
-    del starts
+            idx = torch.searchsorted(rpd, bad)
+            assert torch.all(rpd[idx] == bad), "a row is not strictly increasing"
+    print(f"nnz(C) = {C.nnz}, {rows.size} stratified rows + 65,536-row block, max |c-o|/bound = {worst:.3e}")
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
