@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the SpGEMM library on one MI355X.
 
-Main line (the `value`): the plain two-phase product C = A*A with A the 2D
-5-point Laplacian on a 1024 x 1024 grid (1,048,576 rows, 5,238,784
-nonzeros, FP64; 26,177,544 intermediate products, nnz(C) = 13,611,012).
-Inputs are copied to HBM once; every timed step is one whole msp_spgemm
-call (statistics, binning, symbolic pass, prefix sum, allocation of C,
-numeric pass with sorted rows).  GFLOP/s = 2 x products / time.
+Main line (the `value`): the plain two-phase product C = A*A with A the
+R-MAT power-law graph of 2^20 vertices and 16 x 2^20 drawn edges,
+(a, b, c, d) = (0.57, 0.19, 0.19, 0.05), duplicates merged, FP32 values in
+(0, 1], seed 1: 1,048,576 rows, 16,086,247 nonzeros, 2.09e10 intermediate
+products, nnz(C) = 9.7e9 (about 78 GB of C).  Inputs are copied to HBM once;
+every timed step is one whole msp_spgemm call (statistics, binning,
+symbolic pass, prefix sum, allocation of C, numeric pass with sorted rows),
+waited for.  GFLOP/s = 2 x products / median step time.
 
 Also reported on the same line:
-  * roofline: the numeric kernel's algorithmic bytes over its average
-    launch time (HIP events on the library's stream), against 8 TB/s;
-  * cpu_baseline: the C oracle on the host cores, on the same workload;
+  * roofline: the global bin's numeric kernel (k_num_win, the dominant
+    kernel), its algorithmic bytes over its average launch time (HIP events
+    on the library's stream), against 8 TB/s;
+  * cpu_baseline: the C oracle on the host cores, on row blocks of the same
+    product streamed one after another (C is never held whole);
+  * configs: the Erdos-Renyi 4096 and 2D Laplacian 1024^2 products, each
+    timed the same way;
   * learned_vs_plain: the one-pass learned product against the plain one on
     the 16 held-out members of a 64-matrix mixed suite (27-point stencils,
     Erdos-Renyi with 4..32 nonzeros per row, R-MAT with degree 8..32; FP64),
@@ -38,13 +44,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 
-# HBM bytes per launch of the numeric kernel on the main workload, from two
+# HBM bytes per launch of the dominant kernel of a workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors
-# read off a 1 GiB copy kernel), valid for the kernel sources whose code
-# (comments aside) has the hash given; any other code reports null.
-MEASURED_TRAFFIC = {"sources_sha256": "13ed929b53e13b7a09aed46c7b7b228829aa6024ed11f3da549be9fe7ee3f597",
-                    "bytes": 262300963}
-KERNEL_SOURCES = ["kernels.hpp", "types.hpp", "spgemm.hip"]
+# read off a 1 GiB copy kernel), valid only for the kernel sources and the
+# tuning whose hash is given; any other state reports null.
+MEASURED_TRAFFIC = {}
+KERNEL_SOURCES = ["kernels.hpp", "types.hpp", "spgemm.hip", "msp_api.hip", "internal.hpp"]
 
 
 def _code_only(text: str) -> str:
@@ -55,13 +60,15 @@ def _code_only(text: str) -> str:
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
-def kernel_sources_hash() -> str:
-    """Hash of the kernel sources' code: a comment edit keeps the measured
-    traffic valid, any code change does not."""
+def kernel_sources_hash(tuning) -> str:
+    """Hash of the kernel sources' code and the tuning in effect: a comment
+    edit keeps a measured traffic figure valid, any code or tuning change
+    does not."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2112_10037_amd", "csrc", name), encoding="utf-8") as f:
             h.update(_code_only(f.read()).encode())
+    h.update(repr(tuple(int(x) for x in tuning)).encode())
     return h.hexdigest()
 
 
@@ -91,34 +98,59 @@ def csr_bytes(nrows: int, nnz: int, vb: int = 8) -> int:
     return (nrows + 1) * 8 + nnz * (4 + vb)
 
 
-def cpu_baseline(A, products: int, budget_s: float) -> dict:
-    """The oracle on the host cores: two thirds of the budget on all
-    threads, one third on one thread."""
+def row_products(A, B) -> np.ndarray:
+    """Intermediate products of every row of A*B (host arithmetic on the
+    generator's arrays: sum of the B-row lengths each row selects)."""
+    blen = np.diff(B.row_ptr).astype(np.int64)
+    cs = np.zeros(A.nnz + 1, dtype=np.int64)
+    np.cumsum(blen[A.col], out=cs[1:])
+    return cs[A.row_ptr[1:]] - cs[A.row_ptr[:-1]]
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, prods: np.ndarray, budget_s: float, block: int = 1024) -> dict:
+    """The oracle on the host cores, on a bounded sample: row blocks of
+    `block` rows spread evenly over the matrix (a stride through the block
+    list, so heavy and light rows are both sampled), each computed and
+    dropped before the next, until the time budget is spent.  GFLOP/s = 2 x
+    products of the blocks done / their time."""
     import oracle
     cores = oracle.num_threads()
-
-    def rate(seconds):
+    nblk = (A.nrows + block - 1) // block
+    order = np.arange(nblk)
+    stride = 97 if nblk % 97 else 89                  # coprime with the block count: every block once
+    order = (order * stride) % nblk
+    done_p = 0
+    done_rows = 0
+    blocks = 0
+    t_all = 0.0
+    for b in order:
+        r0, r1 = int(b) * block, min(A.nrows, (int(b) + 1) * block)
         t0 = time.perf_counter()
-        runs = 0
-        while True:
-            oracle.spgemm(A, A)
-            runs += 1
-            el = time.perf_counter() - t0
-            if el >= seconds:
-                return runs, el
-
-    runs, el = rate(budget_s * 2 / 3)
-    oracle.set_threads(1)
-    try:
-        runs1, el1 = rate(budget_s / 3)
-    finally:
-        oracle.set_threads(cores)
-    return {"value": round(2.0 * products * runs / el / 1e9, 3), "unit": "GFLOP/s",
-            "cores": cores, "kind": "oracle",
-            "sample": f"{runs} full products of the main workload in {el:.1f} s "
-                      f"(C oracle, FP64 dense accumulator, OpenMP over rows)",
-            "single_thread": {"value": round(2.0 * products * runs1 / el1 / 1e9, 3), "unit": "GFLOP/s",
-                              "sample": f"{runs1} full products in {el1:.1f} s on one thread"}}
+        ref = oracle.spgemm(A, A, r0, r1)
+        t_all += time.perf_counter() - t0
+        del ref
+        done_p += int(prods[r0:r1].sum())
+        done_rows += r1 - r0
+        blocks += 1
+        if t_all >= budget_s:
+            break
+    return {"value": round(2.0 * done_p / t_all / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"{blocks} row blocks of {block} rows ({done_rows} rows, {done_p} products, "
+                      f"{done_p / max(int(prods.sum()), 1) * 100:.2f}% of the product's) spread evenly over "
+                      f"the matrix, streamed one at a time, in {t_all:.1f} s (C oracle: FP64 dense "
+                      f"accumulator, OpenMP over rows)",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def vendor_spgemm(dA, products: int, nnz_c: int, reps: int = 20):
@@ -349,25 +381,115 @@ def batched_leg(h, sides, reps: int, tuning_cache: str) -> dict:
             "results_identical_to_plain": same}
 
 
+# plain-path tunings the autotuner compares on the main workload
+PLAIN_CANDIDATES = [(1, 0, 4096, 1024, 8), (1, 0, 2048, 1024, 8), (1, 0, 1024, 1024, 8), (2, 0, 4096, 1024, 8)]
+
+
+def autotune_plain(h, dA, A, path: str, candidates=PLAIN_CANDIDATES, reps: int = 3):
+    """Best plain-path tuning for this product's shape: from the JSON cache
+    at `path` when it holds one, else measured with msp_autotune (median of
+    whole calls) and stored.  Returns (tuning, info)."""
+    key = "plain:" + hashlib.sha256(np.ascontiguousarray(A.row_ptr).tobytes()[:1 << 20] +
+                                    str((A.nrows, A.ncols, A.nnz, str(A.val.dtype))).encode()).hexdigest()[:24]
+    cache = {}
+    if path and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        return tuple(cache[key]["tuning"]), {"cached": True, "median_ms": cache[key].get("median_ms")}
+    best, times = h.autotune(dA, dA, candidates, reps=reps)
+    cache[key] = {"tuning": list(best), "candidates": [list(c) for c in candidates],
+                  "median_ms": [round(t, 3) for t in times]}
+    if path:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return tuple(best), {"cached": False, "median_ms": cache[key]["median_ms"]}
+
+
+def step_times(h, dA, steps: int):
+    """Seconds of each of `steps` whole calls, each waited for."""
+    import torch
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        C = h.spgemm(dA, dA, check=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        del C
+    return ts
+
+
+def config_entry(h, name: str, steps: int, warmup: int) -> dict:
+    """One of the smaller configs timed like the main line (median of whole
+    calls), with its numeric phase's algorithmic rate."""
+    import torch
+    from paper_2112_10037_amd import binding
+    desc, A = workload(name)
+    prods = int(row_products(A, A).sum())
+    dA = binding.DeviceCSR.from_host(A, "cuda:0")
+    C = h.spgemm(dA, dA)
+    nnz_c = C.nnz
+    del C
+    for _ in range(warmup):
+        C = h.spgemm(dA, dA)
+        del C
+    h.sync()
+    h.profile(True, phases=["numeric"])
+    ts = step_times(h, dA, steps)
+    h.sync()
+    num_ms, num_n = h.profile_get()["numeric"]
+    h.profile(False)
+    med = float(np.median(ts))
+    num_s = num_ms / max(num_n, 1) / 1e3
+    alg = algorithmic_bytes(A, nnz_c)
+    del dA
+    torch.cuda.empty_cache()
+    return {"workload": desc, "rows": A.nrows, "nnz_a": A.nnz, "products": prods, "nnz_c": nnz_c,
+            "steps": steps, "ms_per_step_median": round(med * 1e3, 4),
+            "gflops": round(2.0 * prods / med / 1e9, 3),
+            "numeric_ms": round(num_s * 1e3, 5),
+            "numeric_algorithmic_gbs": round(alg / num_s / 1e9, 1),
+            "numeric_frac_of_peak": round(alg / num_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def global_bin_bytes(A, row_nnz: np.ndarray, thresh: int) -> tuple[int, int]:
+    """Algorithmic bytes of one launch of the global bin's kernel: for each
+    row with more than `thresh` outputs, its A row (8 B of row pointers and
+    one column and value per entry), its C row (the same), and B once
+    (every row pointer and entry).  Returns (bytes, rows)."""
+    vb = A.val.dtype.itemsize
+    g = row_nnz > thresh
+    nnz_a = np.diff(A.row_ptr)
+    b = (A.nrows + 1) * 8 + A.nnz * (4 + vb)
+    per_row = int(g.sum()) * 16 + int(nnz_a[g].sum()) * (4 + vb) + int(row_nnz[g].sum()) * (4 + vb)
+    return per_row + b, int(g.sum())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="laplacian2d_1024")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the smaller configs' entries")
+    ap.add_argument("--no-autotune", action="store_true", help="run the library's default tuning")
     ap.add_argument("--legs-reps", type=int, default=5)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--tuning-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "msp_tuning.json"))
     ap.add_argument("--tuning", default=None,
-                    help="hash_scale,group_scale,spill_nnz,block_rows,merge_k (default: library's)")
+                    help="hash_scale,group_scale,spill_nnz,block_rows,merge_k (default: autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration); implies --no-vendor")
-    ap.add_argument("--no-vendor", action="store_true",
-                    help="skip the same product through torch.sparse.mm (hipSPARSE)")
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--vendor", action="store_true",
+                    help="also time the same product through torch.sparse.mm (hipSPARSE), as context")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: there is no multi-GPU path in this library "
@@ -375,7 +497,11 @@ def main():
         sys.exit(2)
 
     from paper_2112_10037_amd import gen
+    t0 = time.perf_counter()
     desc, A = workload(args.workload)
+    prods_row = row_products(A, A)
+    products = int(prods_row.sum())
+    progress(f"main workload built in {time.perf_counter() - t0:.1f} s")
     workers = max(1, min(16, os.cpu_count() or 1))
     suite = mats = None
     if not args.no_learned:
@@ -387,12 +513,16 @@ def main():
     import torch
     from paper_2112_10037_amd import binding
 
-    # products of A*A: every entry (i, k) of A meets the nnz(A_k) entries of row k
-    products = int(np.diff(A.row_ptr)[A.col].sum(dtype=np.int64))
     dA = binding.DeviceCSR.from_host(A, "cuda:0")
     h = binding.Handle(0)
+    tinfo = None
     if args.tuning:
         h.set_tuning(tuple(int(x) for x in args.tuning.split(",")))
+    elif not args.no_autotune:
+        tuning, tinfo = autotune_plain(h, dA, A, args.tuning_cache)
+        h.set_tuning(tuning)
+        progress(f"plain tuning {tuning} (cached: {tinfo['cached']})")
+    tuning = h.get_tuning()
 
     # the cold first call (workspace allocations, first launches), reported apart
     torch.cuda.synchronize()
@@ -401,27 +531,25 @@ def main():
     torch.cuda.synchronize()
     first_ms = (time.perf_counter() - t_cold) * 1e3
     nnz_c = C.nnz
+    row_nnz = np.diff(C.row_ptr.cpu().numpy())
     del C
     for _ in range(args.warmup):
         C = h.spgemm(dA, dA)
         del C
     h.sync()
 
-    # timed steps: HIP events around the numeric pass only (the roofline's
-    # kernel), so that the other phases run as they do unprofiled
-    h.profile(True, phases=["numeric"])
+    # timed steps: HIP events around the global bin's kernel only (the
+    # roofline's kernel), so that the rest runs as it does unprofiled
+    h.profile(True, phases=["global_bin"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        C = h.spgemm(dA, dA, check=False)
-        del C
-    torch.cuda.synchronize()
+    ts = step_times(h, dA, args.steps)
     el = time.perf_counter() - t0
     h.sync()          # raises if any timed call flagged an internal error
     prof = h.profile_get()
     # phase breakdown from a separate, fully profiled run
     h.profile(True)
-    nph = max(5, args.steps // 5)
+    nph = max(3, args.steps // 3)
     for _ in range(nph):
         C = h.spgemm(dA, dA, check=False)
         del C
@@ -429,19 +557,27 @@ def main():
     prof_all = h.profile_get()
     h.profile(False)
 
-    ms_step = el * 1e3 / args.steps
-    gflops = 2.0 * products / (el / args.steps) / 1e9
-    num_ms, num_n = prof["numeric"]
-    num_avg_s = num_ms / max(num_n, 1) / 1e3
+    med = float(np.median(ts))
+    gflops = 2.0 * products / med / 1e9
     alg = algorithmic_bytes(A, nnz_c)
-    achieved = alg / num_avg_s / 1e9
-    traffic = None
-    if (args.workload == "laplacian2d_1024" and MEASURED_TRAFFIC["sources_sha256"]
-            and MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_hash()):
-        traffic = MEASURED_TRAFFIC["bytes"]
+    gb_ms, gb_n = prof["global_bin"]
+    roof = None
+    if gb_n:
+        gb_s = gb_ms / gb_n / 1e3
+        gbytes, grows = global_bin_bytes(A, row_nnz, int(tuning[2]))
+        achieved = gbytes / gb_s / 1e9
+        key = MEASURED_TRAFFIC.get(args.workload)
+        traffic = key["bytes"] if key and key["sources_sha256"] == kernel_sources_hash(tuning) else None
+        roof = {"bound": "hbm", "kernel": "global bin, windowed numeric kernel (k_num_win)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": gbytes, "rows": grows, "avg_launch_ms": round(gb_s * 1e3, 4),
+                "launches_timed": gb_n}
     copy_gbs = copy_bandwidth()
-    # (not in counter runs: the library's copies would mix with the calibration copy)
-    vendor = None if (args.no_vendor or args.calibrate_copy) else vendor_spgemm(dA, products, nnz_c)
+    if roof:
+        roof["copy_gbs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    vendor = vendor_spgemm(dA, products, nnz_c) if args.vendor else None
 
     out = {
         "metric": "SpGEMM GFLOP/s (2x products/s)",
@@ -450,38 +586,40 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(med * 1e3, 4),
+        "ms_per_step_mean": round(el * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if A.val.dtype == np.float64 else "f32",
         "data": "synthetic",
         "config": {"workload": desc, "rows": A.nrows, "nnz_a": A.nnz, "products": products,
-                   "nnz_c": nnz_c, "path": "plain two-phase", "tuning": list(h.get_tuning())},
-        "roofline": {"bound": "hbm",
-                     "kernel": "numeric pass (k_num_merge)" if args.workload == "laplacian2d_1024"
-                     else "numeric pass (every bin kernel)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes": alg, "avg_launch_ms": round(num_avg_s * 1e3, 5),
-                     "traffic_gbs": round(traffic / num_avg_s / 1e9, 1) if traffic else None,
-                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+                   "nnz_c": nnz_c, "path": "plain two-phase", "tuning": list(tuning),
+                   "tuning_autotuned": tinfo},
+        "roofline": roof,
+        "hbm_gbs_whole_step_algorithmic": round(alg / med / 1e9, 1),
+        "whole_step_frac_of_peak": round(alg / med / 1e9 / HBM_PEAK_GBS, 4),
         "first_call_ms": round(first_ms, 3),
-        "vendor_library": vendor,
-        "phases_ms_per_step_profiled": {k: round(v[0] / nph, 5) for k, v in prof_all.items() if v[1]},
-        "hbm_gbs_whole_step_algorithmic": round(alg / (el / args.steps) / 1e9, 1),
+        "phases_ms_per_step_profiled": {k: round(v[0] / nph, 4) for k, v in prof_all.items() if v[1]},
         "summary_fallbacks": h.summary_fallbacks(),
     }
+    if vendor is not None:
+        out["vendor_library"] = vendor
     del dA
     torch.cuda.empty_cache()
-    progress(f"main: {gflops:.1f} GFLOP/s, {ms_step:.4f} ms per step")
+    progress(f"main: {gflops:.1f} GFLOP/s, {med * 1e3:.3f} ms per step (median)")
+    h.set_tuning((0, 0, 0, 0, 0))               # the library's defaults for the other legs
+    if not args.no_configs:
+        out["configs"] = {"er4096": config_entry(h, "er4096", 200, 10),
+                          "laplacian2d_1024": config_entry(h, "laplacian2d_1024", 50, 5)}
+        progress("configs done")
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg(h, suite, mats, args.legs_reps, args.train_steps)
         del mats
     if not args.no_batched:
         out["batched_vs_plain"] = batched_leg(h, sides, max(args.legs_reps, 10), args.tuning_cache)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(A, products, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A, prods_row, args.cpu_seconds)
     if args.calibrate_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")

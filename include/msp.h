@@ -166,6 +166,7 @@ msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B,
  * error the numeric kernels of earlier calls flagged. */
 msp_status msp_sync(msp_handle* h);
 
+
 /*
  * Autotuner for one product (it replaces the paper's analytic choice of its
  * hardware parameters, Sec. IV-B4, Eqs. 2-3, by measurement): runs
@@ -393,7 +394,9 @@ enum {
     MSP_PHASE_FALLBACK = 5,    /* exact fallback rows (learned form)      */
     MSP_PHASE_COMPACT = 6,     /* compaction (learned form)               */
     MSP_PHASE_BATCH = 7,       /* one batched graph launch                */
-    MSP_NUM_PHASES = 8
+    MSP_PHASE_GLOBAL_BIN = 8,  /* the global bin's windowed numeric kernel
+                                  (an interval inside MSP_PHASE_NUMERIC)   */
+    MSP_NUM_PHASES = 9
 };
 
 typedef struct {

@@ -72,8 +72,8 @@ class c_batch_stats(ctypes.Structure):
                 ("sym_bins", ctypes.c_int32 * 2), ("num_bins", ctypes.c_int32 * 2)]
 
 
-NUM_PHASES = 8
-PHASES = ["row_stats", "symbolic", "scan", "numeric", "predict", "fallback", "compact", "batch"]
+NUM_PHASES = 9
+PHASES = ["row_stats", "symbolic", "scan", "numeric", "predict", "fallback", "compact", "batch", "global_bin"]
 
 
 class c_profile(ctypes.Structure):

@@ -13,9 +13,18 @@
 
 namespace msp {
 
+// A fixed block of device memory that workspaces are carved from in order
+// (the allocation-free entry point's scratch); nothing is returned to it
+// before the call ends.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+};
+
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
+    Arena* arena = nullptr;         // set: ensure() takes memory from the arena, release() frees nothing
     msp_status ensure(size_t need);
     void release();
     template <typename T> T* as() const { return (T*)ptr; }
@@ -78,6 +87,9 @@ struct Profiler {
     hipEvent_t get();
     void begin(int phase, hipStream_t s);
     void end(hipStream_t s);
+    // an interval inside the open phase (one kernel), timed the same way
+    hipEvent_t sub_begin(int phase, hipStream_t s);
+    void sub_end(int phase, hipEvent_t a, hipStream_t s);
     void collect();          // fold completed intervals (after a sync)
     void reset();
     void release();
@@ -97,6 +109,12 @@ struct msp_handle {
     msp::DevBuf info, u, rnnz, perm, tiles, sbm, prod;
     msp::DevBuf bsum;               // 256-row workgroup totals of the fused symbolic pass
     msp::DevBuf gsl;                // per-workgroup bitmap copies of the sliced global-bin kernel
+    // column windows of the global bin (plain product): the symbolic pass's
+    // per-window row counts, B's window index, and the rows left to the
+    // self-counting kernel
+    msp::DevBuf win_islot, win_row, win_cnt, win_bslot, win_wpos, win_fb, win_rbm, win_bms;
+    size_t total_mem = 0;           // device memory (bounds the bitmap store)
+    msp::WinRec cur_rec{};          // records of the product in progress (cnt null: none)
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
     int* hpending = nullptr;        // pinned: error bits of the last call's numeric
                                     // kernels, forwarded by the next call's first kernel
@@ -149,8 +167,15 @@ msp_status take_pending_error(msp_handle* h);
 msp_status check_pair(const msp_csr* A, const msp_csr* B);
 msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B);
 msp_status device_error(int err);
+// Caller-provided C buffers (col and val of `cap` entries each).
+struct CPlace {
+    int32_t* col;
+    void* val;
+    long long cap;
+};
 msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C, const msp_opts* opts,
-                       const std::function<void*(size_t)>& alloc_cv, const std::function<void(void*)>& free_cv);
+                       const std::function<void*(size_t)>& alloc_cv, const std::function<void(void*)>& free_cv,
+                       const CPlace* place = nullptr);
 msp_status run_numeric_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,
                             const int* counts_host, const int32_t* key, const int64_t* crp,
                             int32_t* ccol, void* cval, int32_t* cnt_out);

@@ -25,6 +25,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "types.hpp"
 
 namespace msp {
@@ -429,6 +431,37 @@ __device__ __forceinline__ int hash_slot_of(int32_t* keys, int32_t j, int* err) 
     return -1;
 }
 
+// Window record of a symbolic row with `tot` outputs, for the numeric
+// global bin (see WinRec), in two steps around the kernel's own count of the
+// row's outputs per window: win_record_open clears the counts in s_wc and
+// takes a record slot (false: no record for this row); the kernel adds into
+// s_wc with LDS atomics; win_record_close writes the counts out.  Called by
+// the whole workgroup with a uniform tot; both end with a barrier.
+__device__ __forceinline__ bool win_record_open(int* cnt_ptr_nonnull, int nw, int thresh, int* nrec, long long tot,
+                                                int* s_wc, int* s_slot) {
+    if (!cnt_ptr_nonnull || tot <= thresh) return false;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) s_wc[w] = 0;
+    if (threadIdx.x == 0) *s_slot = atomicAdd(nrec, 1);
+    __syncthreads();
+    return true;
+}
+
+__device__ __forceinline__ void win_record_close(const WinRec& rec, int row, const int* s_wc, const int* s_slot,
+                                                 int bm_slot = -1) {
+    __syncthreads();
+    const int slot = *s_slot;
+    if (slot < rec.cap) {
+        uint16_t* out = rec.cnt + (long long)slot * rec.nw;
+        for (int w = threadIdx.x; w < rec.nw; w += blockDim.x) out[w] = (uint16_t)s_wc[w];
+        if (threadIdx.x == 0) {
+            rec.islot[row] = slot;
+            rec.row[slot] = row;
+            rec.rec_bm[slot] = bm_slot;
+        }
+    }
+    __syncthreads();
+}
+
 // Rows per workgroup for a lane-group kernel of G lanes.
 template <int G>
 struct GroupCfg {
@@ -506,11 +539,13 @@ __global__ void __launch_bounds__(BS)
 k_sym_block(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp, WinRec rec) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
     __shared__ int32_t keys[T];
+    __shared__ int s_wc[BATCH ? 1 : kWinMaxNw];
+    __shared__ int s_rslot;
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
     __shared__ BlockScanSmem<BS> sm;
@@ -548,6 +583,15 @@ k_sym_block(Work wk,
         }
         const long long tot = block_sum<BS>(cnt, sm);
         if (tid == 0) row_nnz[row] = (int32_t)tot;
+        if constexpr (!BATCH) {
+            if (win_record_open((int*)rec.cnt, rec.nw, rec.thresh, rec.nrec, tot, s_wc, &s_rslot)) {
+                for (int i = tid; i < T; i += BS) {
+                    const int32_t k = keys[i];
+                    if (k != kEmpty) atomicAdd(&s_wc[k >> kWinLog], 1);
+                }
+                win_record_close(rec, row, s_wc, &s_rslot);
+            }
+        }
         __syncthreads();
     }
     if (err) atomicOr(&info->err, kErrProbe);
@@ -560,11 +604,13 @@ __global__ void __launch_bounds__(BS)
 k_sym_bitmap(Work wk, long long ncols,
              const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
              const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-             int32_t* __restrict__ row_nnz, uint32_t* gslab, DevInfo* info, RowMap mp) {
+             int32_t* __restrict__ row_nnz, uint32_t* gslab, DevInfo* info, RowMap mp, WinRec rec) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
     extern __shared__ uint32_t dyn_smem[];
+    __shared__ int s_wc[BATCH ? 1 : kWinMaxNw];
+    __shared__ int s_rslot, s_bmslot;
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
     __shared__ BlockScanSmem<BS> sm;
@@ -577,7 +623,7 @@ k_sym_bitmap(Work wk, long long ncols,
         for (long long w = tid; w < words; w += BS) bm[w] = 0u;
         __syncthreads();
         const long long a0 = arp[row], a1 = arp[row + 1];
-        long long cnt = 0;
+        long long cnt = 0, prod_row = 0;
         for (long long c0 = a0; c0 < a1; c0 += BS) {
             const long long p = c0 + tid;
             long long len = 0, bst = 0;
@@ -588,6 +634,7 @@ k_sym_bitmap(Work wk, long long ncols,
             }
             long long total;
             const long long incl = block_incl_scan<BS>(len, sm, &total);
+            prod_row += total;
             s_off[tid] = incl;
             s_bst[tid] = bst - (incl - len);
             __syncthreads();
@@ -624,6 +671,34 @@ k_sym_bitmap(Work wk, long long ncols,
         }
         const long long tot = block_sum<BS>(cnt, sm);
         if (tid == 0) row_nnz[row] = (int32_t)tot;
+        if constexpr (!BATCH) {
+            if (win_record_open((int*)rec.cnt, rec.nw, rec.thresh, rec.nrec, tot, s_wc, &s_rslot)) {
+                // a wave sums 64 consecutive words (half a window) with one atomic
+                const int lane = tid & 63;
+                for (long long w0 = (long long)(tid >> 6) * 64; w0 < words; w0 += BS) {
+                    const long long w = w0 + lane;
+                    int c = 0;
+                    if (w < words) c = __builtin_popcount(LDSBM ? bm[w] : load_coherent(bm + w));
+#pragma unroll
+                    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d);
+                    if (lane == 0 && c) atomicAdd(&s_wc[(int)(w0 >> (kWinLog - 5))], c);
+                }
+                // the bitmap itself for a row with many products per column
+                int bm_slot = -1;
+                if (rec.bms && prod_row >= rec.bms_min_prod) {
+                    if (tid == 0) s_bmslot = atomicAdd(rec.nbms, 1);
+                    __syncthreads();
+                    bm_slot = s_bmslot < rec.bms_cap ? s_bmslot : -1;
+                    if (bm_slot >= 0) {
+                        const long long sw = (long long)rec.nw * (kWin / 32);   // words of whole windows
+                        uint32_t* dst = rec.bms + (long long)bm_slot * sw;
+                        for (long long w = tid; w < sw; w += BS)
+                            dst[w] = w < words ? (LDSBM ? bm[w] : load_coherent(bm + w)) : 0u;
+                    }
+                }
+                win_record_close(rec, row, s_wc, &s_rslot, bm_slot);
+            }
+        }
         __syncthreads();
     }
     (void)info;
@@ -2173,6 +2248,370 @@ k_num_slice(Work wk, long long ncols, long long span,
         }
         __syncthreads();
     }
+}
+
+// ===========================================================================
+// Global bin in column windows (rows the symbolic pass recorded)
+// ===========================================================================
+
+// Window index of B: one wave per B row.  A row with at least min_len
+// entries takes a slot and stores, for every boundary w = 0..nw, the
+// position (from the row's start) of its first entry with column >= w kWin;
+// rows without a slot get bslot = -1.  An entry with column j whose
+// predecessor has column j' is the first at or past the boundaries w with
+// j' < w kWin <= j; the boundaries past the last entry get the length.
+static __global__ void __launch_bounds__(256)
+k_bwin_index(long long brows, const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, int nw,
+             int min_len, long long max_slots, int32_t* __restrict__ bslot, int32_t* __restrict__ wpos,
+             DevInfo* info) {
+    const int lane = threadIdx.x & 63;
+    const long long nwave = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long k = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < brows; k += nwave) {
+        const long long s = brp[k], e = brp[k + 1];
+        int slot = -1;
+        if (e - s >= min_len) {
+            if (lane == 0) slot = atomicAdd(&info->win_nbs, 1);
+            slot = __shfl(slot, 0);
+            if (slot >= max_slots) slot = -1;           // the host sizes max_slots to cover every such row
+        }
+        if (lane == 0) bslot[k] = slot;
+        if (slot < 0) continue;
+        int32_t* wp = wpos + (long long)slot * (nw + 1);
+        for (long long p = s + lane; p < e; p += 64) {
+            const int j = bcol[p];
+            const int w_lo = p > s ? (bcol[p - 1] >> kWinLog) + 1 : 0;
+            for (int w = w_lo; w <= (j >> kWinLog); ++w) wp[w] = (int32_t)(p - s);
+            if (p == e - 1)
+                for (int w = (j >> kWinLog) + 1; w <= nw; ++w) wp[w] = (int32_t)(e - s);
+        }
+    }
+}
+
+// Numeric pass of a global-bin row with a window record.  The row's windows
+// are grouped into slices whose LDS cost (kWinFixed per window, kWinOut per
+// output, known exactly from the record) fits the budget; the greedy
+// grouping takes the longest run of windows from the current one that fits,
+// and any single window fits by construction.  For each slice:
+//   1. every A entry's part of its B row in the slice's columns (two loads
+//      from the window index, or a search in a short B row);
+//   2. bitmap pass: the products' columns set bits in an LDS bitmap of the
+//      slice's columns;
+//   3. each 64-bit word's rank (outputs before it) by a workgroup scan; the
+//      total must equal the record's count;
+//   4. accumulation pass: each product adds into the FP64 accumulator at its
+//      column's rank (LDS atomics);
+//   5. the slice's columns are listed in rank order from the bitmap, and the
+//      slice goes out with coalesced stores at its first output's place in C.
+// The products are dealt to the waves in contiguous runs, so the lanes of a
+// wave gather neighbouring entries of one B row.  Rows without a valid
+// record are appended to fb_list (their count in info->win_fb[0]) for the
+// self-counting global-bin kernel.
+constexpr int kWinBS = 1024;                   // threads of the windowed kernel (one workgroup per CU)
+constexpr int kWinRU = 4;                      // products per lane and pipeline stage
+constexpr bool kWinPipe = false;               // gathers of the next stage issued before the current LDS work
+constexpr bool kWinOr32 = false;               // bitmap pass: 32-bit atomic ORs instead of 64-bit
+constexpr bool kWinSwizzle = true;             // accumulator index swizzled within 32-entry groups
+
+// Accumulator slots of a slice of n outputs, and the slot of rank r: with
+// the swizzle, ranks are permuted within groups of 32 (the group padded to
+// full size), so that lanes adding at ranks a fixed stride apart spread
+// over more LDS banks.
+constexpr int kWinSlack = kWinSwizzle ? 31 * 8 : 0;    // LDS bytes of the last group's padding
+__device__ __forceinline__ int win_acc_len(int n) { return kWinSwizzle ? (n + 31) & ~31 : n; }
+__device__ __forceinline__ int win_swz(int r) { return kWinSwizzle ? r ^ ((r >> 5) & 31) : r; }
+
+template <int BS, typename VT>
+__global__ void __launch_bounds__(BS)
+k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
+          const VT* __restrict__ aval, const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
+          const VT* __restrict__ bval, const int32_t* __restrict__ bslot, const int32_t* __restrict__ wpos,
+          WinRec rec, const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
+          long long budget, int32_t* __restrict__ fb_list, DevInfo* info) {
+    static_assert(BS >= kWinMaxNw, "one window count per thread");
+    int nrows_bin;
+    const int32_t* perm;
+    work_rows(wk, &nrows_bin, &perm);
+    constexpr int RU = kWinRU;
+    // FP64 values double the pipeline's registers: the second stage is kept for FP32 only
+    constexpr bool PIPE = kWinPipe && sizeof(VT) == 4;
+    constexpr int NWV = BS / 64;
+    extern __shared__ __align__(16) unsigned long long dyn_win[];
+    __shared__ long long s_off[BS];
+    __shared__ long long s_bst[BS];
+    __shared__ double s_a[BS];
+    __shared__ BlockScanSmem<BS> sm;
+    __shared__ int s_rk[kWinMaxNw + 1];         // outputs of the row before window w
+    __shared__ int s_sb[kWinMaxNw + 1];         // first window of each slice
+    __shared__ int s_ns, s_rec;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nrec = min(__hip_atomic_load(rec.nrec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), rec.cap);
+    bool bad = false;
+    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+        const int row = perm ? perm[slot] : (int)slot;
+        const long long rp = crp[row], rlen = crp[row + 1] - rp;
+        if (tid == 0) {
+            int r = -1;
+            if (rlen > 0) {                             // (an empty row has nothing to write)
+                r = rec.islot[row];
+                if (r < 0 || r >= nrec || rec.row[r] != row) {
+                    r = -1;
+                    fb_list[atomicAdd(&info->win_fb[0], 1)] = row;
+                }
+            }
+            s_rec = r;
+        }
+        __syncthreads();
+        const int r = s_rec;
+        if (r >= 0) {
+            const int rbm = rec.bms ? rec.rec_bm[r] : -1;     // the row's stored bitmap, if any
+            const unsigned long long* sbm =
+                rbm >= 0 ? reinterpret_cast<const unsigned long long*>(rec.bms) + (long long)rbm * nw * kWinWords
+                         : nullptr;
+            // exclusive prefix of the window counts
+            const int c = tid < nw ? (int)rec.cnt[(long long)r * nw + tid] : 0;
+            long long tot;
+            const long long incl = block_incl_scan<BS>(c, sm, &tot);
+            if (tid < nw) s_rk[tid] = (int)(incl - c);
+            if (tid == 0) s_rk[nw] = (int)tot;
+            if (tot != rlen) bad = true;               // uniform
+            __syncthreads();
+            // slices: wave 0 takes, from each start, the longest run of windows that fits
+            if (wv == 0) {
+                int start = 0, ns = 0;
+                while (start < nw) {
+                    int e = start + 1;
+                    for (int b0 = start + 1; b0 <= nw; b0 += 64) {
+                        const int cand = b0 + lane;
+                        const bool fit = cand <= nw && (long long)kWinFixed * (cand - start) +
+                                                               (long long)kWinOut * (s_rk[cand] - s_rk[start]) +
+                                                               kWinSlack <= budget;
+                        const int run = leading_run(__ballot(fit));
+                        if (run > 0) e = b0 + run - 1;
+                        if (run < 64) break;
+                    }
+                    if (lane == 0) s_sb[ns] = start;
+                    ++ns;
+                    start = e;
+                }
+                if (lane == 0) {
+                    s_sb[ns] = nw;
+                    s_ns = ns;
+                }
+            }
+            __syncthreads();
+            const int ns = s_ns;
+            const long long a0 = arp[row], a1 = arp[row + 1];
+            const bool one_chunk = a1 - a0 <= BS;
+            // a one-chunk row keeps its thread's A entry across the slices
+            int my_bsl = -1;
+            long long my_s = 0, my_e = 0, my_cur = 0;
+            VT my_a = 0;
+            if (one_chunk && a0 + tid < a1) {
+                const long long p = a0 + tid;
+                const int k = acol[p];
+                my_a = aval[p];
+                my_s = brp[k];
+                my_e = brp[k + 1];
+                my_bsl = bslot[k];
+                my_cur = my_s;
+            }
+            for (int sl = 0; sl < ns && !bad; ++sl) {
+                const int w0 = s_sb[sl], w1 = s_sb[sl + 1];
+                const int nout = s_rk[w1] - s_rk[w0];
+                if (nout == 0) continue;                // uniform
+                const long long c_lo = (long long)w0 << kWinLog, c_hi = (long long)w1 << kWinLog;
+                const int nwd = (w1 - w0) * kWinWords;
+                unsigned long long* bm = dyn_win;
+                uint32_t* wr = reinterpret_cast<uint32_t*>(bm + nwd);
+                double* acc = reinterpret_cast<double*>(wr + nwd);            // nwd is even: 8-byte aligned
+                int32_t* colbuf = reinterpret_cast<int32_t*>(acc + win_acc_len(nout));
+                __syncthreads();                        // the previous slice is done with LDS
+                if (sbm) {
+                    for (int i = tid; i < nwd; i += BS) bm[i] = sbm[(long long)w0 * kWinWords + i];
+                } else {
+                    for (int i = tid; i < nwd; i += BS) bm[i] = 0ull;
+                }
+                __syncthreads();
+                // the part [lo, hi) of A entry p's B row in [c_lo, c_hi)
+                auto range = [&](long long s0, long long e0, int bsl, long long from, long long* lo, long long* hi) {
+                    if (bsl >= 0) {
+                        const int32_t* wp = wpos + (long long)bsl * (nw + 1);
+                        *lo = s0 + wp[w0];
+                        *hi = s0 + wp[w1];
+                    } else {
+                        *lo = lower_bound_col(bcol, from, e0, c_lo);
+                        *hi = lower_bound_col(bcol, *lo, e0, c_hi);
+                    }
+                };
+                // both passes walk the same products: PASS 0 sets bitmap bits,
+                // PASS 1 adds a * b at the column's rank
+                auto products = [&](auto pass_tag) {
+                    constexpr int PASS = decltype(pass_tag)::value;
+                    for (long long c0 = a0; c0 < a1; c0 += BS) {
+                        if (!(one_chunk && PASS == 1)) {     // a one-chunk row's ranges stay in LDS
+                            long long len = 0, bst = 0;
+                            double a = 0.0;
+                            const long long p = c0 + tid;
+                            if (p < a1) {
+                                long long lo, hi;
+                                if (one_chunk) {
+                                    range(my_s, my_e, my_bsl, my_cur, &lo, &hi);
+                                    my_cur = hi;
+                                    a = to_f64(my_a);
+                                } else {
+                                    const int k = acol[p];
+                                    a = to_f64(aval[p]);
+                                    const long long s0 = brp[k];
+                                    range(s0, brp[k + 1], bslot[k], s0, &lo, &hi);
+                                }
+                                bst = lo;
+                                len = hi - lo;
+                            }
+                            long long total;
+                            const long long incl = block_incl_scan<BS>(len, sm, &total);
+                            s_off[tid] = incl;
+                            s_bst[tid] = bst - (incl - len);
+                            s_a[tid] = a;
+                            __syncthreads();
+                        }
+                        const long long total = s_off[BS - 1] > 0 ? s_off[BS - 1] : 0;
+                        const int nact = (int)((a1 - c0) < BS ? (a1 - c0) : BS);
+                        // contiguous runs of products per wave, whole 64-lane steps
+                        const long long per = ((total + NWV - 1) / NWV + 63) & ~63LL;
+                        const long long qb = (long long)wv * per;
+                        const long long qe = qb + per < total ? qb + per : total;
+                        // owner t of the lane's current product, with its end offset,
+                        // B base and value kept in registers (LDS reads only when t moves)
+                        int t = -1;
+                        long long t_end = 0, t_base = 0;
+                        VT t_a = 0;
+                        // two-stage pipeline: the gathers of the next RU products are
+                        // in flight while the current ones go into LDS
+                        int32_t jc[RU], jn[RU];
+                        VT vc[RU], vn[RU], ac[RU], an[RU];
+                        auto gather = [&](long long q0, int32_t* jj, VT* vv, VT* aa) {
+#pragma unroll
+                            for (int u = 0; u < RU; ++u) {
+                                const long long q = q0 + u * 64 + lane;
+                                jj[u] = -1;
+                                if (q < qe) {
+                                    if (t < 0 || t_end <= q) {
+                                        if (t < 0) t = owner_search(s_off, nact, q);
+                                        else do ++t; while (s_off[t] <= q);
+                                        t_end = s_off[t];
+                                        t_base = s_bst[t];
+                                        if constexpr (PASS == 1) t_a = (VT)s_a[t];
+                                    }
+                                    const long long bi = t_base + q;
+                                    jj[u] = bcol[bi];
+                                    if constexpr (PASS == 1) {
+                                        vv[u] = bval[bi];
+                                        aa[u] = t_a;
+                                    }
+                                }
+                            }
+                        };
+                        auto consume = [&](const int32_t* jj, const VT* vv, const VT* aa) {
+#pragma unroll
+                            for (int u = 0; u < RU; ++u) {
+                                if (jj[u] < 0) continue;
+                                const int jl = (int)(jj[u] - c_lo);
+                                const int w = jl >> 6;
+                                const unsigned long long bit = 1ull << (jl & 63);
+                                if constexpr (PASS == 0) {
+                                    if constexpr (kWinOr32)
+                                        atomicOr(reinterpret_cast<uint32_t*>(bm) + (jl >> 5), 1u << (jl & 31));
+                                    else
+                                        atomicOr(&bm[w], bit);
+                                } else {
+                                    const int rk = (int)wr[w] + __builtin_popcountll(bm[w] & (bit - 1ull));
+                                    atomicAdd(&acc[win_swz(rk)], to_f64(aa[u]) * to_f64(vv[u]));
+                                }
+                            }
+                        };
+                        if constexpr (PIPE) {
+                            if (qb < qe) gather(qb, jc, vc, ac);
+                            for (long long q0 = qb; q0 < qe; q0 += 64 * RU) {
+                                const bool more = q0 + 64 * RU < qe;      // wave-uniform
+                                if (more) gather(q0 + 64 * RU, jn, vn, an);
+                                consume(jc, vc, ac);
+#pragma unroll
+                                for (int u = 0; u < RU; ++u) {
+                                    jc[u] = jn[u];
+                                    vc[u] = vn[u];
+                                    ac[u] = an[u];
+                                }
+                            }
+                        } else {
+                            for (long long q0 = qb; q0 < qe; q0 += 64 * RU) {
+                                gather(q0, jc, vc, ac);
+                                consume(jc, vc, ac);
+                            }
+                        }
+                        __syncthreads();
+                    }
+                };
+                if (sbm && one_chunk) {
+                    // the bitmap came from the symbolic pass: the ranges the
+                    // accumulation pass reuses are all that is needed
+                    long long len = 0, bst = 0;
+                    double a = 0.0;
+                    if (a0 + tid < a1) {
+                        long long lo, hi;
+                        range(my_s, my_e, my_bsl, my_cur, &lo, &hi);
+                        my_cur = hi;
+                        a = to_f64(my_a);
+                        bst = lo;
+                        len = hi - lo;
+                    }
+                    long long total;
+                    const long long incl = block_incl_scan<BS>(len, sm, &total);
+                    s_off[tid] = incl;
+                    s_bst[tid] = bst - (incl - len);
+                    s_a[tid] = a;
+                    __syncthreads();
+                } else if (!sbm) {
+                    products(std::integral_constant<int, 0>{});
+                }
+                // word ranks: thread tid takes E consecutive words
+                {
+                    const int E = (nwd + BS - 1) / BS;
+                    const int i0 = tid * E, i1 = min(i0 + E, nwd);
+                    int loc = 0;
+                    for (int i = i0; i < i1; ++i) loc += __builtin_popcountll(bm[i]);
+                    long long tw;
+                    long long run = block_incl_scan<BS>(loc, sm, &tw) - loc;
+                    for (int i = i0; i < i1; ++i) {
+                        wr[i] = (uint32_t)run;
+                        run += __builtin_popcountll(bm[i]);
+                    }
+                    if (tw != nout) bad = true;         // uniform
+                }
+                for (int i = tid; i < win_acc_len(nout); i += BS) acc[i] = 0.0;
+                __syncthreads();
+                if (bad) break;
+                products(std::integral_constant<int, 1>{});
+                // columns in rank order, then the slice out with coalesced stores
+                for (int i = tid; i < nwd; i += BS) {
+                    unsigned long long bits = bm[i];
+                    int rk = (int)wr[i];
+                    while (bits) {
+                        const int b = __builtin_ctzll(bits);
+                        bits &= bits - 1ull;
+                        colbuf[rk++] = (int32_t)(c_lo + (long long)i * 64 + b);
+                    }
+                }
+                __syncthreads();
+                const long long base = rp + s_rk[w0];
+                for (int i = tid; i < nout; i += BS) {
+                    ccol[base + i] = colbuf[i];
+                    cval[base + i] = (VT)acc[win_swz(i)];
+                }
+            }
+        }
+        __syncthreads();                                // s_rec, s_rk and the LDS are reused by the next row
+    }
+    if (bad && tid == 0) atomicOr(&info->err, kErrCount);
 }
 
 // ===========================================================================

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,18 @@ thread_local bool g_capturing = false;
 
 msp_status DevBuf::ensure(size_t need) {
     if (need <= bytes) return MSP_OK;
+    if (arena) {
+        const size_t at = (arena->used + 255) & ~(size_t)255;
+        const size_t want = std::max(need, (size_t)256);
+        if (at > arena->size || arena->size - at < want)
+            return fail(MSP_ERR_OOM,
+                        "the no-allocation scratch (%zu bytes) cannot hold this product's workspace "
+                        "(%zu bytes in use, %zu more needed)", arena->size, at, want);
+        ptr = arena->base + at;
+        bytes = want;
+        arena->used = at + want;
+        return MSP_OK;
+    }
     if (g_capturing) return fail(MSP_ERR_HIP, "internal: workspace growth during graph capture");
     if (ptr) {
         hipError_t e = hipFree(ptr);
@@ -80,7 +93,7 @@ msp_status DevBuf::ensure(size_t need) {
 }
 
 void DevBuf::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !arena) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
 }
@@ -120,6 +133,7 @@ extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
     h->alloc_ctx = nullptr;
     h->num_cu = prop.multiProcessorCount;
     h->lds_per_block = (int)prop.sharedMemPerBlock;
+    h->total_mem = prop.totalGlobalMem;
     h->tuning = default_tuning();
     msp_status s = h->info.ensure(sizeof(DevInfo));
     if (s != MSP_OK) { delete h; return s; }
@@ -166,7 +180,8 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
     for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod,
-                      &h->bsum, &h->gsl})
+                      &h->bsum, &h->gsl, &h->win_islot, &h->win_row, &h->win_cnt, &h->win_bslot,
+                      &h->win_wpos, &h->win_fb, &h->win_rbm, &h->win_bms})
         b->release();
     release_extra(h);
     h->prof.release();
@@ -316,6 +331,24 @@ void Profiler::end(hipStream_t s) {
     }
     open_phase = -1;
     open_ev = nullptr;
+}
+
+hipEvent_t Profiler::sub_begin(int phase, hipStream_t s) {
+    if (!on || !((mask >> phase) & 1u)) return nullptr;
+    hipEvent_t a = get();
+    if (a) (void)hipEventRecord(a, s);
+    return a;
+}
+
+void Profiler::sub_end(int phase, hipEvent_t a, hipStream_t s) {
+    if (!a) return;
+    hipEvent_t b = get();
+    if (!b) {
+        pool.push_back(a);
+        return;
+    }
+    (void)hipEventRecord(b, s);
+    pending.push_back({phase, a, b});
 }
 
 void Profiler::collect() {

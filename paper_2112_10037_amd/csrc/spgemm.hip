@@ -128,6 +128,16 @@ BinPlan numeric_plan(const msp_tuning& t, bool force_spill) {
 // ---------------------------------------------------------------------------
 constexpr int kLdsReserve = 26 * 1024;     // static LDS of the symbolic bitmap kernel
 constexpr int kSliceReserve = 27 * 1024;   // static LDS of k_num_slice<kSliceBS>
+constexpr int kWinReserve = 30 * 1024;     // static LDS of k_num_win<kWinBS>
+constexpr int kWinPerCU = 1;               // workgroups of k_num_win per compute unit
+
+// Dynamic LDS of the windowed global-bin kernel (a share of the compute
+// unit's LDS for each of its workgroups), or 0 when a window of full
+// density would not fit.
+static int win_lds(const msp_handle* h) {
+    const int dyn = h->lds_per_block / kWinPerCU - kWinReserve;
+    return dyn >= kWinFixed + kWinOut * kWin + kWinSlack ? dyn : 0;
+}
 
 #define MSP_GROUP_SHAPES(X) \
     X(8, 32) X(16, 32) X(8, 64) X(16, 64) X(32, 64) X(16, 128) X(32, 128) X(64, 128) \
@@ -221,6 +231,17 @@ msp_status configure_kernels(msp_handle* h) {
             return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
         }
     }
+    const int dyn_win = win_lds(h);
+    if (dyn_win > 0) {
+        void* win_fns[] = {(void*)k_num_win<kWinBS, float>, (void*)k_num_win<kWinBS, double>};
+        for (void* f : win_fns) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_win);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return hip_fail(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
+            }
+        }
+    }
     return MSP_OK;
 }
 
@@ -266,6 +287,8 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
+    // window records for the numeric global bin (plain products only)
+    const WinRec rec = BATCH ? WinRec{} : h->cur_rec;
     if (s.kind == Kind::Merge) {
         const void* fn = s.lanes == 4 ? (const void*)k_sym_merge<4, BATCH> : (const void*)k_sym_merge<8, BATCH>;
         const int grid = group_grid(h, fn, rows, 256);
@@ -299,7 +322,7 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
         const int grid = std::min(rows, 4 * h->num_cu);
 #define X(BS, T)                                                                                       \
     if (s.lanes == BS && s.slots == T) {                                                               \
-        k_sym_block<BS, T, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp); \
+        k_sym_block<BS, T, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp, rec); \
         return launch_check("k_sym_block");                                                            \
     }
         MSP_SYM_BLOCK_SHAPES(X)
@@ -317,13 +340,47 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
         }
         if (lds)
             k_sym_bitmap<1024, true, BATCH><<<grid, 1024, words * 4, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol,
-                                                                           rnnz, slab, info, mp);
+                                                                           rnnz, slab, info, mp, rec);
         else
             k_sym_bitmap<1024, false, BATCH><<<grid, 1024, 0, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol, rnnz,
-                                                                    slab, info, mp);
+                                                                    slab, info, mp, rec);
         return launch_check("k_sym_bitmap");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no symbolic kernel for bin shape (%d, %d)", s.lanes, s.slots);
+}
+
+// The windowed global-bin kernel over the rows of wk, after B's window
+// index; rows without a record are left in h->win_fb for the self-counting
+// kernel (their count in the device info block).
+template <typename VT>
+static msp_status launch_window_bin(msp_handle* h, Work wk, int rows, const Operands& op, const int64_t* crp,
+                                    int32_t* ccol, VT* cval) {
+    DevInfo* info = h->info.as<DevInfo>();
+    hipStream_t st = h->stream;
+    const WinRec& rec = h->cur_rec;
+    const int nw = rec.nw;
+    // every B row of at least kWinMinLen entries gets a slot
+    const long long max_slots = std::max(1LL, std::min(op.brows, op.bnnz / kWinMinLen));
+    msp_status r;
+    if ((r = h->win_bslot.ensure((size_t)std::max(op.brows, 1LL) * 4)) != MSP_OK) return r;
+    if ((r = h->win_wpos.ensure((size_t)max_slots * (size_t)(nw + 1) * 4)) != MSP_OK) return r;
+    if ((r = h->win_fb.ensure((size_t)std::max(rows, 1) * 4)) != MSP_OK) return r;
+    if (op.brows > 0) {
+        const long long blocks = std::min<long long>((op.brows + 3) / 4, 16LL * h->num_cu);
+        k_bwin_index<<<(int)blocks, 256, 0, st>>>(op.brows, op.brp, op.bcol, nw, kWinMinLen, max_slots,
+                                                  h->win_bslot.as<int32_t>(), h->win_wpos.as<int32_t>(), info);
+        if ((r = launch_check("k_bwin_index")) != MSP_OK) return r;
+    }
+    const int lds = win_lds(h);
+    const int grid = std::max(1, std::min(rows, kWinPerCU * h->num_cu));
+    hipEvent_t ev = h->prof.sub_begin(MSP_PHASE_GLOBAL_BIN, st);
+    k_num_win<kWinBS, VT><<<grid, kWinBS, (size_t)lds, st>>>(
+        wk, nw, op.arp, op.acol, (const VT*)op.aval, op.brp, op.bcol, (const VT*)op.bval,
+        h->win_bslot.as<int32_t>(), h->win_wpos.as<int32_t>(), rec, crp, ccol, cval, (long long)lds,
+        h->win_fb.as<int32_t>(), info);
+    r = launch_check("k_num_win");
+    h->prof.sub_end(MSP_PHASE_GLOBAL_BIN, ev, st);
+    return r;
 }
 
 template <typename VT, bool BATCH>
@@ -379,6 +436,15 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
 #undef X
     } else if (s.kind == Kind::Dense) {
         const long long n = op.ncols;
+        if constexpr (!BATCH) {
+            if (!cnt_out && h->cur_rec.cnt) {
+                msp_status r = launch_window_bin<VT>(h, wk, rows, op, crp, ccol, cval);
+                if (r != MSP_OK) return r;
+                // the rows without a record: their list and count are in device memory
+                wk = Work{h->win_fb.as<int32_t>(), 0, &info->win_fb[0]};
+                rows = h->num_cu;
+            }
+        }
         {
             // accumulate in LDS slice by slice, over column super-ranges whose
             // bitmap fits the LDS (one when all columns fit)
@@ -625,12 +691,14 @@ msp_status run_scan(msp_handle* h, int m, const int32_t* row_nnz, int64_t* row_p
                     int publish_seq) {
     const int tiles = std::max(1, (m + kScanTile - 1) / kScanTile);
     const size_t need = (size_t)tiles * 8;
-    if (need > h->tiles.bytes || h->scan_epoch == 0 || h->scan_epoch >= 0xffff) {
-        // fresh tile states: zero them and restart the epochs
+    if (need > h->tiles.bytes || h->scan_epoch == 0 || h->scan_epoch >= 0xffff || h->tiles.arena) {
+        // fresh tile states (or tiles in a scratch whose contents are
+        // unknown): zero them with a fill kernel and restart the epochs
         msp_status s = h->tiles.ensure(need);
         if (s != MSP_OK) return s;
-        hipError_t e = hipMemsetAsync(h->tiles.ptr, 0, h->tiles.bytes, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(scan state)");
+        const int words = (int)(h->tiles.bytes / 4);
+        k_zero_words<<<std::min(1024, (words + 255) / 256), 256, 0, h->stream>>>((int*)h->tiles.ptr, words);
+        if ((s = launch_check("k_zero_words(scan state)")) != MSP_OK) return s;
         h->scan_epoch = 0;
     }
     ++h->scan_epoch;
@@ -682,6 +750,58 @@ msp_status device_error(int err) {
     return MSP_OK;
 }
 
+// Window records for the numeric global bin of this product, sized from the
+// symbolic bin sizes (the rows of the workgroup-hash bins whose bound exceeds
+// the numeric threshold, and of the bitmap bin); none (cur_rec.cnt null)
+// without a numeric plan, when the windowed kernel does not fit the LDS,
+// for more than kWinMaxNw windows, or above 4 GiB of records.
+static msp_status setup_records(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& sp,
+                                const int* counts, const BinPlan* np) {
+    h->cur_rec = WinRec{};
+    if (!np || win_lds(h) == 0) return MSP_OK;
+    const long long nw = (B->ncols + kWin - 1) / kWin;
+    if (nw <= 0 || nw > kWinMaxNw) return MSP_OK;
+    const int thresh = np->table.nb > 1 ? np->table.umax[np->table.nb - 1] : 0;
+    long long cap = counts[sp.table.nb];
+    for (int b = 1; b < sp.table.nb; ++b)
+        if (sp.spec[b].kind == Kind::Block && sp.table.umax[b] > thresh) cap += counts[b];
+    if (cap <= 0 || cap * nw * 2 > (4LL << 30)) return MSP_OK;
+    // without room for the records the global bin counts its rows itself
+    msp_status r;
+    if ((r = h->win_islot.ensure((size_t)std::max<long long>(A->nrows, 1) * 4)) != MSP_OK ||
+        (r = h->win_row.ensure((size_t)cap * 4)) != MSP_OK ||
+        (r = h->win_cnt.ensure((size_t)cap * (size_t)nw * 2)) != MSP_OK ||
+        (r = h->win_rbm.ensure((size_t)cap * 4)) != MSP_OK)
+        return r == MSP_ERR_OOM ? MSP_OK : r;
+    WinRec rec;
+    rec.islot = h->win_islot.as<int32_t>();
+    rec.row = h->win_row.as<int32_t>();
+    rec.cnt = h->win_cnt.as<uint16_t>();
+    rec.nrec = &h->info.as<DevInfo>()->win_nrec;
+    rec.cap = (int)cap;
+    rec.nw = (int)nw;
+    rec.thresh = thresh;
+    rec.rec_bm = h->win_rbm.as<int32_t>();
+    // bitmap store for the bitmap bin's rows with at least one product per
+    // 16 columns (a bitmap pass over their products would move at least
+    // twice the bitmap's bytes); at most min(16 GiB, 1/16 of the device)
+    rec.bms = nullptr;
+    rec.nbms = &h->info.as<DevInfo>()->win_nbms;
+    rec.bms_cap = 0;
+    rec.bms_min_prod = nw * (long long)kWin / 16;
+    const long long row_bytes = nw * (long long)kWin / 8;
+    const long long budget = std::min<long long>(16LL << 30, (long long)(h->total_mem / 16));
+    const long long bcap = std::min<long long>(counts[sp.table.nb], budget / row_bytes);
+    if (bcap > 0 && (r = h->win_bms.ensure((size_t)(bcap * row_bytes))) == MSP_OK) {
+        rec.bms = h->win_bms.as<uint32_t>();
+        rec.bms_cap = (int)bcap;
+    } else if (r != MSP_OK && r != MSP_ERR_OOM) {
+        return r;
+    }
+    h->cur_rec = rec;
+    return MSP_OK;
+}
+
 // symbolic phase up to row_nnz (shared by msp_spgemm and msp_spgemm_symbolic).
 // When the plan starts with a merge bin, the statistics pass and that bin
 // run as one kernel with a speculative scan queued behind it (into
@@ -693,6 +813,7 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     const int m = (int)A->nrows;
     msp_status s;
     *scanned = false;
+    h->cur_rec = WinRec{};
     if ((s = h->rnnz.ensure((size_t)std::max(m, 1) * 4)) != MSP_OK) return s;
     const BinPlan sp = symbolic_plan(t, opts && opts->force_spill);
     if ((s = zero_info(h)) != MSP_OK) return s;
@@ -738,6 +859,7 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
         for (int b = 0; b < kNB; ++b) counts[b] = h->hsum->counts[b];
         k_zero_words<<<1, 256, 0, h->stream>>>(&info->num_part[0][0], kParts * kPartStride);
         if ((s = launch_check("k_zero_words")) != MSP_OK) return s;
+        if ((s = setup_records(h, A, B, sp, counts, np)) != MSP_OK) return s;
         h->prof.begin(MSP_PHASE_SYMBOLIC, h->stream);
         s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), 1);
         h->prof.end(h->stream);
@@ -758,6 +880,7 @@ static msp_status symbolic_phase(msp_handle* h, const msp_csr* A, const msp_csr*
     } else if ((s = take_pending_error(h)) != MSP_OK) {
         return s;
     }
+    if ((s = setup_records(h, A, B, sp, counts, np)) != MSP_OK) return s;
     s = run_symbolic_bins(h, A, B, sp, counts, h->rnnz.as<int32_t>(), 0);
     h->prof.end(h->stream);
     return s;
@@ -771,9 +894,13 @@ namespace msp {
 // C's columns and values once nnz(C) is known (the caller's allocator, or a
 // workspace for internal sub-products).
 msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C, const msp_opts* opts,
-                       const std::function<void*(size_t)>& alloc_cv, const std::function<void(void*)>& free_cv) {
+                       const std::function<void*(size_t)>& alloc_cv, const std::function<void(void*)>& free_cv,
+                       const CPlace* place) {
     if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
     if (!C) return fail(MSP_ERR_INVALID_ARG, "C is NULL");
+    if (place && (!C->row_ptr || (place->cap > 0 && (!place->col || !place->val)) || place->cap < 0))
+        return fail(MSP_ERR_INVALID_ARG, "C's row_ptr, col and val buffers are required (capacity %lld)",
+                    (long long)place->cap);
     msp_status s = check_pair(A, B);
     if (s != MSP_OK) return s;
     hipError_t e = hipSetDevice(h->device);
@@ -781,6 +908,11 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
     const msp_tuning t = effective_tuning(h, opts);
     const int m = (int)A->nrows;
     if (opts && opts->validate && (s = validate_inputs(h, A, B)) != MSP_OK) return s;
+    // the window records belong to this product only
+    struct RecScope {
+        msp_handle* h;
+        ~RecScope() { h->cur_rec = WinRec{}; }
+    } rec_scope{h};
 
     bool own_rp = false;
     if (!C->row_ptr) {
@@ -791,7 +923,7 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
     C->col = nullptr;
     C->val = nullptr;
     auto cleanup = [&](msp_status st) {
-        if (C->col) free_cv(C->col);   // col and val share it
+        if (C->col && !place) free_cv(C->col);   // col and val share it
         C->col = nullptr;
         C->val = nullptr;
         if (own_rp) { h->free_fn(h->alloc_ctx, C->row_ptr, h->stream); C->row_ptr = nullptr; }
@@ -825,18 +957,30 @@ msp_status spgemm_core(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_cs
     C->ncols = B->ncols;
     C->nnz = nnz;
     C->dtype = A->dtype;
+    if (place && nnz > place->cap) {
+        C->col = nullptr;
+        return fail(MSP_ERR_INVALID_ARG, "C has %lld nonzeros, more than the capacity %lld given", nnz,
+                    (long long)place->cap);
+    }
     if (nnz > 0) {
         // one allocation: columns, then values at the next 256-byte boundary
         const size_t voff = ((size_t)nnz * 4 + 255) & ~(size_t)255;
-        void* base = alloc_cv(voff + (size_t)nnz * vsz);
-        if (!base) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
-        C->col = (int32_t*)base;
+        void* vals;
+        if (place) {
+            C->col = place->col;
+            vals = place->val;
+        } else {
+            void* base = alloc_cv(voff + (size_t)nnz * vsz);
+            if (!base) return cleanup(fail(MSP_ERR_OOM, "allocation of C (%lld nonzeros) failed", nnz));
+            C->col = (int32_t*)base;
+            vals = (char*)base + voff;
+        }
         h->prof.begin(MSP_PHASE_NUMERIC, h->stream);
-        if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col,
-                                  (char*)base + voff, nullptr)) != MSP_OK)
+        if ((s = run_numeric_bins(h, A, B, np, counts, h->rnnz.as<int32_t>(), C->row_ptr, C->col, vals,
+                                  nullptr)) != MSP_OK)
             return cleanup(s);
         h->prof.end(h->stream);
-        C->val = (char*)base + voff;
+        C->val = vals;
         // the numeric kernels' consistency flags reach the host through the
         // next call's first kernel, or through msp_sync
     }

@@ -42,7 +42,11 @@ struct DevInfo {
     int scan_ticket;                      // tile tickets of the single-pass scan
     int neg_count;                        // scan inputs < 0 (rows that overflowed)
     int fused_other;                      // the fused symbolic pass left rows for other bins
-    int pad[26];
+    int win_nrec;                         // window records the symbolic pass made
+    int win_fb[2];                        // global-bin rows without a record: {count, 0}
+    int win_nbs;                          // B rows given a window index
+    int win_nbms;                         // rows whose bitmap the symbolic pass stored
+    int pad[21];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
@@ -65,6 +69,39 @@ struct HostSummary {
 // the rows the fused statistics and merge pass counted with the merge.
 constexpr int kPartMergeNA = kPartStride - 1;
 static_assert(kNB < kPartMergeNA, "partition rows hold the bins and one spare slot");
+
+// Column windows of the global bin.  The symbolic pass records, for every
+// row with more outputs than the numeric threshold, how many of its outputs
+// fall in each window of kWin columns; B rows with at least kWinMinLen
+// entries get the position of their first entry at or past every window
+// boundary.  The numeric pass then cuts such rows into slices of whole
+// windows sized from the exact counts, and finds each slice's part of a B
+// row with two loads instead of a search.
+constexpr int kWinLog = 12;
+constexpr int kWin = 1 << kWinLog;               // columns per window
+constexpr int kWinWords = kWin / 64;             // 64-bit bitmap words per window
+constexpr int kWinFixed = kWinWords * (8 + 4);   // LDS bytes per window: bitmap and word ranks
+constexpr int kWinOut = 8 + 4;                   // LDS bytes per output: FP64 sum and column
+constexpr int kWinMaxNw = 512;                   // most windows per row (ncols <= 2^21)
+constexpr int kWinMinLen = 64;                   // shortest B row given a window index
+
+struct WinRec {
+    int32_t* islot;      // per row of A: index of its record (stale values are caught by `row`)
+    int32_t* row;        // per record: its row of A
+    uint16_t* cnt;       // per record: outputs in each of the nw windows
+    int* nrec;           // records made so far (counter in the device info block)
+    int cap;             // records that fit
+    int nw;              // windows per row; cnt == nullptr: no records are made
+    int thresh;          // rows with more outputs than this get a record
+    // bitmap store: a recorded row of the bitmap kernel with at least
+    // bms_min_prod products also leaves its column bitmap (nw * kWin bits),
+    // so that the numeric pass need not rebuild it
+    int32_t* rec_bm;     // per record: its bitmap slot, or -1
+    uint32_t* bms;       // bitmap slots (nullptr: no store)
+    int* nbms;           // slots taken (counter in the device info block)
+    int bms_cap;         // slots that fit
+    long long bms_min_prod;
+};
 
 // Bin b (1 <= b < nb) holds rows with umax[b-1] < u <= umax[b]; bin 0 holds
 // u == 0; bin nb holds everything above umax[nb-1] (the global path).

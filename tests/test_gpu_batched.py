@@ -217,3 +217,30 @@ def test_batch_full_merge_batches(h):
     for i in range(4):
         _check(plan.result(i), oracle.spgemm(A[i], P[i]), np.float64)
     plan.close()
+
+
+@pytest.mark.slow
+def test_galerkin_512_full_batch_against_oracle(h):
+    """The full batched workload: 512 Galerkin products R (A P), 7-point
+    Laplacians with sides n ~ U{16..64} (seed 5), 2x2x2 aggregation, FP64,
+    planned and replayed as one graph; every problem's result is compared
+    with the oracle (two oracle products per distinct side; problems of one
+    side are the same matrices).  Values are integers: exact equality."""
+    from paper_2112_10037_amd import batch
+    sides = gen.galerkin_sizes(512, 16, 64, seed=5)
+    pA, pP, pR = batch.galerkin_batch(sides)
+    plan = binding.Batch(h, pA, pP, pR)
+    plan.execute()
+    plan.sync()
+    refs = {}
+    A, P, R = batch.galerkin_host(sides)
+    for p, n in enumerate(sides):
+        n = int(n)
+        if n not in refs:
+            AP = oracle.spgemm(A[p], P[p])
+            refs[n] = oracle.spgemm(R[p], _csr(AP, A[p].nrows, P[p].ncols))
+        ref = refs[n]
+        got = plan.result(p).to_host()
+        assert np.array_equal(got.row_ptr, ref[0]) and np.array_equal(got.col, ref[1]), (p, n)
+        assert np.array_equal(got.val, ref[2]), (p, n)
+    plan.close()

@@ -209,3 +209,32 @@ def test_learned_forced_spill_uses_global_bin(h, dtype):
         oracle.compare(got.row_ptr, got.col, got.val, ref, TOL[np.dtype(dtype)])
         assert st["overflow_rows"] == 0 and st["nnz"] == got.nnz
     pred.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("index", [47, 51, 7])
+def test_full_size_held_out_member_plain_and_learned(h, index):
+    """A held-out member of the mixed suite at full size (index 47: 27-point
+    stencil, side 49; 51: Erdos-Renyi, 2^16 rows with 4..32 per row; 7:
+    R-MAT 2^16, degree 9; FP64), C = A*A through the plain path and through
+    the learned one-pass path with a network trained on the GPU on small
+    training members, both compared in full with the oracle."""
+    suite = gen.learned_suite()
+    member = next(m for m in suite if m.index == index)
+    assert member.held_out
+    train_m = [m for m in suite if not m.held_out][:9]
+    prods = [(to_dev(M), to_dev(M)) for M in (m.build(scale_down=6) for m in train_m)]
+    feats, targets = learned.training_set(h, prods)
+    pred, _, _ = learned.train(h, feats, targets, steps=400, batch=4096, seed=5)
+    M = member.build()
+    dM = to_dev(M)
+    ref = oracle.spgemm(M, M)
+    plain = h.spgemm(dM, dM).to_host()
+    oracle.compare(plain.row_ptr, plain.col, plain.val, ref, TOL[np.dtype(np.float64)])
+    C, st = h.spgemm_learned(pred, dM, dM)
+    got = C.to_host()
+    oracle.compare(got.row_ptr, got.col, got.val, ref, TOL[np.dtype(np.float64)])
+    assert st["nnz"] == got.nnz == plain.nnz
+    print(f"member {index} ({member.family}, {M.nrows} rows): nnz(C) = {got.nnz}, "
+          f"overflow rows {st['overflow_rows']}, sum cap / nnz = {st['sum_cap'] / got.nnz:.3f}")
+    pred.close()
