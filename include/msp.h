@@ -166,6 +166,33 @@ msp_status msp_spgemm(msp_handle* h, const msp_csr* A, const msp_csr* B,
  * error the numeric kernels of earlier calls flagged. */
 msp_status msp_sync(msp_handle* h);
 
+/*
+ * msp_spgemm for callers that cannot allocate device memory: code under
+ * stream or graph capture, serving loops and harnesses that forbid
+ * allocation.  It calls no hipMalloc, hipFree or allocator callback.
+ *   - Workspace: every per-call workspace of msp_spgemm is carved from one
+ *     fixed device array of MSP_NOALLOC_SCRATCH_BYTES bytes per GPU, set up
+ *     when the library's first handle on that GPU is created and held until
+ *     the process ends.  All handles and calls on a GPU share it, and it keeps
+ *     the last call's contents: calls on one GPU whose work overlaps (two
+ *     handles, two streams, two threads) race; serialise them.  Products
+ *     whose workspace does not fit are refused with MSP_ERR_INVALID_ARG (more
+ *     than about (MSP_NOALLOC_SCRATCH_BYTES - 1 MiB) / 24 rows, checked
+ *     before anything runs) or MSP_ERR_OOM (a larger workspace found later,
+ *     after some kernels ran: C's contents are then undefined).
+ *   - Output: the caller sets C->row_ptr (A.nrows + 1 int64), C->col
+ *     (capacity int32) and C->val (capacity values of the operands' type),
+ *     device buffers; on return C->nnz is nnz(C) and C->col / C->val are the
+ *     caller's buffers.  When nnz(C) > capacity the call returns
+ *     MSP_ERR_INVALID_ARG with C->nnz set to the count needed and C->row_ptr
+ *     holding C's row pointers (the numeric pass has not run).
+ *   - Otherwise as msp_spgemm: the same kernels and results, the same host
+ *     reads, and the numeric pass only queued on the handle's stream.
+ *     Profiling is suspended during the call.
+ */
+#define MSP_NOALLOC_SCRATCH_BYTES (64LL << 20)
+msp_status msp_spgemm_noalloc(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C,
+                              int64_t capacity, const msp_opts* opts);
 
 /*
  * Autotuner for one product (it replaces the paper's analytic choice of its

@@ -96,6 +96,8 @@ SIGNATURES = [
     ("msp_spgemm", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
                                   ctypes.POINTER(c_csr_out), ctypes.POINTER(c_opts)]),
     ("msp_sync", ctypes.c_int, [ctypes.c_void_p]),
+    ("msp_spgemm_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
+                                          ctypes.POINTER(c_csr_out), ctypes.c_int64, ctypes.POINTER(c_opts)]),
     ("msp_spgemm_symbolic", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(c_opts)]),

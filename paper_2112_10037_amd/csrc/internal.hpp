@@ -114,6 +114,7 @@ struct msp_handle {
     // self-counting kernel
     msp::DevBuf win_islot, win_row, win_cnt, win_bslot, win_wpos, win_fb, win_rbm, win_bms;
     size_t total_mem = 0;           // device memory (bounds the bitmap store)
+    void* scratch = nullptr;        // device address of this device's no-allocation scratch
     msp::WinRec cur_rec{};          // records of the product in progress (cnt null: none)
     msp::DevInfo* hinfo = nullptr;  // pinned mirror of info
     int* hpending = nullptr;        // pinned: error bits of the last call's numeric

@@ -100,6 +100,31 @@ void DevBuf::release() {
 
 }  // namespace msp
 
+// The allocation-free entry point's workspace: one fixed array per device,
+// held until the process ends and shared by every handle on that device.
+// Host code uses only the device address hipGetSymbolAddress gives for it
+// (the array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[MSP_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mutex;
+static void* g_scratch_addr[256] = {};
+
+// Device address of `scratch` on the current device `device` (looked up once).
+static msp_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= 256) return fail(MSP_ERR_UNSUPPORTED, "device index %d", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        }
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return MSP_OK;
+}
+
 static void* default_alloc(void*, size_t bytes, void*) {
     void* p = nullptr;
     if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
@@ -124,8 +149,12 @@ extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(MSP_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+    void* scr = nullptr;
+    msp_status ss = scratch_address(device, &scr);
+    if (ss != MSP_OK) return ss;
     msp_handle* h = new (std::nothrow) msp_handle();
     if (!h) return fail(MSP_ERR_OOM, "msp_create: host allocation failed");
+    h->scratch = scr;
     h->device = device;
     h->stream = (hipStream_t)stream;
     h->alloc = default_alloc;

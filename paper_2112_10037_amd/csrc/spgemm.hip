@@ -1109,3 +1109,43 @@ extern "C" msp_status msp_autotune(msp_handle* h, const msp_csr* A, const msp_cs
     *best = cand[best_i];
     return check_tuning(best);
 }
+
+// Every per-call workspace of the plain product in the device's fixed
+// scratch array (the handle's own workspaces are set aside meanwhile), C
+// in the caller's buffers, no profiling events: nothing is allocated.
+extern "C" msp_status msp_spgemm_noalloc(msp_handle* h, const msp_csr* A, const msp_csr* B, msp_csr_out* C,
+                                         int64_t capacity, const msp_opts* opts) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    if (!C) return fail(MSP_ERR_INVALID_ARG, "C is NULL");
+    msp_status s = check_pair(A, B);
+    if (s != MSP_OK) return s;
+    if (!h->scratch) return fail(MSP_ERR_UNSUPPORTED, "no scratch on this device");
+    // the per-row workspaces alone must fit: refused before anything runs
+    const long long m = A->nrows;
+    if (m * 24 + (1 << 20) > (long long)MSP_NOALLOC_SCRATCH_BYTES)
+        return fail(MSP_ERR_INVALID_ARG, "%lld rows exceed the no-allocation scratch (%lld bytes, about %lld rows)",
+                    m, (long long)MSP_NOALLOC_SCRATCH_BYTES, ((long long)MSP_NOALLOC_SCRATCH_BYTES - (1 << 20)) / 24);
+    Arena ar;
+    ar.base = (char*)h->scratch;
+    ar.size = MSP_NOALLOC_SCRATCH_BYTES;
+    DevBuf* bufs[] = {&h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod, &h->bsum, &h->gsl,
+                      &h->win_islot, &h->win_row, &h->win_cnt, &h->win_bslot, &h->win_wpos, &h->win_fb,
+                      &h->win_rbm, &h->win_bms};
+    constexpr int nb = sizeof(bufs) / sizeof(bufs[0]);
+    DevBuf saved[nb];
+    for (int i = 0; i < nb; ++i) {
+        saved[i] = *bufs[i];
+        *bufs[i] = DevBuf{};
+        bufs[i]->arena = &ar;
+    }
+    const bool prof_on = h->prof.on;
+    h->prof.on = false;
+    CPlace place{C->col, C->val, capacity};
+    s = spgemm_core(
+        h, A, B, C, opts, [](size_t) -> void* { return nullptr; }, [](void*) {}, &place);
+    h->prof.on = prof_on;
+    for (int i = 0; i < nb; ++i) *bufs[i] = saved[i];
+    C->col = place.col;                 // the caller's buffers, whatever happened
+    C->val = place.val;
+    return s;
+}
