@@ -197,6 +197,104 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
 
 
 # ---------------------------------------------------------------------------
+# energy (the paper's Sec. V-C energy per SpGEMM and its utilization factor)
+# ---------------------------------------------------------------------------
+PEAK_VECTOR_GFLOPS = {"f32": 157300.0, "f64": 78600.0}     # MI355X vendor figures
+
+
+class EnergyMeter:
+    """Board energy of GPU 0 from the SMI energy counter (the accumulator
+    times its resolution, in microjoules)."""
+
+    def __init__(self):
+        import amdsmi
+        self._smi = amdsmi
+        amdsmi.amdsmi_init()
+        self._h = amdsmi.amdsmi_get_processor_handles()[0]
+
+    def joules(self) -> float:
+        e = self._smi.amdsmi_get_energy_count(self._h)
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+
+    def close(self):
+        try:
+            self._smi.amdsmi_shut_down()
+        except Exception:
+            pass
+
+
+def energy_of(meter, fn, min_seconds: float = 3.0, idle_seconds: float = 1.0) -> dict:
+    """Energy per call of fn (which waits for its own result), from the
+    counter read before and after as many calls as fill min_seconds; the
+    idle draw over idle_seconds is measured first, and the energy above it
+    is reported as well."""
+    import torch
+    torch.cuda.synchronize()
+    e0, t0 = meter.joules(), time.perf_counter()
+    time.sleep(idle_seconds)
+    e1, t1 = meter.joules(), time.perf_counter()
+    idle_w = (e1 - e0) / (t1 - t0)
+    fn()
+    n = 0
+    e0, t0 = meter.joules(), time.perf_counter()
+    while True:
+        fn()
+        n += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    torch.cuda.synchronize()
+    e1, t1 = meter.joules(), time.perf_counter()
+    per = (e1 - e0) / n
+    per_s = (t1 - t0) / n
+    return {"joules_per_call": round(per, 6), "calls": n, "avg_power_w": round((e1 - e0) / (t1 - t0), 1),
+            "idle_power_w": round(idle_w, 1), "joules_per_call_above_idle": round(per - idle_w * per_s, 6),
+            "seconds_per_call": round(per_s, 6)}
+
+
+def energy_entry(meter, fn, products: int, dtype: str) -> dict:
+    e = energy_of(meter, fn)
+    gflops = 2.0 * products / e["seconds_per_call"] / 1e9
+    e["gflops_per_watt"] = round(gflops / e["avg_power_w"], 3) if e["avg_power_w"] > 0 else None
+    # the paper's utilization factor: operations over (clock x units x time),
+    # i.e. the achieved rate over the peak vector rate of the value type
+    e["stuf"] = round(gflops / PEAK_VECTOR_GFLOPS[dtype], 6)
+    return e
+
+
+# ---------------------------------------------------------------------------
+# the paper's eight matrices, as FP32 stand-ins of the same shapes
+# ---------------------------------------------------------------------------
+# FSpGEMM on the Arria 10 GX, ms per SpGEMM (Sec. V-C, Table VII): context
+# only (the paper's matrices, FLOP convention and product are not ours)
+PAPER_FPGA_MS = {"poisson3Da": 5, "2cubes_sphere": 9, "filter3D": 42, "cage12": 15, "scircuit": 6,
+                 "mac_econ_fwd500": 7, "offshore": 23, "webbase-1M": 25}
+
+
+def table4_leg(h, steps: int = 10) -> dict:
+    """C = A*A on each stand-in: median of whole calls, GFLOP/s."""
+    import torch
+    from paper_2112_10037_amd import binding, gen
+    rows = []
+    for name, A in gen.table4_standins():
+        prods = int(row_products(A, A).sum())
+        dA = binding.DeviceCSR.from_host(A, "cuda:0")
+        C = h.spgemm(dA, dA)
+        nnz_c = C.nnz
+        del C
+        ts = step_times(h, dA, steps)
+        h.sync()
+        med = float(np.median(ts))
+        rows.append({"name": name, "rows": A.nrows, "nnz_a": A.nnz, "products": prods, "nnz_c": nnz_c,
+                     "ms": round(med * 1e3, 4), "gflops": round(2.0 * prods / med / 1e9, 3),
+                     "paper_fpga_ms_context": PAPER_FPGA_MS[name]})
+        del dA
+        torch.cuda.empty_cache()
+    return {"workload": "FP32 stand-ins of the paper's eight matrices (Table IV dimensions and densities), "
+                        "C = A*A, plain path",
+            "geomean_gflops": round(geomean([r["gflops"] for r in rows]), 3), "per_matrix": rows}
+
+
+# ---------------------------------------------------------------------------
 # host data (built before the GPU is touched: the pool forks)
 # ---------------------------------------------------------------------------
 def _build_member(m):
@@ -289,7 +387,8 @@ def learned_leg(h, suite, mats, reps: int, steps: int) -> dict:
             C = run_l()
             same = bool(torch.equal(C.row_ptr, Cp.row_ptr) and torch.equal(C.col, Cp.col))
             res[name] = {"ms": round(t * 1e3, 3), "speedup": round(t_plain / t, 4),
-                         "overflow_rows": st["overflow_rows"], "sum_cap_over_nnz": round(st["sum_cap"] / max(Cp.nnz, 1), 4),
+                         "overflow_rows": st["overflow_rows"], "exact_rows": st["exact_rows"],
+                         "sum_cap_over_nnz": round(st["sum_cap"] / max(Cp.nnz, 1), 4),
                          "structure_identical": same}
             del C
         del Cp, dM
@@ -316,7 +415,7 @@ def learned_leg(h, suite, mats, reps: int, steps: int) -> dict:
     return out
 
 
-def batched_leg(h, sides, reps: int, tuning_cache: str) -> dict:
+def batched_leg(h, sides, reps: int, tuning_cache: str, meter=None) -> dict:
     import torch
     from paper_2112_10037_amd import batch, binding, gen
     t0 = time.perf_counter()
@@ -340,6 +439,9 @@ def batched_leg(h, sides, reps: int, tuning_cache: str) -> dict:
 
     t_graph = timed(replay, reps)
     nprob = len(sides)
+    energy = None
+    if meter:
+        energy = energy_entry(meter, replay, int(pA.nnz + int(info["nnz"][0])), "f64")
 
     def plain_all():
         for p in range(nprob):
@@ -378,7 +480,7 @@ def batched_leg(h, sides, reps: int, tuning_cache: str) -> dict:
             "tuning": list(tuning), "tuning_cached": tinfo["cached"],
             "autotune_median_ms": tinfo.get("median_ms"),
             "plan": info, "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2),
-            "results_identical_to_plain": same}
+            "results_identical_to_plain": same, "energy": energy}
 
 
 # plain-path tunings the autotuner compares on the main workload
@@ -480,6 +582,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the smaller configs' entries")
+    ap.add_argument("--no-energy", action="store_true", help="skip the energy entries")
+    ap.add_argument("--no-table4", action="store_true", help="skip the Table IV stand-ins")
     ap.add_argument("--no-autotune", action="store_true", help="run the library's default tuning")
     ap.add_argument("--legs-reps", type=int, default=5)
     ap.add_argument("--train-steps", type=int, default=2000)
@@ -605,6 +709,19 @@ def main():
     }
     if vendor is not None:
         out["vendor_library"] = vendor
+    meter = None
+    if not args.no_energy:
+        try:
+            meter = EnergyMeter()
+        except Exception as e:          # no SMI access on this machine
+            out["energy"] = {"error": repr(e)[:200]}
+    if meter:
+        def one_call():
+            C = h.spgemm(dA, dA, check=False)
+            torch.cuda.synchronize()
+            del C
+        out["energy"] = energy_entry(meter, one_call, products, out["dtype"])
+        progress(f"main: {out['energy']['joules_per_call']} J per SpGEMM")
     del dA
     torch.cuda.empty_cache()
     progress(f"main: {gflops:.1f} GFLOP/s, {med * 1e3:.3f} ms per step (median)")
@@ -612,14 +729,31 @@ def main():
     if not args.no_configs:
         out["configs"] = {"er4096": config_entry(h, "er4096", 200, 10),
                           "laplacian2d_1024": config_entry(h, "laplacian2d_1024", 50, 5)}
+        if meter:
+            from paper_2112_10037_amd import binding as _b
+            _, L = workload("laplacian2d_1024")
+            dL = _b.DeviceCSR.from_host(L, "cuda:0")
+
+            def lap_call():
+                C = h.spgemm(dL, dL, check=False)
+                torch.cuda.synchronize()
+                del C
+            out["configs"]["laplacian2d_1024"]["energy"] = energy_entry(
+                meter, lap_call, out["configs"]["laplacian2d_1024"]["products"], "f64")
+            del dL
         progress("configs done")
+    if not args.no_table4:
+        out["table4_standins"] = table4_leg(h)
+        progress(f"table4 stand-ins: geomean {out['table4_standins']['geomean_gflops']} GFLOP/s")
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg(h, suite, mats, args.legs_reps, args.train_steps)
         del mats
     if not args.no_batched:
-        out["batched_vs_plain"] = batched_leg(h, sides, max(args.legs_reps, 10), args.tuning_cache)
+        out["batched_vs_plain"] = batched_leg(h, sides, max(args.legs_reps, 10), args.tuning_cache, meter)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, prods_row, args.cpu_seconds)
+    if meter:
+        meter.close()
     if args.calibrate_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")

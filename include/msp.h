@@ -145,9 +145,11 @@ msp_status msp_get_tuning(const msp_handle* h, msp_tuning* t);
  *      per-bin LDS hash of keys, an LDS bitmap, or a global bitmap;
  *   4. device prefix sum -> C.row_ptr, nnz(C);
  *   5. re-binning by row_nnz_i and the numeric pass: LDS hash accumulators
- *      (FP64 sums for both value types) with an in-row column sort, or a
- *      global dense accumulator with an ordered bitmap scan for rows too
- *      large for LDS.
+ *      (FP64 sums for both value types) with an in-row column sort; rows
+ *      too large for LDS are cut into column slices, each with an LDS
+ *      bitmap and an FP64 accumulator indexed by the column's rank, and go
+ *      out in column order from the bitmap (the slices are sized from the
+ *      symbolic pass's per-window output counts).
  * Host synchronisation: two small device-to-host reads (bin counts, then
  * nnz(C) with the numeric bin counts).  The numeric pass is only queued:
  * it completes on the handle's stream after the call returns.  Its internal
@@ -243,9 +245,12 @@ typedef struct {
 } msp_train_opts;
 
 typedef struct {
-    int64_t overflow_rows;   /* rows recomputed on the exact path          */
+    int64_t overflow_rows;   /* rows whose output outgrew their capacity and
+                                were recomputed on the exact path           */
     int64_t sum_cap;         /* total predicted capacity (padded entries)   */
     int64_t nnz;             /* nnz(C)                                      */
+    int64_t exact_rows;      /* rows whose capacity fell in the global bin,
+                                sent to the exact path without a padded try */
 } msp_learned_stats;
 
 /* Create on the handle's device from 4801 host floats (copied). */
@@ -317,8 +322,9 @@ msp_status msp_predictor_calibrate(msp_handle* h, msp_predictor* p, const float*
  * with min(prod_i, n) <= 32 take that bound without the network, and so does
  * every row whose bound falls in the same numeric bin as cap_i (same
  * kernel, no risk of overflow) or is at most 2 cap_i (at most twice the
- * room, no risk of overflow)), rows binned by capacity, numeric kernels
- * writing into a padded buffer,
+ * room, no risk of overflow)), rows binned by capacity (a row whose
+ * capacity falls in the global bin goes straight to the exact path, unless
+ * opts->force_spill), numeric kernels writing into a padded buffer,
  * the rows that did not fit recomputed exactly (two-phase path on their
  * sub-matrix), and a compaction into tight CSR.  The result equals
  * msp_spgemm's (identical structure) for any predictor.  Two host reads in

@@ -58,7 +58,8 @@ class c_train_opts(ctypes.Structure):
 
 
 class c_learned_stats(ctypes.Structure):
-    _fields_ = [("overflow_rows", ctypes.c_int64), ("sum_cap", ctypes.c_int64), ("nnz", ctypes.c_int64)]
+    _fields_ = [("overflow_rows", ctypes.c_int64), ("sum_cap", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("exact_rows", ctypes.c_int64)]
 
 
 class c_batch_csr(ctypes.Structure):
@@ -398,7 +399,8 @@ class Handle:
             val = torch.empty(0, dtype=vdt, device=rp.device)
         if check:
             self.sync()
-        stats = {"overflow_rows": int(st.overflow_rows), "sum_cap": int(st.sum_cap), "nnz": int(st.nnz)}
+        stats = {"overflow_rows": int(st.overflow_rows), "sum_cap": int(st.sum_cap), "nnz": int(st.nnz),
+                 "exact_rows": int(st.exact_rows)}
         return DeviceCSR(A.nrows, B.ncols, rp, col, val), stats
 
     def training_rows(self, A: DeviceCSR, B: DeviceCSR, feats=None, targets=None):

@@ -13,8 +13,9 @@
 //   * a numeric pass adds a_ik * b_kj into an LDS hash of (key, FP64 value)
 //     sized by the exact row_nnz_i, then writes the row in column order (a
 //     rank count for short rows, an LDS bitonic sort for long rows); rows
-//     too large for LDS use a global dense FP64 accumulator whose bitmap is
-//     scanned in column order, so they need no sort.
+//     too large for LDS are cut into column slices whose bitmap, word ranks
+//     and FP64 accumulator (indexed by the column's rank) fit the LDS, and
+//     each slice goes out in column order from its bitmap, with no sort.
 // Products of a row are enumerated "flattened": a lane group loads a chunk
 // of A's row, prefix-sums the B-row lengths, and every lane takes the next
 // product index and finds its A entry by binary search, so that the lanes
@@ -55,8 +56,9 @@ __device__ __forceinline__ T gat(const T* __restrict__ p, IT i) {
     }
 }
 
-// Loads that must observe device-scope atomics performed by other lanes of
-// the same workgroup (global dense accumulator): bypass the non-coherent L1.
+// Loads that must observe atomics other lanes of the workgroup performed on
+// global memory (the symbolic bitmap's global slab): bypass the
+// non-coherent L1.
 __device__ __forceinline__ double load_coherent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1360,6 +1362,150 @@ k_scan_fused(int m, const int32_t* __restrict__ cnt, const long long* __restrict
 // workgroups per compute unit).
 constexpr int kMergeStage = 704;
 
+// Numeric rows of a merge batch that the per-lane merge does not take
+// (more A entries than heads), taken in groups: consecutive such rows (lane
+// order) whose A entries fit the 64 lanes, then of those the leading rows
+// whose products fit them too.  One lane per A entry finds its B row; one
+// lane per product loads (column, a * b) with the key (row lane, column);
+// the wave sorts the keys (bitonic network over lane shuffles), sums equal
+// keys with a segmented scan, and the last lane of each run writes the sum
+// at the column's rank in its row's staging area.  The rank of a run is the
+// number of runs before it in its row, so the row comes out in column order.
+// Every lane takes part (the lookups are shuffles); a row with more than
+// 64 A entries or products is returned in the result mask for the LDS-hash
+// path.  Per-lane inputs describe the lane's row of the batch.
+template <typename VT>
+__device__ __forceinline__ uint64_t merge_fallback_sorted(
+    uint64_t todo, long long a0, long long a1, long long bo, long long nn, int row, const int* st_off,
+    int32_t* st_k, double* st_v, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
+    const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
+    int32_t* __restrict__ cnt_out, int* err) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t left = 0;                                     // rows for the LDS-hash path
+    while (todo) {                                         // wave-uniform
+        const bool cand = (todo >> lane) & 1ull;
+        const long long na = cand ? (a1 - a0 < 65 ? a1 - a0 : 65) : 0;
+        const long long ia = group_incl_scan<64>(na, lane);          // A slots of the candidates before
+        const uint64_t take = __ballot(cand && ia <= 64);
+        if (!take) {                                       // the first candidate alone has > 64 A entries
+            const uint64_t first = todo & (~todo + 1ull);
+            left |= first;
+            todo &= ~first;
+            continue;
+        }
+        const long long total_a = __shfl(ia, 63 - __builtin_clzll(take));
+        // A slot `lane`: its row r (the first lane whose prefix passes it),
+        // its entry, and that entry's B row
+        int r = 0;
+        {
+            int lo = 0, hi = 63;
+#pragma unroll
+            for (int st = 0; st < 6; ++st) {
+                const int mid = (lo + hi) >> 1;
+                const long long v = __shfl(ia, mid);
+                if (v > lane) hi = mid; else lo = mid + 1;
+            }
+            r = lo;
+        }
+        const long long r_start = __shfl(ia - na, r), r_a0 = __shfl(a0, r), r_bo = __shfl(bo, r);
+        long long bst = 0, blen = 0;
+        double av = 0.0;
+        if (lane < total_a) {
+            const long long p = r_a0 + (lane - r_start);
+            const long long k = acol[p] + r_bo;
+            av = to_f64(aval[p]);
+            bst = brp[k];
+            blen = brp[k + 1] - bst;
+        }
+        const long long ip = group_incl_scan<64>(blen, lane);        // products of the slots up to this one
+        // products of the rows up to each taken row: the prefix at its last slot
+        const long long last_slot = ia - 1 < 63 ? (ia - 1 > 0 ? ia - 1 : 0) : 63;
+        const long long upto = __shfl(ip, (int)last_slot);
+        const uint64_t fin = __ballot(((take >> lane) & 1ull) && upto <= 64);
+        if (!fin) {                                        // the first row alone has > 64 products
+            const uint64_t first = take & (~take + 1ull);
+            left |= first;
+            todo &= ~first;
+            continue;
+        }
+        const long long P = __shfl(upto, 63 - __builtin_clzll(fin));
+        // product `lane`: its slot s (the first slot whose prefix passes it)
+        int sl = 0;
+        {
+            int lo = 0, hi = 63;
+#pragma unroll
+            for (int st = 0; st < 6; ++st) {
+                const int mid = (lo + hi) >> 1;
+                const long long v = __shfl(ip, mid);
+                if (v > lane) hi = mid; else lo = mid + 1;
+            }
+            sl = lo;
+        }
+        const long long s_bst = __shfl(bst - (ip - blen), sl);
+        const double s_av = __shfl(av, sl);
+        const int s_row = __shfl(r, sl);
+        unsigned long long key = ~0ull;
+        double v = 0.0;
+        if (lane < P) {
+            const long long bi = s_bst + lane;
+            key = ((unsigned long long)(unsigned)s_row << 32) | (unsigned)bcol[bi];
+            v = s_av * to_f64(bval[bi]);
+        }
+        // ascending bitonic sort of (key, v) across the wave
+#pragma unroll
+        for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const unsigned long long ok = __shfl_xor(key, j);
+                const double ov = __shfl_xor(v, j);
+                const bool up = (lane & kk) == 0, low = (lane & j) == 0;
+                if (low == up ? ok < key : ok > key) {
+                    key = ok;
+                    v = ov;
+                }
+            }
+        }
+        // segmented inclusive sums of equal keys; a run's last lane holds its sum
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned long long ok = __shfl_up(key, d);
+            const double ov = __shfl_up(v, d);
+            if (lane >= d && ok == key) v += ov;
+        }
+        // (every lane takes part in each shuffle: none sits under a condition)
+        const unsigned long long knext = __shfl_down(key, 1), kprev = __shfl_up(key, 1);
+        const bool valid = key != ~0ull;
+        const bool tail = valid && (lane == 63 || knext != key);
+        const uint64_t tails = __ballot(tail);
+        const int rl = (int)(key >> 32);
+        const bool row_head = lane == 0 || (int)(kprev >> 32) != rl;
+        int hd = row_head ? lane : 0;                      // first lane of this lane's row
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(hd, d);
+            if (lane >= d && o > hd) hd = o;
+        }
+        const int rank = __builtin_popcountll(tails & below) - __builtin_popcountll(tails & ((1ull << hd) - 1ull));
+        const int so = st_off[valid ? rl : 0];
+        const long long rnn = __shfl(nn, valid ? rl : 0);
+        const int rrow = __shfl(row, valid ? rl : 0);
+        if (tail && rank < rnn) {
+            st_k[so + rank] = (int32_t)(key & 0xffffffffu);
+            st_v[so + rank] = v;
+        }
+        // the row's last run gives its count
+        const bool row_end = tail && (lane == 63 || (int)(knext >> 32) != rl);
+        if (row_end) {
+            const int c = rank + 1;
+            if (cnt_out) cnt_out[rrow] = c <= rnn ? c : -1;
+            else if (c != rnn) *err |= 2;
+        }
+        todo &= ~fin;
+    }
+    return left;
+}
+
 template <int K, typename VT, typename IT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_num_merge(Work wk,
@@ -1467,8 +1613,11 @@ k_num_merge(Work wk,
             if (cnt_out) cnt_out[row] = t <= nn ? t : -1;
             else if (t != nn) err |= 2;
         }
-        // rows with more than K A entries: the whole wave, one row at a time
-        uint64_t fb = __ballot(in && !mine);
+        // rows with more than K A entries: groups of them whose A entries
+        // and products each fit the 64 lanes go through a register sort;
+        // the rest, the whole wave with an LDS hash, one row at a time
+        uint64_t fb = merge_fallback_sorted<VT>(__ballot(in && !mine), a0, a1, bo, nn, row, st_off[w], st_k[w],
+                                                st_v[w], acol, aval, brp, bcol, bval, cnt_out, &err);
         while (fb) {                                   // wave-uniform
             const int r = __builtin_ctzll(fb);
             fb &= fb - 1;
@@ -1574,7 +1723,7 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
     __syncthreads();
     const int tile = s_tile;
     if (tile >= (int)gridDim.x) {            // tickets not reset: report, touch nothing
-        if (threadIdx.x == 0) atomicOr(&info->err, kErrProbe);
+        if (threadIdx.x == 0) atomicOr(&info->err, kErrScan);
         return;
     }
     const long long base = (long long)tile * kScanTile + (long long)threadIdx.x * kScanPer;
@@ -1656,7 +1805,8 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
             const int first = incl_mask ? __builtin_ctzll(incl_mask) : 64;
             const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
             if (wait_mask & need) {             // a state we need is not published yet
-                if (++spins > (1LL << 26)) { if (lane == 0) atomicOr(&info->err, kErrProbe); break; }
+                // (the row pointers are then wrong: the call reports the error)
+                if (++spins > (1LL << 26)) { if (lane == 0) atomicOr(&info->err, kErrScan); break; }
                 __builtin_amdgcn_s_sleep(1);
                 continue;
             }

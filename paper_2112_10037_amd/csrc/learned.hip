@@ -82,11 +82,12 @@ k_mlp_predict(long long n, const float* __restrict__ feats, const float* __restr
 __global__ void __launch_bounds__(256, 4)
 k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ hi, const int32_t* __restrict__ lo,
            const float* __restrict__ params, float delta, int32_t* __restrict__ cap, int32_t* __restrict__ cnt,
-           BinTable nt) {
+           BinTable nt, int big, int* __restrict__ nbig) {
     __shared__ __align__(16) float w[kNParam + 3];
     for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
     __syncthreads();
     const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    bool to_exact = false;
     if (r < m) {
         const int h = hi[r];
         const int l = lo[r] < h ? lo[r] : h;
@@ -115,9 +116,16 @@ k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ h
             // otherwise overflow into the exact recomputation
             if ((long long)h <= 2LL * c || (nt.nb > 0 && bin_of(nt, c) == bin_of(nt, h))) c = h;
         }
+        // a capacity in the global bin: the row goes to the exact two-phase
+        // path (its per-window counts come from the symbolic pass there),
+        // with no padded room here
+        to_exact = big >= 0 && c > big;
+        if (to_exact) c = 0;
         cap[r] = c;
-        if (c == 0) cnt[r] = 0;
+        if (c == 0) cnt[r] = to_exact ? -2 : 0;
     }
+    const uint64_t bm = __ballot(to_exact);
+    if (bm && (threadIdx.x & 63) == __builtin_ctzll(bm)) atomicAdd(nbig, __builtin_popcountll(bm));
 }
 
 // ---------------------------------------------------------------------------
@@ -197,40 +205,78 @@ k_mlp_fwd_bwd(int batch, long long n, const int32_t* __restrict__ idx, const flo
     for (int i = 0; i < kH1; ++i) DZ1[(long long)s * kH1 + i] = (act1 >> i) & 1 ? dz1[i] : 0.f;
 }
 
-// One thread per parameter: its gradient is a sum over the batch, taken in
-// sample order (deterministic) in FP64.  The b3 thread also writes the loss.
+// Gradient, first level: workgroup t sums the batch tile [t TS, t TS + TS)
+// for every parameter, in FP64, in sample order, into partial[t][p]; the
+// tile's activations and deltas are staged in LDS first.  (The tiles
+// replace one long serial loop per parameter; the sums stay in a fixed
+// order, so the gradient is deterministic.)
+constexpr int kGradTS = 32;                    // samples per tile
 __global__ void __launch_bounds__(256)
-k_mlp_grad(int batch, const float* __restrict__ X, const float* __restrict__ H1, const float* __restrict__ H2,
-           const float* __restrict__ DZ1, const float* __restrict__ DZ2, const float* __restrict__ D,
-           float* __restrict__ grad, float* __restrict__ loss) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= kNParam) return;
-    double acc = 0.0;
-    const double scale = 2.0 / (double)batch;
-    if (p < kOffB1) {
-        const int i = p / kNF, f = p % kNF;
-        for (int s = 0; s < batch; ++s) acc += (double)DZ1[(long long)s * kH1 + i] * X[(long long)s * kNF + f];
-    } else if (p < kOffW2) {
-        const int i = p - kOffB1;
-        for (int s = 0; s < batch; ++s) acc += DZ1[(long long)s * kH1 + i];
-    } else if (p < kOffB2) {
-        const int q = p - kOffW2, j = q / kH1, i = q % kH1;
-        for (int s = 0; s < batch; ++s) acc += (double)DZ2[(long long)s * kH2 + j] * H1[(long long)s * kH1 + i];
-    } else if (p < kOffW3) {
-        const int j = p - kOffB2;
-        for (int s = 0; s < batch; ++s) acc += DZ2[(long long)s * kH2 + j];
-    } else if (p < kOffB3) {
-        const int j = p - kOffW3;
-        for (int s = 0; s < batch; ++s) acc += scale * D[s] * H2[(long long)s * kH2 + j];
-    } else {
-        double l = 0.0;
-        for (int s = 0; s < batch; ++s) {
-            acc += scale * D[s];
-            l += (double)D[s] * D[s];
-        }
-        if (loss) *loss = (float)(l / batch);
+k_mlp_grad_tile(int batch, const float* __restrict__ X, const float* __restrict__ H1, const float* __restrict__ H2,
+                const float* __restrict__ DZ1, const float* __restrict__ DZ2, const float* __restrict__ D,
+                double* __restrict__ partial, double* __restrict__ partial_loss) {
+    __shared__ float sx[kGradTS][kNF], sh1[kGradTS][kH1], sh2[kGradTS][kH2], sd1[kGradTS][kH1 + 1],
+        sd2[kGradTS][kH2 + 1], sd[kGradTS];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int s0 = t * kGradTS;
+    const int ns = batch - s0 < kGradTS ? batch - s0 : kGradTS;
+    for (int e = tid; e < kGradTS * kH1; e += 256) {
+        const int a = e / kH1, b = e % kH1;
+        const bool in = a < ns;
+        const long long g = (long long)(s0 + a);
+        sh1[a][b] = in ? H1[g * kH1 + b] : 0.f;
+        sh2[a][b] = in ? H2[g * kH2 + b] : 0.f;
+        sd1[a][b] = in ? DZ1[g * kH1 + b] : 0.f;
+        sd2[a][b] = in ? DZ2[g * kH2 + b] : 0.f;
+        if (b < kNF) sx[a][b] = in ? X[g * kNF + b] : 0.f;
+        if (b == 0) sd[a] = in ? D[g] : 0.f;
     }
-    grad[p] = (float)acc;
+    __syncthreads();
+    const double scale = 2.0 / (double)batch;
+    for (int p = tid; p < kNParam; p += 256) {
+        double acc = 0.0;
+        if (p < kOffB1) {
+            const int i = p / kNF, f = p % kNF;
+            for (int a = 0; a < ns; ++a) acc += (double)sd1[a][i] * sx[a][f];
+        } else if (p < kOffW2) {
+            const int i = p - kOffB1;
+            for (int a = 0; a < ns; ++a) acc += sd1[a][i];
+        } else if (p < kOffB2) {
+            const int q = p - kOffW2, j = q / kH1, i = q % kH1;
+            for (int a = 0; a < ns; ++a) acc += (double)sd2[a][j] * sh1[a][i];
+        } else if (p < kOffW3) {
+            const int j = p - kOffB2;
+            for (int a = 0; a < ns; ++a) acc += sd2[a][j];
+        } else if (p < kOffB3) {
+            const int j = p - kOffW3;
+            for (int a = 0; a < ns; ++a) acc += scale * sd[a] * sh2[a][j];
+        } else {
+            double l = 0.0;
+            for (int a = 0; a < ns; ++a) {
+                acc += scale * sd[a];
+                l += (double)sd[a] * sd[a];
+            }
+            partial_loss[t] = l;
+        }
+        partial[(long long)t * kNParam + p] = acc;
+    }
+}
+
+// Gradient, second level: the tiles' partial sums in tile order.
+__global__ void __launch_bounds__(256)
+k_mlp_grad_sum(int tiles, int batch, const double* __restrict__ partial, const double* __restrict__ partial_loss,
+               float* __restrict__ grad, float* __restrict__ loss) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < kNParam) {
+        double acc = 0.0;
+        for (int t = 0; t < tiles; ++t) acc += partial[(long long)t * kNParam + p];
+        grad[p] = (float)acc;
+    }
+    if (p == 0 && loss) {
+        double l = 0.0;
+        for (int t = 0; t < tiles; ++t) l += partial_loss[t];
+        *loss = (float)(l / batch);
+    }
 }
 
 // Adam (Kingma and Ba, 2015) with bias-corrected moments; step is 1-based.
@@ -426,7 +472,7 @@ static msp_status launch_check2(const char* what) {
 
 struct msp_predictor {
     int device = 0;
-    msp::DevBuf params, m, v, grad, loss, bad, X, H1, H2, DZ1, DZ2, D;
+    msp::DevBuf params, m, v, grad, loss, bad, X, H1, H2, DZ1, DZ2, D, part, part_loss;
     int batch_cap = 0;
     float delta = 0.f;
     long long step = 0;
@@ -462,7 +508,8 @@ extern "C" msp_status msp_predictor_destroy(msp_predictor* p) {
     if (!p) return MSP_OK;
     (void)hipSetDevice(p->device);
     for (DevBuf* b :
-         {&p->params, &p->m, &p->v, &p->grad, &p->loss, &p->bad, &p->X, &p->H1, &p->H2, &p->DZ1, &p->DZ2, &p->D})
+         {&p->params, &p->m, &p->v, &p->grad, &p->loss, &p->bad, &p->X, &p->H1, &p->H2, &p->DZ1, &p->DZ2, &p->D,
+          &p->part, &p->part_loss})
         b->release();
     delete p;
     return MSP_OK;
@@ -609,6 +656,9 @@ static msp_status ensure_batch(msp_predictor* p, int batch) {
         (s = p->H2.ensure(b * kH2 * 4)) != MSP_OK || (s = p->DZ1.ensure(b * kH1 * 4)) != MSP_OK ||
         (s = p->DZ2.ensure(b * kH2 * 4)) != MSP_OK || (s = p->D.ensure(b * 4)) != MSP_OK)
         return s;
+    const size_t tiles = (b + kGradTS - 1) / kGradTS;
+    if ((s = p->part.ensure(tiles * kNParam * 8)) != MSP_OK || (s = p->part_loss.ensure(tiles * 8)) != MSP_OK)
+        return s;
     p->batch_cap = batch;
     return MSP_OK;
 }
@@ -622,11 +672,15 @@ static msp_status grad_step(msp_handle* h, msp_predictor* p, const float* feats,
         batch, n, idx, feats, targets, p->params.as<float>(), p->X.as<float>(), p->H1.as<float>(), p->H2.as<float>(),
         p->DZ1.as<float>(), p->DZ2.as<float>(), p->D.as<float>(), p->bad.as<int>());
     if ((s = launch_check2("k_mlp_fwd_bwd")) != MSP_OK) return s;
-    k_mlp_grad<<<(kNParam + 255) / 256, 256, 0, h->stream>>>(batch, p->X.as<float>(), p->H1.as<float>(),
-                                                              p->H2.as<float>(), p->DZ1.as<float>(),
-                                                              p->DZ2.as<float>(), p->D.as<float>(),
-                                                              p->grad.as<float>(), loss_dev);
-    return launch_check2("k_mlp_grad");
+    const int tiles = (batch + kGradTS - 1) / kGradTS;
+    k_mlp_grad_tile<<<tiles, 256, 0, h->stream>>>(batch, p->X.as<float>(), p->H1.as<float>(), p->H2.as<float>(),
+                                                  p->DZ1.as<float>(), p->DZ2.as<float>(), p->D.as<float>(),
+                                                  p->part.as<double>(), p->part_loss.as<double>());
+    if ((s = launch_check2("k_mlp_grad_tile")) != MSP_OK) return s;
+    k_mlp_grad_sum<<<(kNParam + 255) / 256, 256, 0, h->stream>>>(tiles, batch, p->part.as<double>(),
+                                                                  p->part_loss.as<double>(), p->grad.as<float>(),
+                                                                  loss_dev);
+    return launch_check2("k_mlp_grad_sum");
 }
 
 // Sample indices outside [0, n) were flagged by the forward/backward kernel:
@@ -778,9 +832,12 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     h->prof.begin(MSP_PHASE_PREDICT, h->stream);
     if (m > 0) {
         const int blocks = (m + 255) / 256;
+        // rows whose capacity falls in the global bin take the exact path
+        const int big = (opts && opts->force_spill) || np.table.nb <= 1 ? -1 : np.table.umax[np.table.nb - 1];
         k_capacity<<<blocks, 256, 0, h->stream>>>(m, x->feat.as<float>(), h->u.as<int32_t>(), x->lo.as<int32_t>(),
                                                   p->params.as<float>(), p->delta, x->cap.as<int32_t>(),
-                                                  x->cnt.as<int32_t>(), np.table);
+                                                  x->cnt.as<int32_t>(), np.table, big,
+                                                  &h->info.as<DevInfo>()->learned_big);
         if ((s = launch_check2("k_capacity")) != MSP_OK) return cleanup(s);
     }
     h->prof.end(h->stream);
@@ -792,6 +849,7 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
     const long long sum_cap = h->hinfo->nnz;
     stats.sum_cap = sum_cap;
+    stats.exact_rows = h->hinfo->learned_big;
     int counts[kNB];
     sum_parts(h->hinfo->num_part, counts);
     // 4. numeric pass in capacity mode into the padded area
@@ -813,7 +871,7 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     if ((s = read_info(h)) != MSP_OK) return cleanup(s);
     if ((s = device_error(h->hinfo->err)) != MSP_OK) return cleanup(s);
     const int novf = h->hinfo->neg_count;
-    stats.overflow_rows = novf;
+    stats.overflow_rows = novf - stats.exact_rows;
     int64_t* src_off = nullptr;
     int32_t* scol = nullptr;
     char* sval = nullptr;

@@ -745,6 +745,7 @@ msp_status validate_inputs(msp_handle* h, const msp_csr* A, const msp_csr* B) {
 }
 
 msp_status device_error(int err) {
+    if (err & kErrScan) return fail(MSP_ERR_HIP, "internal: prefix-sum look-back wait exceeded its bound");
     if (err & kErrProbe) return fail(MSP_ERR_HIP, "internal: hash probe bound exceeded");
     if (err & kErrCount) return fail(MSP_ERR_HIP, "internal: numeric row count differs from symbolic count");
     return MSP_OK;

@@ -20,6 +20,7 @@ constexpr int kErrRange = 4;      // input index out of range / row_ptr not mono
 constexpr int kErrCount = 8;      // numeric count disagrees with the symbolic count
 constexpr int kErrPlan = 16;      // batch replay: a row fell in a bin the plan has no kernel for
 constexpr int kErrCapacity = 32;  // batch replay: the output outgrew the plan's arena
+constexpr int kErrScan = 64;      // prefix sum: a look-back wait passed its bound, or tile tickets were stale
 
 // Predictor features 0..5 are log2(1 + x) scaled by this factor so that
 // every network input is of order one.
@@ -46,7 +47,8 @@ struct DevInfo {
     int win_fb[2];                        // global-bin rows without a record: {count, 0}
     int win_nbs;                          // B rows given a window index
     int win_nbms;                         // rows whose bitmap the symbolic pass stored
-    int pad[21];
+    int learned_big;                      // learned product: rows sent to the exact path by capacity
+    int pad[20];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors

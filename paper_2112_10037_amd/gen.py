@@ -135,6 +135,79 @@ def erdos_renyi(nrows: int, ncols: int, k, seed: int, dtype=np.float64) -> CSR:
     return CSR(nrows, ncols, row_ptr, cols.astype(np.int32), val)
 
 
+def banded_random(n: int, k: int, halfwidth: int, seed: int, dtype=np.float64) -> CSR:
+    """n x n: row i holds the diagonal and k - 1 other distinct columns drawn
+    uniformly from the band [i - w, i + w] clipped to [0, n) (fewer when the
+    clipped band is narrower), the locality of a mesh-based matrix.
+    Values U[-1, 1] in CSR order."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [np.arange(n, dtype=np.int64)], [np.arange(n, dtype=np.int64)]
+    i = np.arange(n, dtype=np.int64)
+    lo = np.maximum(0, i - halfwidth)
+    size = np.minimum(n - 1, i + halfwidth) - lo          # band width minus the diagonal
+    kk = np.minimum(k - 1, size)
+    m = int(kk.max()) if n else 0
+    if m > 0:
+        draw = (rng.random((n, m)) * size[:, None]).astype(np.int64)
+        s = np.sort(draw, axis=1)
+        bad = np.nonzero(np.any((s[:, 1:] == s[:, :-1]) & (np.arange(1, m)[None, :] < kk[:, None]), axis=1))[0]
+        for r in bad:
+            draw[r, :kk[r]] = rng.choice(size[r], size=int(kk[r]), replace=False)
+        c = lo[:, None] + draw
+        c = np.where(c >= i[:, None], c + 1, c)            # skip the diagonal
+        keep = np.arange(m)[None, :] < kk[:, None]
+        rows.append(np.repeat(i, kk))
+        cols.append(c[keep])
+    rr, cc = np.concatenate(rows), np.concatenate(cols)
+    row_ptr, col, _ = _from_coo(n, n, rr, cc)
+    return CSR(n, n, row_ptr, col, _uniform_pm1(rng, col.size, dtype))
+
+
+def powerlaw_rows(n: int, alpha: float, kmin: int, kmax: int, seed: int, dtype=np.float64) -> CSR:
+    """n x n with power-law row lengths: k_i = floor(kmin (1 - u)^(-1/alpha))
+    clipped to [kmin, kmax] (mean about kmin alpha / (alpha - 1)), columns
+    uniform without replacement as in erdos_renyi.  Values U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    k = np.floor(kmin * (1.0 - rng.random(n)) ** (-1.0 / alpha)).astype(np.int64)
+    k = np.clip(k, kmin, min(kmax, n))
+    # every row's columns in one draw; rows where a column repeats are
+    # redrawn without replacement
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(k, out=row_ptr[1:])
+    rid = np.repeat(np.arange(n, dtype=np.int64), k)
+    cols = rng.integers(0, n, size=int(row_ptr[-1]), dtype=np.int64)
+    cols = cols[np.lexsort((cols, rid))]
+    dup = np.nonzero((cols[1:] == cols[:-1]) & (rid[1:] == rid[:-1]))[0]
+    for r in np.unique(rid[dup + 1]):
+        cols[row_ptr[r]:row_ptr[r + 1]] = np.sort(rng.choice(n, size=int(k[r]), replace=False))
+    return CSR(n, n, row_ptr, cols.astype(np.int32), _uniform_pm1(rng, cols.size, dtype))
+
+
+# Stand-ins for the eight matrices of the paper's evaluation (Sec. V-A,
+# Table IV: SuiteSparse matrices, not available here), with the dimensions
+# and densities the table gives and a structure of the same kind: 3D
+# 27-point stencils for the FEM Poisson and filter matrices, banded random
+# rows for the FEM sphere and offshore meshes, uniform rows for the DNA
+# electrophoresis and economics matrices, power-law rows for the circuit and
+# an R-MAT graph for the web crawl.  FP32, as in the paper.
+TABLE4 = [
+    # name, rows, density (Table IV), recipe
+    ("poisson3Da", 14_000, 1.9e-3, lambda dt: stencil_27(24, seed=4001, dtype=dt)),
+    ("2cubes_sphere", 101_000, 1.6e-4, lambda dt: banded_random(101_000, 16, 2_170, seed=4002, dtype=dt)),
+    ("filter3D", 106_000, 2.4e-4, lambda dt: stencil_27(47, seed=4003, dtype=dt)),
+    ("cage12", 130_000, 1.2e-4, lambda dt: erdos_renyi(130_000, 130_000, 16, seed=4004, dtype=dt)),
+    ("scircuit", 171_000, 3.3e-5, lambda dt: powerlaw_rows(171_000, 1.45, 2, 2_000, seed=4005, dtype=dt)),
+    ("mac_econ_fwd500", 207_000, 3.0e-5, lambda dt: erdos_renyi(207_000, 207_000, 6, seed=4006, dtype=dt)),
+    ("offshore", 260_000, 6.3e-5, lambda dt: banded_random(260_000, 16, 4_070, seed=4007, dtype=dt)),
+    ("webbase-1M", 1_000_000, 3.1e-6, lambda dt: rmat(20, int(3.2 * 2 ** 20), seed=4008, dtype=dt)),
+]
+
+
+def table4_standins(dtype=np.float32):
+    """[(name, CSR)] of the Table IV stand-ins (FP32 unless told)."""
+    return [(name, recipe(dtype)) for name, _, _, recipe in TABLE4]
+
+
 # ---------------------------------------------------------------------------
 # Finite-difference stencils (Dirichlet boundary: off-grid neighbours dropped)
 # ---------------------------------------------------------------------------

@@ -67,3 +67,31 @@ def test_suite():
     assert {m.family for m in s} == {"stencil27", "er", "rmat"}
     m = s[1].build(scale_down=8)
     m.check()
+
+
+def test_table4_standins_match_the_table_shapes():
+    """The stand-ins for the paper's eight matrices (Sec. V-A, Table IV) have
+    its dimensions within 5% and its densities within 15%, FP32, canonical."""
+    for (name, rows, dens, _), (name2, M) in zip(gen.TABLE4, gen.table4_standins()):
+        assert name == name2
+        M.check()
+        assert M.val.dtype == np.float32 and M.nrows == M.ncols
+        assert abs(M.nrows / rows - 1) < 0.05, name
+        assert abs(M.nnz / M.nrows / M.ncols / dens - 1) < 0.15, name
+
+
+def test_banded_random_rows():
+    M = gen.banded_random(500, 9, 20, seed=3)
+    M.check()
+    r = np.repeat(np.arange(500), np.diff(M.row_ptr))
+    assert np.all(np.abs(M.col.astype(np.int64) - r) <= 20)
+    assert np.all(np.diff(M.row_ptr) == 9)
+    assert np.all(np.bincount(r[M.col == r], minlength=500) == 1)    # every row holds its diagonal
+
+
+def test_powerlaw_rows_lengths():
+    M = gen.powerlaw_rows(20000, 1.45, 2, 500, seed=9)
+    M.check()
+    k = np.diff(M.row_ptr)
+    assert k.min() >= 2 and k.max() <= 500
+    assert 4.5 < k.mean() < 7.0 and np.median(k) <= 4

@@ -172,6 +172,29 @@ def test_trained_network_gains_over_no_network(h):
           f"overflow {ovf / rows:.4f} of rows")
     assert cap_tr < cap_up
     assert ovf <= 0.05 * rows
+    # timed, at full size, on a held-out 27-point member (side 80, 512,000
+    # rows): the trained capacities keep its rows in their accumulator bins
+    # where the network-free bound moves them to far larger tables
+    import time
+    M = next(m for m in suite if m.index == 59).build()
+    dM = to_dev(M)
+
+    def median_ms(fn, reps=7):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    t_tr = median_ms(lambda: h.spgemm_learned(pred, dM, dM))
+    t_up = median_ms(lambda: h.spgemm_learned(upper, dM, dM))
+    t_pl = median_ms(lambda: h.spgemm(dM, dM))
+    print(f"27-point side 80: trained {t_tr:.3f} ms, network-free {t_up:.3f} ms, plain {t_pl:.3f} ms")
+    assert t_tr * 1.5 < t_up
     pred.close()
     upper.close()
 

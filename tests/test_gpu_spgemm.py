@@ -95,9 +95,9 @@ def test_forced_spill(h, dtype):
     check_full(h, B, B, force_spill=True)
 
 
-def test_hub_rows_lds_bitmap_and_dense(h):
+def test_hub_rows_lds_bitmap_and_global_bin(h):
     """A few rows whose union exceeds every LDS table: symbolic bitmap (LDS)
-    and numeric global dense accumulator."""
+    and the numeric global bin (column-window slices)."""
     rng = np.random.default_rng(8)
     n = 20000
     B = gen.erdos_renyi(n, n, 8, seed=9)
@@ -485,3 +485,12 @@ def test_validation_accepts_views(h):
     with pytest.raises(binding.MspError) as e:
         h.spgemm(bad, to_dev(B), validate=True)
     assert e.value.name == "MSP_ERR_INVALID_ARG"
+
+
+@pytest.mark.parametrize("index", range(8))
+def test_table4_standins(h, index):
+    """C = A*A on the FP32 stand-ins of the paper's eight matrices (Table IV
+    shapes and densities), compared with the oracle in full."""
+    name, A = gen.TABLE4[index][0], gen.TABLE4[index][3](np.float32)
+    err = check_full(h, A, A)
+    print(f"{name}: max |c-o|/bound = {err:.3e}")
