@@ -483,6 +483,75 @@ def batched_leg(h, sides, reps: int, tuning_cache: str, meter=None) -> dict:
             "results_identical_to_plain": same, "energy": energy}
 
 
+OMAR_GROUPS = (2, 4, 8, 16, 32, 64)
+
+
+def sharing_leg(h, dmain, main_name: str, mats, reps: int = 20) -> dict:
+    """B-row sharing (Sec. IV-A): OMAR of Eq. (1) at the paper's group sizes
+    on each config (computed on the GPU), and the numeric merge with and
+    without the LDS stage on the 2D Laplacian and on a Galerkin A P (n = 32)."""
+    import torch
+    from paper_2112_10037_amd import binding, gen
+    out = {"omar_percent": {}, "groups": list(OMAR_GROUPS)}
+
+    def omar_row(dX):
+        return [round(h.omar(dX, g), 3) for g in OMAR_GROUPS]
+
+    for name in ("er4096", "laplacian2d_1024"):
+        _, X = workload(name)
+        dX = binding.DeviceCSR.from_host(X, "cuda:0")
+        out["omar_percent"][name] = omar_row(dX)
+        del dX
+    out["omar_percent"][main_name] = omar_row(dmain)
+    if mats is not None:
+        for i in (11, 15, 7):                # one suite member per family
+            dX = binding.DeviceCSR.from_host(mats[i], "cuda:0")
+            out["omar_percent"][f"suite_{i}_{('er', 'rmat', 'stencil27')[i % 3]}"] = omar_row(dX)
+            del dX
+
+    def timing(X, Y, base, label):
+        dX = binding.DeviceCSR.from_host(X, "cuda:0")
+        dY = dX if Y is X else binding.DeviceCSR.from_host(Y, "cuda:0")
+        res = {}
+        for g in (0, 16, 32, 64):
+            t = tuple(base) + ((g,) if g else ())
+            C = h.spgemm(dX, dY, tuning=t)
+            del C
+            h.sync()
+            h.profile(True, phases=["numeric"])
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                C = h.spgemm(dX, dY, tuning=t, check=False)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                del C
+            h.sync()
+            num_ms, num_n = h.profile_get()["numeric"]
+            h.profile(False)
+            st = h.share_stats()
+            key = f"share_g_{g}" if g else "unshared"
+            res[key] = {"ms_median": round(float(np.median(ts)) * 1e3, 4),
+                        "numeric_ms": round(num_ms / max(num_n, 1), 5)}
+            if g:
+                res[key].update(st)
+                if st["a_entries"]:
+                    res[key]["b_reads_saved_percent"] = round(
+                        100.0 * (st["a_entries"] - st["b_rows"]) / st["a_entries"], 3)
+        del dX, dY
+        torch.cuda.empty_cache()
+        progress(f"sharing: {label}: " + ", ".join(f"{k} {v['numeric_ms']} ms" for k, v in res.items()))
+        return res
+
+    _, L = workload("laplacian2d_1024")
+    out["laplacian2d_1024_numeric"] = timing(L, L, (1, 0, 4096, 1024, 8), "laplacian2d_1024")
+    # (a 3D band spans 2 n^2 B rows: n = 32 keeps a batch within the stage's
+    # 4,096-row span bitmap)
+    A, P, _ = gen.galerkin_problem(32)
+    out["galerkin32_AP_numeric"] = timing(A, P, (1, 0, 4096, 1024, 8), "galerkin n=32, A P")
+    return out
+
+
 # plain-path tunings the autotuner compares on the main workload
 PLAIN_CANDIDATES = [(1, 0, 4096, 1024, 8), (1, 0, 2048, 1024, 8), (1, 0, 1024, 1024, 8), (2, 0, 4096, 1024, 8)]
 
@@ -584,6 +653,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the smaller configs' entries")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy entries")
     ap.add_argument("--no-table4", action="store_true", help="skip the Table IV stand-ins")
+    ap.add_argument("--no-sharing", action="store_true", help="skip the B-row sharing leg (OMAR, staged merge)")
     ap.add_argument("--no-autotune", action="store_true", help="run the library's default tuning")
     ap.add_argument("--legs-reps", type=int, default=5)
     ap.add_argument("--train-steps", type=int, default=2000)
@@ -742,6 +812,11 @@ def main():
                 meter, lap_call, out["configs"]["laplacian2d_1024"]["products"], "f64")
             del dL
         progress("configs done")
+    if not args.no_sharing:
+        dA = binding.DeviceCSR.from_host(A, "cuda:0")
+        out["b_row_sharing"] = sharing_leg(h, dA, args.workload, mats)
+        del dA
+        torch.cuda.empty_cache()
     if not args.no_table4:
         out["table4_standins"] = table4_leg(h)
         progress(f"table4 stand-ins: geomean {out['table4_standins']['geomean_gflops']} GFLOP/s")

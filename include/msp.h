@@ -108,6 +108,10 @@ typedef struct {
                                over)                                            */
     int32_t merge_k;        /* rows with bound <= 32 and at most merge_k A
                                entries use the per-lane merge (4 or 8; -1: off) */
+    int32_t share_g;        /* B-row sharing in the numeric merge (Sec. IV-A):
+                               a wave takes at most share_g rows (8..64) and
+                               stages every distinct B row they reference once
+                               in LDS when they fit (-1: off, the default)    */
 } msp_tuning;
 
 typedef struct {
@@ -211,6 +215,28 @@ msp_status msp_spgemm_noalloc(msp_handle* h, const msp_csr* A, const msp_csr* B,
  */
 msp_status msp_autotune(msp_handle* h, const msp_csr* A, const msp_csr* B, const msp_tuning* cand, int ncand,
                         int reps, msp_tuning* best, double* times_ms);
+
+/* ---- B-row sharing (Sec. IV-A) ------------------------------------------- */
+
+/* The count behind OMAR (Eq. 1).  With A's rows taken in groups of `group`
+ * consecutive rows (the last group may be shorter), a row of B is read once
+ * per distinct (group, column) pair of A rather than once per entry; this
+ * writes that number of pairs to *distinct (host memory), so that
+ * OMAR = (nnz(A) - *distinct) / nnz(A).  A is a device CSR (canonical);
+ * group in 1..4096 (MSP_ERR_INVALID_ARG otherwise).  Synchronises the
+ * handle's stream. */
+msp_status msp_omar(msp_handle* h, const msp_csr* A, int64_t group, int64_t* distinct);
+
+typedef struct {
+    int64_t batches;      /* merge batches that read B from the LDS stage     */
+    int64_t a_entries;    /* A entries of those batches' merge rows: the B-row
+                             reads they would make without sharing           */
+    int64_t b_rows;       /* distinct B rows they staged, each read once      */
+} msp_share_stats;
+
+/* B-row sharing figures of the handle's last call (msp_spgemm with
+ * tuning.share_g on; zero otherwise).  Synchronises the handle's stream. */
+msp_status msp_share_stats_get(msp_handle* h, msp_share_stats* out);
 
 /* Only the symbolic part: row_nnz (device, A.nrows int32) and the total.
  * Used to produce training targets for the predictor. */
@@ -408,8 +434,9 @@ msp_status msp_batch_info(const msp_batch* plan, msp_batch_stats* st);
 msp_status msp_batch_autotune(msp_handle* h, const msp_batch_csr* R, const msp_batch_csr* A,
                               const msp_batch_csr* P, const msp_tuning* cand, int ncand, int reps,
                               msp_tuning* best, double* times_ms);
-/* A tuning as a flat JSON object of its five fields; returns the length
- * written (snprintf semantics), or -1 when t is NULL. */
+/* A tuning as a flat JSON object of its fields; returns the length
+ * written (snprintf semantics), or -1 when t is NULL.  When parsing, share_g
+ * may be absent (the default). */
 int msp_tuning_to_json(const msp_tuning* t, char* buf, size_t n);
 /* Parse that object (field order and spacing free); checks the values as
  * msp_set_tuning does. */

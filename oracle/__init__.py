@@ -173,6 +173,24 @@ def features(A, B) -> np.ndarray:
     return f
 
 
+def omar_distinct(A, group: int) -> int:
+    """B-row reads of the buffering scheme of Sec. IV-A (Eq. (1)): with A's
+    rows taken in groups of ``group`` consecutive rows (the last group may be
+    shorter), one read of B row k per group whose rows hold column k.  The
+    number of distinct (group, column) pairs, by the definition: the union of
+    the columns of each group's rows, summed over groups."""
+    rp = np.asarray(A.row_ptr, dtype=np.int64)
+    rows = np.repeat(np.arange(A.nrows, dtype=np.int64), np.diff(rp))
+    keys = (rows // int(group)) * max(int(A.ncols), 1) + np.asarray(A.col, dtype=np.int64)
+    return int(np.unique(keys).size)
+
+
+def omar(A, group: int) -> float:
+    """OMAR of Eq. (1) in percent: the B-row reads saved, over nnz(A)."""
+    nnz = int(A.row_ptr[-1]) if A.nrows else 0
+    return 100.0 * (nnz - omar_distinct(A, group)) / nnz if nnz else 0.0
+
+
 def compare(rp, col, val, ref, tol: float):
     """Check a computed C block against an oracle block ``ref`` (the tuple
     returned by :func:`spgemm`).  Structure must be identical; every value

@@ -44,7 +44,18 @@ class c_csr_out(ctypes.Structure):
 class c_tuning(ctypes.Structure):
     _fields_ = [("hash_scale", ctypes.c_int32), ("group_scale", ctypes.c_int32),
                 ("spill_nnz", ctypes.c_int32), ("block_rows", ctypes.c_int32),
-                ("merge_k", ctypes.c_int32)]
+                ("merge_k", ctypes.c_int32), ("share_g", ctypes.c_int32)]
+
+
+def _tuple(t: "c_tuning"):
+    """A tuning as a tuple: its five fields, and share_g sixth when sharing
+    is on (a five-field tuple leaves it at the default, off)."""
+    base = (t.hash_scale, t.group_scale, t.spill_nnz, t.block_rows, t.merge_k)
+    return base + (t.share_g,) if t.share_g > 0 else base
+
+
+class c_share_stats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("a_entries", ctypes.c_int64), ("b_rows", ctypes.c_int64)]
 
 
 class c_opts(ctypes.Structure):
@@ -150,6 +161,9 @@ SIGNATURES = [
     ("msp_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.POINTER(c_csr),
                                     ctypes.POINTER(c_tuning), ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(c_tuning), ctypes.POINTER(ctypes.c_double)]),
+    ("msp_omar", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_csr), ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int64)]),
+    ("msp_share_stats_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_share_stats)]),
     ("msp_tuning_to_json", ctypes.c_int, [ctypes.POINTER(c_tuning), ctypes.c_char_p, ctypes.c_size_t]),
     ("msp_tuning_from_json", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(c_tuning)]),
     ("msp_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -340,7 +354,7 @@ class Handle:
     def get_tuning(self):
         t = c_tuning()
         _check(self._lib.msp_get_tuning(self._h, ctypes.byref(t)))
-        return (t.hash_scale, t.group_scale, t.spill_nnz, t.block_rows, t.merge_k)
+        return _tuple(t)
 
     def sync(self):
         """Wait for the handle's stream; raise on any internal error that the
@@ -452,8 +466,26 @@ class Handle:
                                           ctypes.byref(best), times))
         finally:
             self._end()
-        return ((best.hash_scale, best.group_scale, best.spill_nnz, best.block_rows, best.merge_k),
-                [float(t) for t in times])
+        times = [float(t) for t in times]
+        return tuple(candidates[times.index(min(times))]), times
+
+    def omar_distinct(self, A: DeviceCSR, group: int) -> int:
+        """Distinct (row group, column) pairs of A for groups of `group`
+        consecutive rows: the B-row reads of Eq. (1)'s buffering scheme."""
+        out = ctypes.c_int64()
+        a = A.c()
+        _check(self._lib.msp_omar(self._h, ctypes.byref(a), int(group), ctypes.byref(out)))
+        return int(out.value)
+
+    def omar(self, A: DeviceCSR, group: int) -> float:
+        """OMAR of Eq. (1) in percent."""
+        return 100.0 * (A.nnz - self.omar_distinct(A, group)) / A.nnz if A.nnz else 0.0
+
+    def share_stats(self) -> dict:
+        """B-row sharing figures of the handle's last call (after a wait)."""
+        st = c_share_stats()
+        _check(self._lib.msp_share_stats_get(self._h, ctypes.byref(st)))
+        return {"batches": st.batches, "a_entries": st.a_entries, "b_rows": st.b_rows}
 
     def row_features(self, A: DeviceCSR, B: DeviceCSR):
         """(prod int64 [m], features float32 [m, 8])."""
@@ -716,8 +748,8 @@ def autotune(handle: "Handle", A: PackedBatch, P: PackedBatch, R: PackedBatch | 
     _check(handle._lib.msp_batch_autotune(handle._h, ctypes.byref(cr) if cr is not None else None,
                                           ctypes.byref(ca), ctypes.byref(cp), arr, n, reps,
                                           ctypes.byref(best), times))
-    return ((best.hash_scale, best.group_scale, best.spill_nnz, best.block_rows, best.merge_k),
-            [float(t) for t in times])
+    times = [float(t) for t in times]
+    return tuple(candidates[times.index(min(times))]), times
 
 
 def tuning_to_json(t) -> str:
@@ -733,4 +765,4 @@ def tuning_from_json(js: str):
     lib = load()
     ct = c_tuning()
     _check(lib.msp_tuning_from_json(js.encode(), ctypes.byref(ct)))
-    return (ct.hash_scale, ct.group_scale, ct.spill_nnz, ct.block_rows, ct.merge_k)
+    return _tuple(ct)

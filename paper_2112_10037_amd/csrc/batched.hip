@@ -670,13 +670,15 @@ extern "C" msp_status msp_batch_autotune(msp_handle* h, const msp_batch_csr* R, 
 }
 
 // ---------------------------------------------------------------------------
-// tuning <-> JSON (a flat object of the five integer fields)
+// tuning <-> JSON (a flat object of the integer fields; share_g may be
+// absent, meaning the default)
 // ---------------------------------------------------------------------------
 extern "C" int msp_tuning_to_json(const msp_tuning* t, char* buf, size_t n) {
     if (!t) return -1;
     return snprintf(buf, buf ? n : 0,
-                    "{\"hash_scale\": %d, \"group_scale\": %d, \"spill_nnz\": %d, \"block_rows\": %d, \"merge_k\": %d}",
-                    t->hash_scale, t->group_scale, t->spill_nnz, t->block_rows, t->merge_k);
+                    "{\"hash_scale\": %d, \"group_scale\": %d, \"spill_nnz\": %d, \"block_rows\": %d, \"merge_k\": %d, "
+                    "\"share_g\": %d}",
+                    t->hash_scale, t->group_scale, t->spill_nnz, t->block_rows, t->merge_k, t->share_g);
 }
 
 static bool json_int(const char* js, const char* key, int* out) {
@@ -701,6 +703,7 @@ extern "C" msp_status msp_tuning_from_json(const char* js, msp_tuning* t) {
         !json_int(js, "spill_nnz", &x.spill_nnz) || !json_int(js, "block_rows", &x.block_rows) ||
         !json_int(js, "merge_k", &x.merge_k))
         return fail(MSP_ERR_INVALID_ARG, "tuning JSON lacks one of its five integer fields");
+    if (!json_int(js, "share_g", &x.share_g)) x.share_g = 0;
     msp_status s = check_tuning(&x);
     if (s != MSP_OK) return s;
     *t = x;

@@ -38,6 +38,7 @@ struct BinSpec {
     int lanes = 0;      // K lists for Merge, rows per batch R for Batch, G for Group,
                         // BS for Block/Bitmap/Dense
     int slots = 0;      // T (hash slots) for Group/Block
+    int share = 0;      // Merge, numeric: rows per batch that share staged B rows (0: off)
 };
 
 struct BinPlan {

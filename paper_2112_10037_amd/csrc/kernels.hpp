@@ -26,6 +26,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <climits>
 #include <type_traits>
 
 #include "types.hpp"
@@ -1506,13 +1507,48 @@ __device__ __forceinline__ uint64_t merge_fallback_sorted(
     return left;
 }
 
-template <int K, typename VT, typename IT, bool BATCH = false>
+// B-row sharing across the rows of a merge batch (Sec. IV-A, Fig. 3).  The
+// paper's processing elements each take one row of A, and a row of B that
+// they all need is read from off-chip memory once and buffered for all of
+// them.  Here the lanes of a wave take one row each: the wave stages every
+// distinct B row that its merge rows reference once in LDS (in ascending B
+// row order, one lane copying each row), and the lanes' merges read B from
+// LDS.  A batch is staged when its B rows span at most 64 kShareSpanWords
+// rows, number at most kShareRows and hold at most share_entries<VT>()
+// entries; otherwise it reads B from global memory as without sharing.
+constexpr int kShareSpanWords = 64;               // span bitmap: 64-bit words per wave
+constexpr int kShareRows = 256;                   // distinct B rows per staged batch
+template <typename VT>
+constexpr int share_entries() { return sizeof(VT) == 8 ? 512 : 768; }
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const T y = __shfl_xor(x, d);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const T y = __shfl_xor(x, d);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// With SHARE, a batch takes at most share_g rows (the group of rows that
+// share the staged B rows).
+template <int K, typename VT, typename IT, bool BATCH = false, bool SHARE = false>
 __global__ void __launch_bounds__(256)
 k_num_merge(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp, int share_g) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
@@ -1525,8 +1561,21 @@ k_num_merge(Work wk,
     __shared__ double fb_vals[4][FT + 1];
     __shared__ int st_off[4][65];               // staging offset of each row of the batch
     __shared__ long long st_c0[4][64];          // C row start of each row of the batch
+    // shared B rows (SHARE only): bit d of the span bitmap is B row kmin + d;
+    // sh_wr holds the rank of each bitmap word's first row, sh_row the
+    // distinct rows in order (as d, then as their start in B), sh_off their
+    // offsets in the stage
+    constexpr int SE = SHARE ? share_entries<VT>() : 1;
+    __shared__ unsigned long long sh_bm[4][SHARE ? kShareSpanWords : 1];
+    __shared__ int sh_wr[4][SHARE ? kShareSpanWords : 1];
+    __shared__ int sh_row[4][SHARE ? kShareRows : 1];
+    __shared__ int sh_off[4][SHARE ? kShareRows + 1 : 1];
+    __shared__ int32_t sh_col[4][SE];
+    __shared__ VT sh_val[4][SE];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int err = 0;
+    // sharing figures of the wave's batches, added to the totals once at the end
+    unsigned long long sh_batches = 0, sh_nnz = 0, sh_rows = 0;
     long long lo, hi;
     wave_range(nrows_bin, &lo, &hi);
     for (long long pos = lo; pos < hi;) {
@@ -1546,12 +1595,111 @@ k_num_merge(Work wk,
         const uint64_t fits = __ballot(lane < ncand && incl <= SN);
         int nb = leading_run(fits);             // all 64 rows may fit
         if (nb == 0) nb = 1;                    // never happens in bins with nnz <= SN
+        if (SHARE && nb > share_g) nb = share_g;
         const bool in = lane < nb;
         if (in) { st_off[w][lane] = (int)(incl - nn); st_c0[w][lane] = c0; }
         if (lane == nb - 1) st_off[w][nb] = (int)incl;
         lds_fence();
         const bool mine = in && a1 - a0 <= K && nn <= SN;
-        if (mine) {
+        bool shared = false;                    // wave-uniform
+        long long kmin = 0;
+        if constexpr (SHARE) {
+            // the span of the B rows the merge rows reference (A rows are sorted)
+            long long k_lo = LLONG_MAX, k_hi = -1;
+            if (mine && a1 > a0) {
+                k_lo = acol[a0] + bo;
+                k_hi = acol[a1 - 1] + bo;
+            }
+            kmin = wave_min(k_lo);
+            k_hi = wave_max(k_hi);
+            if (k_hi >= 0 && k_hi - kmin < 64LL * kShareSpanWords) {
+                sh_bm[w][lane] = 0ull;
+                lds_fence();
+                if (mine)
+                    for (long long p = a0; p < a1; ++p) {
+                        const int d = (int)(acol[p] + bo - kmin);
+                        atomicOr(&sh_bm[w][d >> 6], 1ull << (d & 63));
+                    }
+                lds_fence();
+                unsigned long long bits = sh_bm[w][lane];
+                const int c = __builtin_popcountll(bits);
+                const int wincl = (int)group_incl_scan<64>(c, lane);
+                const int nd = __shfl(wincl, 63);
+                if (nd <= kShareRows) {
+                    sh_wr[w][lane] = wincl - c;
+                    int r = wincl - c;
+                    while (bits) {
+                        const int t = __builtin_ctzll(bits);
+                        bits &= bits - 1ull;
+                        sh_row[w][r++] = lane * 64 + t;
+                    }
+                    lds_fence();
+                    // stage offsets: the prefix of the distinct rows' lengths;
+                    // sh_row[d] then holds row d's start in B (positions are
+                    // 32-bit where sharing runs)
+                    int tot = 0;
+                    for (int d0 = 0; d0 < nd; d0 += 64) {
+                        const int d = d0 + lane;
+                        long long len = 0, src = 0;
+                        if (d < nd) {
+                            const long long k = kmin + sh_row[w][d];
+                            src = brp[k];
+                            len = brp[k + 1] - src;
+                        }
+                        const long long li = group_incl_scan<64>(len, lane);
+                        if (d < nd) {
+                            sh_off[w][d] = (int)(tot + li - len);
+                            sh_row[w][d] = (int)src;
+                        }
+                        tot += (int)__shfl(li, 63);
+                        if (tot > SE) break;                // uniform
+                    }
+                    if (tot <= SE) {
+                        if (lane == 0) sh_off[w][nd] = tot;
+                        lds_fence();
+                        // the stage entry by entry: consecutive lanes take
+                        // consecutive entries (coalesced within a B row), and
+                        // CU rounds of loads are in flight before any store;
+                        // entry e is in the last row d with sh_off[d] <= e
+                        constexpr int CU = 4;
+                        for (int e0 = 0; e0 < tot; e0 += 64 * CU) {
+                            int32_t cc[CU];
+                            VT vv[CU];
+#pragma unroll
+                            for (int u = 0; u < CU; ++u) {
+                                const int e = e0 + u * 64 + lane;
+                                if (e < tot) {
+                                    int dlo = 0, dhi = nd;      // sh_off[dlo] <= e < sh_off[dhi]
+                                    while (dhi - dlo > 1) {
+                                        const int mid = (dlo + dhi) >> 1;
+                                        if (sh_off[w][mid] <= e) dlo = mid; else dhi = mid;
+                                    }
+                                    const long long q = (long long)sh_row[w][dlo] + (e - sh_off[w][dlo]);
+                                    cc[u] = bcol[q];
+                                    vv[u] = bval[q];
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < CU; ++u) {
+                                const int e = e0 + u * 64 + lane;
+                                if (e < tot) {
+                                    sh_col[w][e] = cc[u];
+                                    sh_val[w][e] = vv[u];
+                                }
+                            }
+                        }
+                        lds_fence();
+                        shared = true;
+                        sh_batches += 1;
+                        sh_nnz += group_sum<64>(mine ? (int)(a1 - a0) : 0);
+                        sh_rows += nd;
+                    }
+                }
+            }
+        }
+        // the merge of one lane's row over B's columns cs and values vs;
+        // range(k, &p, &e) gives head k's entries [p, e) there
+        auto merge_row = [&](const int32_t* __restrict__ cs, const VT* __restrict__ vs, auto&& range) {
             // heads: column hk at position hp (end he) in B, scale ha; the
             // head's value is loaded when it is consumed.  IT is int32 when
             // nnz(B) fits.
@@ -1571,13 +1719,11 @@ k_num_merge(Work wk,
                 hp[k] = 0;
                 he[k] = 0;
                 if (k < (int)(a1 - a0)) {
-                    const long long kk = acol[a0 + k] + bo;
                     ha[k] = to_f64(aval[a0 + k]);
-                    hp[k] = (IT)brp[kk];
-                    he[k] = (IT)brp[kk + 1];
+                    range(k, &hp[k], &he[k]);
                     if (hp[k] < he[k]) {
-                        hk[k] = bcol[hp[k]];
-                        if constexpr (PRE) hv[k] = to_f64(bval[hp[k]]);
+                        hk[k] = cs[hp[k]];
+                        if constexpr (PRE) hv[k] = to_f64(vs[hp[k]]);
                     }
                 }
             }
@@ -1596,15 +1742,15 @@ k_num_merge(Work wk,
                             acc += ha[k] * hv[k];
                             ++hp[k];
                             if (hp[k] < he[k]) {
-                                hk[k] = bcol[hp[k]];
-                                hv[k] = to_f64(bval[hp[k]]);
+                                hk[k] = cs[hp[k]];
+                                hv[k] = to_f64(vs[hp[k]]);
                             } else {
                                 hk[k] = 0x7fffffff;
                             }
                         } else {
-                            acc += ha[k] * to_f64(bval[hp[k]]);
+                            acc += ha[k] * to_f64(vs[hp[k]]);
                             ++hp[k];
-                            hk[k] = hp[k] < he[k] ? bcol[hp[k]] : 0x7fffffff;
+                            hk[k] = hp[k] < he[k] ? cs[hp[k]] : 0x7fffffff;
                         }
                     }
                 if (t < nn) { st_k[w][so + t] = m; st_v[w][so + t] = acc; }
@@ -1612,6 +1758,24 @@ k_num_merge(Work wk,
             }
             if (cnt_out) cnt_out[row] = t <= nn ? t : -1;
             else if (t != nn) err |= 2;
+        };
+        if (mine) {
+            if (SHARE && shared) {
+                // head k's B row is distinct row number rank(d) of the stage
+                merge_row(sh_col[w], sh_val[w], [&](int k, IT* p, IT* e) {
+                    const int d = (int)(acol[a0 + k] + bo - kmin);
+                    const int wd = d >> 6;
+                    const int rk = sh_wr[w][wd] + __builtin_popcountll(sh_bm[w][wd] & ((1ull << (d & 63)) - 1ull));
+                    *p = (IT)sh_off[w][rk];
+                    *e = (IT)sh_off[w][rk + 1];
+                });
+            } else {
+                merge_row(bcol, bval, [&](int k, IT* p, IT* e) {
+                    const long long kk = acol[a0 + k] + bo;
+                    *p = (IT)brp[kk];
+                    *e = (IT)brp[kk + 1];
+                });
+            }
         }
         // rows with more than K A entries: groups of them whose A entries
         // and products each fit the 64 lanes go through a register sort;
@@ -1684,6 +1848,11 @@ k_num_merge(Work wk,
         }
         lds_fence();
         pos += nb;
+    }
+    if (SHARE && lane == 0 && sh_batches) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(&info->share_batches), sh_batches);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&info->share_nnz), sh_nnz);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&info->share_rows), sh_rows);
     }
     if (err & 1) atomicOr(&info->err, kErrProbe);
     if (err & 2) atomicOr(&info->err, kErrCount);
@@ -2762,6 +2931,44 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
         __syncthreads();                                // s_rec, s_rk and the LDS are reused by the next row
     }
     if (bad && tid == 0) atomicOr(&info->err, kErrCount);
+}
+
+// ===========================================================================
+// Off-chip access reduction of B-row sharing (Eq. 1)
+// ===========================================================================
+
+// Taking A's rows in groups of `group` consecutive rows (the last group may
+// be shorter), a row of B is read once per distinct (group, column) pair
+// instead of once per entry of A.  Counts those pairs: an entry is the first
+// of its pair when no earlier row of its group holds its column (a binary
+// search in each of them).  One thread per entry, one atomic per wave.
+static __global__ void __launch_bounds__(256)
+k_omar(long long nrows, long long nnz, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
+       long long group, unsigned long long* __restrict__ distinct) {
+    unsigned long long firsts = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride) {
+        long long lo = 0, hi = nrows;               // arp[lo] <= p < arp[hi]
+        while (hi - lo > 1) {
+            const long long mid = (lo + hi) >> 1;
+            if (arp[mid] <= p) lo = mid; else hi = mid;
+        }
+        const int c = acol[p];
+        bool first = true;
+        for (long long q = lo - lo % group; q < lo && first; ++q) {
+            long long s = arp[q], e = arp[q + 1];
+            const long long end = e;
+            while (s < e) {
+                const long long mid = (s + e) >> 1;
+                if (acol[mid] < c) s = mid + 1; else e = mid;
+            }
+            if (s < end && acol[s] == c) first = false;
+        }
+        firsts += first ? 1ull : 0ull;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) firsts += __shfl_xor(firsts, d);
+    if ((threadIdx.x & 63) == 0 && firsts) atomicAdd(distinct, firsts);
 }
 
 // ===========================================================================

@@ -288,6 +288,7 @@ msp_tuning default_tuning() {
     t.spill_nnz = 4096;
     t.block_rows = 1024;
     t.merge_k = 8;
+    t.share_g = -1;
     return t;
 }
 
@@ -299,6 +300,9 @@ msp_status check_tuning(msp_tuning* t) {
     if (t->merge_k == 0) t->merge_k = d.merge_k;
     if (t->merge_k != 4 && t->merge_k != 8 && t->merge_k != -1)
         return fail(MSP_ERR_INVALID_ARG, "tuning.merge_k must be 4, 8 or -1");
+    if (t->share_g == 0) t->share_g = d.share_g;
+    if (t->share_g != -1 && (t->share_g < 8 || t->share_g > 64))
+        return fail(MSP_ERR_INVALID_ARG, "tuning.share_g must be -1 or in 8..64");
     if (t->hash_scale < 1 || t->hash_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.hash_scale must be 1 or 2");
     if (t->group_scale < 0 || t->group_scale > 2) return fail(MSP_ERR_INVALID_ARG, "tuning.group_scale must be 0..2");
     if (t->spill_nnz < 256 || t->spill_nnz > 4096 || (t->spill_nnz & (t->spill_nnz - 1)))
@@ -311,7 +315,8 @@ msp_status check_tuning(msp_tuning* t) {
 msp_tuning effective_tuning(const msp_handle* h, const msp_opts* o) {
     if (!o) return h->tuning;
     const msp_tuning& t = o->tuning;
-    if (t.hash_scale == 0 && t.group_scale == 0 && t.spill_nnz == 0 && t.block_rows == 0 && t.merge_k == 0)
+    if (t.hash_scale == 0 && t.group_scale == 0 && t.spill_nnz == 0 && t.block_rows == 0 && t.merge_k == 0 &&
+        t.share_g == 0)
         return h->tuning;
     msp_tuning c = t;
     if (check_tuning(&c) != MSP_OK) return h->tuning;

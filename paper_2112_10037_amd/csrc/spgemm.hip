@@ -54,7 +54,7 @@ static void add_small_bins(BinPlan& p, const msp_tuning& t, int limit, bool nume
     // the merge takes row_nnz steps of K comparisons each: worth it for the
     // shortest rows only
     if (t.merge_k > 0 && limit >= 32) {
-        add_bin(p, 32, BinSpec{Kind::Merge, t.merge_k, kMergeFT});
+        add_bin(p, 32, BinSpec{Kind::Merge, t.merge_k, kMergeFT, numeric && t.share_g > 0 ? t.share_g : 0});
         covered = 32;
     }
     for (int i = 0; i < 7; ++i) {
@@ -393,16 +393,23 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
     const VT* bv = (const VT*)op.bval;
     if (s.kind == Kind::Merge) {
         const bool small = op.bnnz < INT32_MAX;     // 32-bit positions into B
-#define MSP_MERGE(KK, IT)                                                                                \
+#define MSP_MERGE(KK, IT, SH)                                                                            \
     {                                                                                                    \
-        const int grid = group_grid(h, (const void*)k_num_merge<KK, VT, IT, BATCH>, rows, 256);         \
-        k_num_merge<KK, VT, IT, BATCH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, \
-                                                             ccol, cval, cnt_out, info, mp);            \
+        const int grid = group_grid(h, (const void*)k_num_merge<KK, VT, IT, BATCH, SH>, rows, 256);     \
+        k_num_merge<KK, VT, IT, BATCH, SH><<<grid, 256, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, \
+                                                                 crp, ccol, cval, cnt_out, info, mp,    \
+                                                                 s.share);                              \
         return launch_check("k_num_merge");                                                              \
     }
-        if (s.lanes == 4) { if (small) MSP_MERGE(4, int) else MSP_MERGE(4, long long) }
-        else if (s.lanes == 6) { if (small) MSP_MERGE(6, int) else MSP_MERGE(6, long long) }
-        else { if (small) MSP_MERGE(8, int) else MSP_MERGE(8, long long) }
+        // B-row sharing stages rows of B with 32-bit positions only
+        if (s.share > 0 && small) {
+            if (s.lanes == 4) MSP_MERGE(4, int, true)
+            else if (s.lanes == 6) MSP_MERGE(6, int, true)
+            else MSP_MERGE(8, int, true)
+        }
+        if (s.lanes == 4) { if (small) MSP_MERGE(4, int, false) else MSP_MERGE(4, long long, false) }
+        else if (s.lanes == 6) { if (small) MSP_MERGE(6, int, false) else MSP_MERGE(6, long long, false) }
+        else { if (small) MSP_MERGE(8, int, false) else MSP_MERGE(8, long long, false) }
 #undef MSP_MERGE
     } else if (s.kind == Kind::Batch) {
 #define X(T, R)                                                                                          \
@@ -1038,6 +1045,39 @@ extern "C" msp_status msp_row_features(msp_handle* h, const msp_csr* A, const ms
     memset(&none, 0, sizeof(none));
     if ((s = zero_info(h)) != MSP_OK) return s;
     return run_row_stats(h, A, B, none, prod, features ? features : nullptr, nullptr);
+}
+
+extern "C" msp_status msp_omar(msp_handle* h, const msp_csr* A, int64_t group, int64_t* distinct) {
+    if (!h) return fail(MSP_ERR_INVALID_ARG, "null handle");
+    if (!distinct) return fail(MSP_ERR_INVALID_ARG, "distinct is NULL");
+    msp_status s = check_csr(A, "A");
+    if (s != MSP_OK) return s;
+    if (group < 1 || group > kOmarMaxGroup) return fail(MSP_ERR_INVALID_ARG, "group must be in 1..4096");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((s = zero_info(h)) != MSP_OK) return s;
+    if (A->nnz > 0) {
+        const long long blocks = std::min<long long>((A->nnz + 255) / 256, 64LL * h->num_cu);
+        DevInfo* info = h->info.as<DevInfo>();
+        k_omar<<<(int)blocks, 256, 0, h->stream>>>(A->nrows, A->nnz, A->row_ptr, A->col, group,
+                                                    &info->omar_distinct);
+        if ((s = launch_check("k_omar")) != MSP_OK) return s;
+    }
+    if ((s = read_info(h)) != MSP_OK) return s;
+    *distinct = (int64_t)h->hinfo->omar_distinct;
+    return MSP_OK;
+}
+
+extern "C" msp_status msp_share_stats_get(msp_handle* h, msp_share_stats* out) {
+    if (!h || !out) return fail(MSP_ERR_INVALID_ARG, "null argument");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    msp_status s = read_info(h);
+    if (s != MSP_OK) return s;
+    out->batches = h->hinfo->share_batches;
+    out->a_entries = h->hinfo->share_nnz;
+    out->b_rows = h->hinfo->share_rows;
+    return MSP_OK;
 }
 
 extern "C" long long msp_internal_summary_fallbacks(const msp_handle* h) { return h ? h->summary_fallbacks : -1; }

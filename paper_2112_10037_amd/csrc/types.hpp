@@ -37,6 +37,8 @@ constexpr int kPartStride = 32;    // ints per partition row (128 bytes)
 // scan tile finds the total before it in a bounded number of reads.
 constexpr int kSupers = 1024;
 
+constexpr long long kOmarMaxGroup = 4096;   // largest row group of the sharing count
+
 struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
     int err;                              // error bits of the current call
@@ -48,7 +50,11 @@ struct DevInfo {
     int win_nbs;                          // B rows given a window index
     int win_nbms;                         // rows whose bitmap the symbolic pass stored
     int learned_big;                      // learned product: rows sent to the exact path by capacity
-    int pad[20];
+    long long share_batches;              // merge batches that read B from a shared LDS stage
+    long long share_nnz;                  // A entries of those batches' merge rows
+    long long share_rows;                 // distinct B rows those batches staged
+    unsigned long long omar_distinct;     // distinct (row group, column) pairs of A (Eq. 1)
+    int pad[12];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
