@@ -118,6 +118,11 @@ typedef struct {
     int32_t validate;       /* 1: check inputs on the device first            */
     int32_t force_spill;    /* 1: every nonempty row takes the global path    */
     msp_tuning tuning;      /* zero: defaults (or the handle's tuned values)  */
+    int32_t queue_rows;     /* batches: the numeric merge's rows reach the
+                               waves as tickets of queue_rows consecutive rows
+                               from one shared atomic counter (0: 1024; a
+                               multiple of 64 up to 65536; -1: one static row
+                               range per wave instead).  Plain calls: unused */
 } msp_opts;
 
 typedef struct msp_handle msp_handle;
@@ -403,8 +408,9 @@ typedef struct {
  * each replay reads them again, so their values may change between
  * replays; their structure must not (a replay that detects a change
  * reports an error and produces nothing).  opts->tuning selects the bin
- * thresholds (zero: the handle's); validate and force_spill are not
- * supported.  Synchronises.
+ * thresholds (zero: the handle's) and opts->queue_rows the work queue of
+ * the numeric merge; validate and force_spill are not supported.
+ * Synchronises.
  */
 msp_status msp_batch_create(msp_handle* h, const msp_batch_csr* R, const msp_batch_csr* A,
                             const msp_batch_csr* P, const msp_opts* opts, msp_batch** plan);

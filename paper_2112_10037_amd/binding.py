@@ -60,7 +60,7 @@ class c_share_stats(ctypes.Structure):
 
 class c_opts(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("force_spill", ctypes.c_int32),
-                ("tuning", c_tuning)]
+                ("tuning", c_tuning), ("queue_rows", ctypes.c_int32)]
 
 
 class c_train_opts(ctypes.Structure):
@@ -236,9 +236,9 @@ class DeviceCSR:
                      self.val.data_ptr() if self.nnz else None, self.dtype_code)
 
 
-def _opts(validate=False, force_spill=False, tuning=None) -> c_opts:
+def _opts(validate=False, force_spill=False, tuning=None, queue_rows=0) -> c_opts:
     t = c_tuning(*(tuning or (0, 0, 0, 0, 0)))
-    return c_opts(int(bool(validate)), int(bool(force_spill)), t)
+    return c_opts(int(bool(validate)), int(bool(force_spill)), t, int(queue_rows))
 
 
 class Handle:
@@ -683,14 +683,16 @@ class Batch:
     """A planned batch C_p = A_p P_p, or C_p = R_p (A_p P_p) with R."""
 
     def __init__(self, handle: "Handle", A: PackedBatch, P: PackedBatch, R: PackedBatch | None = None,
-                 tuning=None):
+                 tuning=None, queue_rows: int = 0):
+        """queue_rows: rows per ticket of the numeric merge's shared work
+        queue (0: the library's 1024; -1: one static row range per wave)."""
         self.h = handle
         self._lib = handle._lib
         self._inputs = (A, P, R)                # the plan reads them on every replay
         ca, cp = A.c(), P.c()
         cr = R.c() if R is not None else None
         self._c = (ca, cp, cr)
-        o = _opts(False, False, tuning)
+        o = _opts(False, False, tuning, queue_rows)
         self._b = ctypes.c_void_p()
         _check(self._lib.msp_batch_create(handle._h, ctypes.byref(cr) if cr is not None else None,
                                           ctypes.byref(ca), ctypes.byref(cp), ctypes.byref(o),

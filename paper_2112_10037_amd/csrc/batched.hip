@@ -110,6 +110,7 @@ struct BatchStage {
     bool sym_fused = false;                     // replays: statistics and merge bin in one kernel
     int num_single = -1;                        // numeric bin that takes all rows in order
     DevBuf crp, cv, wsym, wnum;                 // row pointers, col+val arena, work items
+    DevBuf tick;                                // work-queue counter of each numeric bin
     long long nnz = 0, cap = 0;
     size_t voff = 0;                            // values start at cv + voff
 };
@@ -125,6 +126,7 @@ struct msp_batch {
     std::vector<int64_t> row_start;  // rows of each output problem (host)
     std::vector<int64_t> ncols;      // columns of each output problem (host)
     msp::DevBuf rp_local, bases, flag;
+    int queue_rows = 0;              // rows per ticket of the numeric merge's queue (0: static ranges)
     int64_t* hbases = nullptr;       // pinned
     int* hflag = nullptr;            // pinned
     bool pending = false;            // a replay whose flag has not been read
@@ -220,6 +222,7 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
         if ((s = S.crp.ensure((size_t)(M + 1) * 8)) != MSP_OK) return s;
         if ((s = S.wsym.ensure((kNB + 1) * 2 * 4)) != MSP_OK) return s;
         if ((s = S.wnum.ensure((kNB + 1) * 2 * 4)) != MSP_OK) return s;
+        if ((s = S.tick.ensure((kNB + 1) * 4)) != MSP_OK) return s;
         const int tiles = std::max(1, (M + kScanTile - 1) / kScanTile);
         if ((s = h->tiles.ensure((size_t)tiles * 8)) != MSP_OK) return s;
         if ((s = h->bsum.ensure((size_t)std::max((M + 255) / 256, 1) * 8)) != MSP_OK) return s;
@@ -333,13 +336,21 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
     k_bin_work<<<1, 64, 0, st>>>(&info->num_part[0][0], S.np.table.nb, S.num_planned, S.M, &info->nnz, S.cap,
                                  S.wnum.as<int>(), flag);
     if ((s = launch_ok("k_bin_work")) != MSP_OK) return s;
-    // 4. numeric pass into the arena
+    // 4. numeric pass into the arena; the merge bins' waves draw their rows
+    // from a shared work queue (one counter per bin, zeroed by a kernel)
     const int* wnum = S.wnum.as<int>();
     int32_t* ccol = S.cv.as<int32_t>();
     void* cval = (char*)S.cv.ptr + S.voff;
+    int* tick = b->queue_rows > 0 ? S.tick.as<int>() : nullptr;
+    if (tick) {
+        k_zero_words<<<1, 64, 0, st>>>(tick, kNB + 1);
+        if ((s = launch_ok("k_zero_words")) != MSP_OK) return s;
+    }
+    auto queue = [&](int bn) { return tick ? tick + bn : nullptr; };
     if (S.num_single >= 0) {
-        if ((s = launch_numeric_bin<true>(h, S.np.spec[S.num_single], Work{nullptr, M, wnum + 2 * kNB}, M, S.op,
-                                          S.crp.as<int64_t>(), ccol, cval, nullptr, S.mp)) != MSP_OK)
+        if ((s = launch_numeric_bin<true>(h, S.np.spec[S.num_single],
+                                          Work{nullptr, M, wnum + 2 * kNB, queue(S.num_single), b->queue_rows}, M,
+                                          S.op, S.crp.as<int64_t>(), ccol, cval, nullptr, S.mp)) != MSP_OK)
             return s;
     } else if (S.num_planned) {
         k_zero_words<<<1, 256, 0, st>>>(&info->cursor[0][0], kParts * kPartStride);
@@ -348,7 +359,8 @@ static msp_status run_stage(msp_batch* b, int si, bool eager) {
         if ((s = launch_ok("k_scatter")) != MSP_OK) return s;
         for (int bn = 1; bn <= S.np.table.nb; ++bn) {
             if (!((S.num_planned >> bn) & 1u)) continue;
-            if ((s = launch_numeric_bin<true>(h, S.np.spec[bn], Work{h->perm.as<int32_t>(), 0, wnum + 2 * bn},
+            if ((s = launch_numeric_bin<true>(h, S.np.spec[bn],
+                                              Work{h->perm.as<int32_t>(), 0, wnum + 2 * bn, queue(bn), b->queue_rows},
                                               S.num_rows[bn], S.op, S.crp.as<int64_t>(), ccol, cval, nullptr,
                                               S.mp)) != MSP_OK)
                 return s;
@@ -379,7 +391,8 @@ static void release_batch(msp_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (BatchStage& S : b->st)
-        for (DevBuf* d : {&S.tile_prob, &S.row_start, &S.boff, &S.ncols, &S.crp, &S.cv, &S.wsym, &S.wnum}) d->release();
+        for (DevBuf* d : {&S.tile_prob, &S.row_start, &S.boff, &S.ncols, &S.crp, &S.cv, &S.wsym, &S.wnum, &S.tick})
+            d->release();
     for (DevBuf* d : {&b->rp_local, &b->bases, &b->flag}) d->release();
     msp_handle* h = &b->inner;
     for (DevBuf* d : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod,
@@ -422,12 +435,16 @@ extern "C" msp_status msp_batch_create(msp_handle* h, const msp_batch_csr* R, co
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if (opts && opts->validate) return fail(MSP_ERR_INVALID_ARG, "validate is not supported for batches");
     if (opts && opts->force_spill) return fail(MSP_ERR_INVALID_ARG, "force_spill is not supported for batches");
+    const int qr = opts ? opts->queue_rows : 0;
+    if (qr != 0 && qr != -1 && (qr < 64 || qr > 65536 || qr % 64 != 0))
+        return fail(MSP_ERR_INVALID_ARG, "queue_rows must be 0, -1 or a multiple of 64 in 64..65536");
     msp_batch* b = new (std::nothrow) msp_batch();
     if (!b) return fail(MSP_ERR_OOM, "host allocation failed");
     b->device = h->device;
     b->dtype = A->dtype;
     b->nprob = A->nprob;
     b->nstage = R ? 2 : 1;
+    b->queue_rows = qr == 0 ? 1024 : (qr < 0 ? 0 : qr);
     msp_handle* in = &b->inner;
     in->device = h->device;
     in->alloc = h->alloc;

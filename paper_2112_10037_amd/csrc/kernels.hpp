@@ -774,6 +774,28 @@ __device__ __forceinline__ int wave_row_of(const WaveRows<RM>& wr, int nb, long 
 }
 
 // contiguous slot range of this wave (4 waves per workgroup)
+__device__ __forceinline__ void wave_range(long long n, long long* lo, long long* hi);
+
+// The rows [lo, hi) of the launch's n that a wave takes next.  Without a
+// ticket counter: one contiguous range per wave (wave_range), once.  With
+// one: blocks of wk.tk consecutive rows, drawn in turn from the counter that
+// every wave of the launch shares (a work queue: a wave that finishes early
+// takes more blocks); false once the rows run out.
+__device__ __forceinline__ bool wave_block(const Work& wk, long long n, bool first, long long* lo, long long* hi) {
+    if (!wk.ticket) {
+        if (!first) return false;
+        wave_range(n, lo, hi);
+        return true;
+    }
+    int t = 0;
+    if ((threadIdx.x & 63) == 0) t = atomicAdd(wk.ticket, 1);
+    t = __shfl(t, 0);
+    *lo = (long long)t * wk.tk;
+    if (*lo >= n) return false;
+    *hi = *lo + wk.tk < n ? *lo + wk.tk : n;
+    return true;
+}
+
 __device__ __forceinline__ void wave_range(long long n, long long* lo, long long* hi) {
     const long long nw = (long long)gridDim.x * 4;
     const long long wid = (long long)xcd_block() * 4 + (threadIdx.x >> 6);
@@ -1577,7 +1599,7 @@ k_num_merge(Work wk,
     // sharing figures of the wave's batches, added to the totals once at the end
     unsigned long long sh_batches = 0, sh_nnz = 0, sh_rows = 0;
     long long lo, hi;
-    wave_range(nrows_bin, &lo, &hi);
+    for (bool first = true; wave_block(wk, nrows_bin, first, &lo, &hi); first = false)
     for (long long pos = lo; pos < hi;) {
         const int ncand = (int)(hi - pos < 64 ? hi - pos : 64);
         int row = -1;

@@ -125,6 +125,8 @@ struct Work {
     const int32_t* perm;
     int n;
     const int* dev;
+    int* ticket;        // shared work queue of the launch (zero at launch), or null
+    int tk;             // rows per ticket
 };
 
 __device__ __forceinline__ void work_rows(const Work& w, int* n, const int32_t** perm) {

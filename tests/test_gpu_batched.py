@@ -244,3 +244,44 @@ def test_galerkin_512_full_batch_against_oracle(h):
         assert np.array_equal(got.row_ptr, ref[0]) and np.array_equal(got.col, ref[1]), (p, n)
         assert np.array_equal(got.val, ref[2]), (p, n)
     plan.close()
+
+
+def test_uneven_batch_work_queue(h):
+    """Problem sides 2..64 in one batch (8 to 262,144 rows each): the numeric
+    merge's waves draw row blocks from the shared work queue; every problem
+    is checked against the oracle, and the static split (one row range per
+    wave) and a small ticket give the same results bit for bit."""
+    rng = np.random.default_rng(17)
+    sides = [2, 64, 3, 5, 63, 2, 17, 40] + [int(x) for x in rng.integers(2, 65, 16)]
+    probs = [gen.galerkin_problem(n) for n in sides]
+    pA, pP, pR = (binding.PackedBatch.from_host([x[k] for x in probs]) for k in range(3))
+    plans = {q: binding.Batch(h, pA, pP, pR, queue_rows=q) for q in (0, -1, 64)}
+    for plan in plans.values():
+        plan.execute()
+    for i, (A, P, R) in enumerate(probs):
+        AP = oracle.spgemm(A, P)
+        ref = oracle.spgemm(R, _csr(AP, A.nrows, P.ncols))
+        got = plans[0].result(i).to_host()
+        oracle.compare(got.row_ptr, got.col, got.val, ref, TOL[np.dtype(np.float64)])
+        for q in (-1, 64):
+            other = plans[q].result(i).to_host()
+            assert np.array_equal(other.row_ptr, got.row_ptr) and np.array_equal(other.col, got.col)
+            assert np.array_equal(other.val, got.val)
+    for plan in plans.values():
+        plan.close()
+
+
+def test_work_queue_rows_validation(h):
+    probs = [gen.galerkin_problem(n) for n in (4, 5)]
+    pA, pP, pR = (binding.PackedBatch.from_host([x[k] for x in probs]) for k in range(3))
+    for bad in (32, 100, 65600, -2):
+        with pytest.raises(binding.MspError):
+            binding.Batch(h, pA, pP, pR, queue_rows=bad)
+    plan = binding.Batch(h, pA, pP, pR, queue_rows=65536)
+    plan.execute()
+    A, P, R = probs[1]
+    AP = oracle.spgemm(A, P)
+    ref = oracle.spgemm(R, _csr(AP, A.nrows, P.ncols))
+    got = plan.result(1).to_host()
+    assert np.array_equal(got.col, ref[1]) and np.array_equal(got.val, ref[2])
+    plan.close()
