@@ -48,7 +48,14 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors
 # read off a 1 GiB copy kernel), valid only for the kernel sources and the
 # tuning whose hash is given; any other state reports null.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch of the roofline kernel, from two rocprofv3 --pmc runs
+# (2 x FETCH_SIZE + WRITE_SIZE, the factors a 1 GiB device copy gives in the
+# same runs): profiles/rmat20_kernels.md.  Keyed by workload and tuning; a
+# figure is reported only while the kernel sources' code is the one measured.
+MEASURED_TRAFFIC = {
+    ("rmat20", (1, 0, 2048, 1024, 8)): {"bytes": 351210697728, "sources_sha256": "d8c792c97cfc7853e6fc5acc64f23fefc54f675da7b5d84911d52612b12ae781"},
+    ("rmat20", (1, 0, 1024, 1024, 8)): {"bytes": 352371464192, "sources_sha256": "05affb8dc93d30c0ab285d00e34c66a6fe23d9ede7673a0148ff933f5856343d"},
+}
 KERNEL_SOURCES = ["kernels.hpp", "types.hpp", "spgemm.hip", "msp_api.hip", "internal.hpp"]
 
 
@@ -751,7 +758,7 @@ def main():
         gb_s = gb_ms / gb_n / 1e3
         gbytes, grows = global_bin_bytes(A, row_nnz, int(tuning[2]))
         achieved = gbytes / gb_s / 1e9
-        key = MEASURED_TRAFFIC.get(args.workload)
+        key = MEASURED_TRAFFIC.get((args.workload, tuple(int(x) for x in tuning)))
         traffic = key["bytes"] if key and key["sources_sha256"] == kernel_sources_hash(tuning) else None
         roof = {"bound": "hbm", "kernel": "global bin, windowed numeric kernel (k_num_win)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

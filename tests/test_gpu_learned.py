@@ -261,3 +261,44 @@ def test_full_size_held_out_member_plain_and_learned(h, index):
     print(f"member {index} ({member.family}, {M.nrows} rows): nnz(C) = {got.nnz}, "
           f"overflow rows {st['overflow_rows']}, sum cap / nnz = {st['sum_cap'] / got.nnz:.3f}")
     pred.close()
+
+
+def _blocks(m, k, l, dtype=np.float64):
+    """m identical rows of k entries whose B rows (l entries each) hold
+    disjoint columns: prod = row nnz = k l = ncols(B), so the upper bound is
+    k l and the lower bound (largest B row) l."""
+    A = gen.CSR(m, k, np.arange(0, m * k + 1, k, dtype=np.int64), np.tile(np.arange(k, dtype=np.int32), m),
+                np.ones(m * k, dtype))
+    B = gen.CSR(k, k * l, np.arange(0, k * l + 1, l, dtype=np.int64), np.arange(k * l, dtype=np.int32),
+                np.ones(k * l, dtype))
+    return A, B
+
+
+# (k, l, point prediction, margin delta, expected capacity).  Numeric bins of
+# the tuning below: (32, 64], (64, 128], (128, 256], (256, 512], (512, 2048],
+# (2048, 4096], then the global bin.  Point predictions sit half-way between
+# integers, so the ceiling is the same however the FP32 network rounds.
+CAPACITY_CASES = [
+    (15, 100, 99.5, 0.5, 128),     # 100 * 2^0.5 = 141 is past (64, 128]: held at the bin's bound
+    (15, 100, 299.5, 0.0, 300),    # bound 1500: neither twice 300 nor in its bin
+    (15, 100, 599.5, 0.0, 1500),   # 600 and the bound 1500 share (512, 2048]: the bound
+    (11, 50, 299.5, 0.0, 550),     # bound 550 <= 2 * 300 (bins differ): the bound
+    (14, 50, 299.5, 0.0, 300),     # bound 700 > 2 * 300, bins differ: 300
+    (16, 500, 5999.5, 0.0, 0),     # 8000 (the bound, within 2x) is in the global bin: exact path
+]
+
+
+@pytest.mark.parametrize("k,l,pt,delta,expect", CAPACITY_CASES)
+def test_capacity_rule(h, k, l, pt, delta, expect):
+    """The capacity rule on rows with identical bounds, one case per clause."""
+    m = 300
+    A, B = _blocks(m, k, l)
+    pred = binding.Predictor(h, learned.fixed_capacity_params(np.log2(pt) / 16.0))
+    pred.set(None, delta)
+    C, st = h.spgemm_learned(pred, to_dev(A), to_dev(B), tuning=(1, 0, 4096, 1024, 8))
+    assert st["sum_cap"] == m * expect
+    assert st["exact_rows"] == (m if expect == 0 else 0)
+    assert st["overflow_rows"] == (m if 0 < expect < k * l else 0)
+    got = C.to_host()
+    oracle.compare(got.row_ptr, got.col, got.val, oracle.spgemm(A, B), TOL[np.dtype(np.float64)])
+    pred.close()
