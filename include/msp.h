@@ -281,7 +281,11 @@ typedef struct {
     int64_t sum_cap;         /* total predicted capacity (padded entries)   */
     int64_t nnz;             /* nnz(C)                                      */
     int64_t exact_rows;      /* rows whose capacity fell in the global bin,
-                                sent to the exact path without a padded try */
+                                sent to the exact path without a padded try;
+                                all rows (and sum_cap 0) when the upper
+                                bounds of those rows exceed the predicted
+                                rows' total capacity, in which case the whole
+                                product runs on the two-phase path          */
 } msp_learned_stats;
 
 /* Create on the handle's device from 4801 host floats (copied). */

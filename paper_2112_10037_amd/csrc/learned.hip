@@ -82,12 +82,13 @@ k_mlp_predict(long long n, const float* __restrict__ feats, const float* __restr
 __global__ void __launch_bounds__(256, 4)
 k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ hi, const int32_t* __restrict__ lo,
            const float* __restrict__ params, float delta, int32_t* __restrict__ cap, int32_t* __restrict__ cnt,
-           BinTable nt, int big, int* __restrict__ nbig) {
+           BinTable nt, int big, int* __restrict__ nbig, unsigned long long* __restrict__ big_hi) {
     __shared__ __align__(16) float w[kNParam + 3];
     for (int i = threadIdx.x; i < kNParam; i += 256) w[i] = params[i];
     __syncthreads();
     const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
     bool to_exact = false;
+    unsigned long long exact_hi = 0;
     if (r < m) {
         const int h = hi[r];
         const int l = lo[r] < h ? lo[r] : h;
@@ -120,12 +121,20 @@ k_capacity(int m, const float* __restrict__ feats, const int32_t* __restrict__ h
         // path (its per-window counts come from the symbolic pass there),
         // with no padded room here
         to_exact = big >= 0 && c > big;
-        if (to_exact) c = 0;
+        if (to_exact) {
+            c = 0;
+            exact_hi = (unsigned long long)h;
+        }
         cap[r] = c;
         if (c == 0) cnt[r] = to_exact ? -2 : 0;
     }
     const uint64_t bm = __ballot(to_exact);
-    if (bm && (threadIdx.x & 63) == __builtin_ctzll(bm)) atomicAdd(nbig, __builtin_popcountll(bm));
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) exact_hi += __shfl_xor(exact_hi, d);
+    if (bm && (threadIdx.x & 63) == __builtin_ctzll(bm)) {
+        atomicAdd(nbig, __builtin_popcountll(bm));
+        atomicAdd(big_hi, exact_hi);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -837,7 +846,8 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
         k_capacity<<<blocks, 256, 0, h->stream>>>(m, x->feat.as<float>(), h->u.as<int32_t>(), x->lo.as<int32_t>(),
                                                   p->params.as<float>(), p->delta, x->cap.as<int32_t>(),
                                                   x->cnt.as<int32_t>(), np.table, big,
-                                                  &h->info.as<DevInfo>()->learned_big);
+                                                  &h->info.as<DevInfo>()->learned_big,
+                                                  &h->info.as<DevInfo>()->learned_big_hi);
         if ((s = launch_check2("k_capacity")) != MSP_OK) return cleanup(s);
     }
     h->prof.end(h->stream);
@@ -850,6 +860,24 @@ extern "C" msp_status msp_spgemm_learned(msp_handle* h, const msp_predictor* p, 
     const long long sum_cap = h->hinfo->nnz;
     stats.sum_cap = sum_cap;
     stats.exact_rows = h->hinfo->learned_big;
+    if (stats.exact_rows > 0 && (long long)h->hinfo->learned_big_hi > sum_cap) {
+        // more of the bounded work is in rows that take the exact path anyway
+        // than in the predicted rows: the two-phase product of the whole
+        // matrix does less than the two paths together
+        msp_opts so;
+        memset(&so, 0, sizeof(so));
+        so.tuning = t;
+        s = spgemm_core(
+            h, A, B, C, &so, [h](size_t bytes) -> void* { return h->alloc(h->alloc_ctx, bytes, h->stream); },
+            [h](void* ptr) { h->free_fn(h->alloc_ctx, ptr, h->stream); });
+        if (s != MSP_OK) return cleanup(s);
+        stats.exact_rows = m;
+        stats.sum_cap = 0;
+        stats.overflow_rows = 0;
+        stats.nnz = C->nnz;
+        if (st) *st = stats;
+        return MSP_OK;
+    }
     int counts[kNB];
     sum_parts(h->hinfo->num_part, counts);
     // 4. numeric pass in capacity mode into the padded area

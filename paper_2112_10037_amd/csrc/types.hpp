@@ -54,7 +54,8 @@ struct DevInfo {
     long long share_nnz;                  // A entries of those batches' merge rows
     long long share_rows;                 // distinct B rows those batches staged
     unsigned long long omar_distinct;     // distinct (row group, column) pairs of A (Eq. 1)
-    int pad[12];
+    unsigned long long learned_big_hi;    // learned product: upper bounds of the rows sent to the exact path
+    int pad[10];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
