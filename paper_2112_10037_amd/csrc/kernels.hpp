@@ -2086,11 +2086,10 @@ k_num_group(Work wk,
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
     constexpr int NG = GroupCfg<G>::NG;
-    constexpr int CK = T / 2 + 4;                 // compacted keys, 16-byte rows
-    __shared__ int32_t keys[NG][T + 1];
+    // (rows of 16-byte multiples: the rank count reads four keys at a time;
+    // the occupied slots are compacted to the front of the table in place)
+    __shared__ __align__(16) int32_t keys[NG][T + 4];
     __shared__ double vals[NG][T + 1];
-    __shared__ __align__(16) int32_t ck[NG][CK];
-    __shared__ double cv[NG][T / 2 + 1];
     __shared__ long long s_off[NG][G + 1];
     __shared__ long long s_bst[NG][G + 1];
     __shared__ double s_a[NG][G + 1];
@@ -2141,17 +2140,21 @@ k_num_group(Work wk,
         }
         lds_fence();
     }
-    // compact the occupied slots
+    // compact the occupied slots to the front, in place: a slot moves to a
+    // position no later than its own, and the group reads its G slots before
+    // any of them is written
     int n = 0;
 #pragma unroll
     for (int s0 = 0; s0 < T; s0 += G) {
         const int s = s0 + gl;
         const int32_t k = kt[s];
+        const double v = vt[s];
         const bool occ = k != kEmpty;
         const uint64_t mask = group_ballot<G>(occ, lane);
         if (occ) {
             const int pos = n + __builtin_popcountll(mask & ((1ull << gl) - 1));
-            if (pos < T / 2) { ck[g][pos] = k; cv[g][pos] = vt[s]; }
+            kt[pos] = k;
+            vt[pos] = v;
         }
         n += __builtin_popcountll(mask);
     }
@@ -2168,17 +2171,17 @@ k_num_group(Work wk,
         continue;
     }
     const int n4 = (n + 3) & ~3;
-    if (gl < n4 - n) ck[g][n + gl] = 0x7fffffff;      // pads sort after every key
+    if (gl < n4 - n) kt[n + gl] = 0x7fffffff;         // pads sort after every key
     lds_fence();
     for (int e = gl; e < n; e += G) {
-        const int32_t k = ck[g][e];
+        const int32_t k = kt[e];
         int rank = 0;
         for (int f = 0; f < n4; f += 4) {
-            const int4 q = *reinterpret_cast<const int4*>(&ck[g][f]);
+            const int4 q = *reinterpret_cast<const int4*>(&kt[f]);
             rank += (q.x < k) + (q.y < k) + (q.z < k) + (q.w < k);
         }
         ccol[rp + rank] = k;
-        cval[rp + rank] = (VT)cv[g][e];
+        cval[rp + rank] = (VT)vt[e];
     }
     lds_fence();
     }
@@ -2186,8 +2189,10 @@ k_num_group(Work wk,
 }
 
 // Numeric, one workgroup per row: LDS hash of T (key, FP64) slots, then the
-// occupied slots are compacted to the front and bitonic-sorted by key in
-// LDS, and the row is written with coalesced stores.
+// occupied slots are compacted to the front and put in column order: rows of
+// at most kBlockRankMax outputs by counting each key's smaller keys, longer
+// rows by a bitonic sort in LDS and coalesced stores.
+constexpr int kBlockRankMax = 512;
 template <int BS, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
 k_num_block(Work wk,
@@ -2200,7 +2205,7 @@ k_num_block(Work wk,
     work_rows(wk, &nrows_bin, &perm);
     constexpr int PER = T / BS;    // slots per thread in the compaction
     static_assert(PER >= 1, "T must be >= BS");
-    __shared__ int32_t keys[T];
+    __shared__ __align__(16) int32_t keys[T];
     __shared__ double vals[T];
     __shared__ long long s_off[BS];
     __shared__ long long s_bst[BS];
@@ -2272,11 +2277,30 @@ k_num_block(Work wk,
         }
         int P = 1;
         while (P < n) P <<= 1;
+        // pad to the sort's power of two, and to the rank count's four
+        // (both within T: n <= T / 2)
         if (!bad)
-            for (int s = (int)n + tid; s < P; s += BS) keys[s] = 0x7fffffff;   // pad: sorts last
+            for (int s = (int)n + tid; s < (P < 4 ? 4 : P); s += BS) keys[s] = 0x7fffffff;   // sorts last
         __syncthreads();
         if (bad) {
             if (tid == 0 && !cnt_out) atomicOr(&info->err, failed ? kErrProbe : kErrCount);
+            continue;
+        }
+        if (n <= kBlockRankMax) {
+            // a short row: each key's rank is the number of smaller keys
+            // (one pass over the padded keys, no barrier between stages)
+            const int n4 = ((int)n + 3) & ~3;
+            for (int e = tid; e < n; e += BS) {
+                const int32_t k = keys[e];
+                int rank = 0;
+                for (int f = 0; f < n4; f += 4) {
+                    const int4 q = *reinterpret_cast<const int4*>(&keys[f]);
+                    rank += (q.x < k) + (q.y < k) + (q.z < k) + (q.w < k);
+                }
+                ccol[rp + rank] = k;
+                cval[rp + rank] = (VT)vals[e];
+            }
+            __syncthreads();
             continue;
         }
         // bitonic sort of keys[0..P) ascending, values follow
