@@ -261,7 +261,8 @@ __device__ __forceinline__ void wave_hist_add_w(int* hist, int b, int w) {
 // One wave per 64 consecutive rows.  The wave walks the A entries of its
 // rows flattened (lane = entry), so a row's B-row lengths are gathered in
 // parallel; each entry finds its row by binary search in the 65 row
-// pointers held in LDS and adds into the row's LDS accumulator.
+// pointers held in LDS and adds into the row's LDS accumulator (after a
+// reduction across the wave when the step's entries are all of one row).
 // Outputs: u_i = min(prod_i, ncols(B)) (int32), optional int64 prod_i and
 // FP32 features, row_nnz_i = 0 for rows with u_i = 0, and the bin
 // histogram of u_i (partitioned global counters).
@@ -301,24 +302,92 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     }
     __syncthreads();
     if (nr > 0) {
+        // RU entries per lane have their loads in flight together; a step
+        // whose active lanes all belong to one row (a long row) is reduced
+        // across the wave first, so its accumulators take one atomic each
+        // instead of 64 on one address
+        constexpr int RU = 4;
         const long long e0 = s_rp[w][0], e1 = s_rp[w][nr];
-        for (long long p = e0 + lane; p < e1; p += 64) {
-            // last row r with s_rp[r] <= p (skips empty rows)
-            int lo = 0, hi = nr;           // s_rp[lo] <= p < s_rp[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_rp[w][mid] <= p) lo = mid; else hi = mid;
+        for (long long pb = e0; pb < e1; pb += 64 * RU) {      // wave-uniform
+            int rw[RU];
+            long long b0[RU], b1[RU];
+            int c0[RU], c1[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const long long p = pb + u * 64 + lane;
+                rw[u] = -1;
+                b0[u] = b1[u] = 0;
+                if (p < e1) {
+                    // last row r with s_rp[r] <= p (skips empty rows)
+                    int lo = 0, hi = nr;       // s_rp[lo] <= p < s_rp[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_rp[w][mid] <= p) lo = mid; else hi = mid;
+                    }
+                    rw[u] = lo;
+                    b0[u] = (long long)acol[p] + (BATCH ? s_bo[w][lo] : 0);   // the B row, for now
+                }
             }
-            const long long k = (long long)acol[p] + (BATCH ? s_bo[w][lo] : 0);
-            const long long b0 = brp[k], b1 = brp[k + 1];
-            const long long l = b1 - b0;
-            atomicAdd(&s_prod[w][lo], (unsigned long long)l);
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                if (rw[u] >= 0) {
+                    const long long k = b0[u];
+                    b0[u] = brp[k];
+                    b1[u] = brp[k + 1];
+                }
             if constexpr (FEAT) {
-                atomicMin(&s_mn[w][lo], (int)l);
-                atomicMax(&s_mx[w][lo], (int)l);
-                if (l > 0) {
-                    atomicMin(&s_lo[w][lo], bcol[b0]);
-                    atomicMax(&s_hi[w][lo], bcol[b1 - 1]);
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    c0[u] = 0x7fffffff;
+                    c1[u] = -1;
+                    if (rw[u] >= 0 && b1[u] > b0[u]) {
+                        c0[u] = bcol[b0[u]];
+                        c1[u] = bcol[b1[u] - 1];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const bool ok = rw[u] >= 0;
+                const long long l = b1[u] - b0[u];
+                const int r0l = __shfl(rw[u], 0);
+                const uint64_t act = __ballot(ok);
+                if (act && __ballot(ok && rw[u] == r0l) == act) {       // one row: reduce first
+                    unsigned long long sl = ok ? (unsigned long long)l : 0ull;
+                    int mn = ok ? (int)l : 0x7fffffff, mx = ok ? (int)l : 0;
+                    int lo = FEAT ? c0[u] : 0, hi = FEAT ? c1[u] : 0;
+#pragma unroll
+                    for (int d = 32; d > 0; d >>= 1) {
+                        sl += __shfl_xor(sl, d);
+                        if constexpr (FEAT) {
+                            mn = min(mn, __shfl_xor(mn, d));
+                            mx = max(mx, __shfl_xor(mx, d));
+                            lo = min(lo, __shfl_xor(lo, d));
+                            hi = max(hi, __shfl_xor(hi, d));
+                        }
+                    }
+                    if (lane == 0) {
+                        atomicAdd(&s_prod[w][r0l], sl);
+                        if constexpr (FEAT) {
+                            atomicMin(&s_mn[w][r0l], mn);
+                            atomicMax(&s_mx[w][r0l], mx);
+                            if (hi >= 0) {
+                                atomicMin(&s_lo[w][r0l], lo);
+                                atomicMax(&s_hi[w][r0l], hi);
+                            }
+                        }
+                    }
+                } else if (ok) {
+                    const int lo = rw[u];
+                    atomicAdd(&s_prod[w][lo], (unsigned long long)l);
+                    if constexpr (FEAT) {
+                        atomicMin(&s_mn[w][lo], (int)l);
+                        atomicMax(&s_mx[w][lo], (int)l);
+                        if (l > 0) {
+                            atomicMin(&s_lo[w][lo], c0[u]);
+                            atomicMax(&s_hi[w][lo], c1[u]);
+                        }
+                    }
                 }
             }
         }

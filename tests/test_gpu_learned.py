@@ -173,9 +173,20 @@ def test_trained_network_gains_over_no_network(h):
     assert cap_tr < cap_up
     assert ovf <= 0.05 * rows
     # timed, at full size, on a held-out 27-point member (side 80, 512,000
-    # rows): the trained capacities keep its rows in their accumulator bins
+    # rows), with a network trained on full-size 27-point training members
+    # (the features of scaled-down members differ in their column-count
+    # terms): the trained capacities keep its rows in their accumulator bins
     # where the network-free bound moves them to far larger tables
     import time
+    fam = [m for m in suite if not m.held_out and m.family == "stencil27"][:3]
+    fprods = []
+    for Mf in fam:
+        dF = to_dev(Mf.build())
+        fprods.append((dF, dF))
+    ffeats, ftargets = learned.training_set(h, fprods)
+    del fprods
+    pred.close()
+    pred, _, _ = learned.train(h, ffeats, ftargets, steps=600, batch=4096, seed=5)
     M = next(m for m in suite if m.index == 59).build()
     dM = to_dev(M)
 
