@@ -114,6 +114,8 @@ struct msp_handle {
     // per-window row counts, B's window index, and the rows left to the
     // self-counting kernel
     msp::DevBuf win_islot, win_row, win_cnt, win_bslot, win_wpos, win_fb, win_rbm, win_bms;
+    // row statistics: the rows with more than kLongRow A entries and their chunks
+    msp::DevBuf lr_list, lr_base, lr_chunk, lr_acc;
     size_t total_mem = 0;           // device memory (bounds the bitmap store)
     void* scratch = nullptr;        // device address of this device's no-allocation scratch
     msp::WinRec cur_rec{};          // records of the product in progress (cnt null: none)

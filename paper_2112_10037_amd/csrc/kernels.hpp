@@ -266,18 +266,40 @@ __device__ __forceinline__ void wave_hist_add_w(int* hist, int b, int w) {
 // Outputs: u_i = min(prod_i, ncols(B)) (int32), optional int64 prod_i and
 // FP32 features, row_nnz_i = 0 for rows with u_i = 0, and the bin
 // histogram of u_i (partitioned global counters).
+// The eight predictor inputs of a row from its statistics: A entries len,
+// products s, shortest / longest B row mn / mx, and the column span hi - lo
+// (hi < 0: no nonempty B row).
+__device__ __forceinline__ void write_features(float* __restrict__ f, long long len, long long s, int mn, int mx,
+                                               int lo, int hi, long long ncols) {
+    const double n = (double)(ncols > 0 ? ncols : 1);
+    const float mean = len > 0 ? (float)((double)s / (double)len) : 0.f;
+    f[0] = log2f(1.f + (float)len) * kFeatLogScale;
+    f[1] = log2f(1.f + (float)s) * kFeatLogScale;
+    f[2] = log2f(1.f + (float)(len > 0 ? mn : 0)) * kFeatLogScale;
+    f[3] = log2f(1.f + mean) * kFeatLogScale;
+    f[4] = log2f(1.f + (float)mx) * kFeatLogScale;
+    f[5] = log2f(1.f + (float)ncols) * kFeatLogScale;
+    f[6] = fminf(1.f, (float)((double)s / n));
+    f[7] = (float)((double)(hi < 0 ? 0 : hi - lo) / n);
+}
+
+// Rows with more than kLongRow A entries (single products, when lr.list is
+// set) are left out of the wave's walk: each is listed with a contiguous
+// range of kLongChunk-entry chunks for k_row_stats_long, and
+// k_row_stats_long_fin writes its outputs.
 template <bool FEAT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             int32_t* __restrict__ u_out, int64_t* __restrict__ prod_out,
             int32_t* __restrict__ row_nnz, BinTable bins, DevInfo* info,
-            float* __restrict__ feat, int32_t* __restrict__ lo_out, RowMap mp) {
+            float* __restrict__ feat, int32_t* __restrict__ lo_out, RowMap mp, LongRows lr = LongRows{}) {
     static_assert(!(FEAT && BATCH), "features are computed for single products");
     __shared__ int hist[kNB];
     __shared__ long long s_bo[BATCH ? 4 : 1][64];   // batched: B-row offset and width of each row
     __shared__ long long s_nc[BATCH ? 4 : 1][64];
     __shared__ long long s_rp[4][65];
+    __shared__ long long s_cp[4][65];               // prefix of the walked entries (long rows count 0)
     __shared__ unsigned long long s_prod[4][64];
     __shared__ int s_mn[FEAT ? 4 : 1][64], s_mx[FEAT ? 4 : 1][64];
     __shared__ int s_lo[FEAT ? 4 : 1][64], s_hi[FEAT ? 4 : 1][64];
@@ -301,30 +323,52 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
         s_mn[w][lane] = 0x7fffffff; s_mx[w][lane] = 0; s_lo[w][lane] = 0x7fffffff; s_hi[w][lane] = -1;
     }
     __syncthreads();
+    bool longr = false;
     if (nr > 0) {
+        // the walked entries: every row's, except the long rows when they are
+        // taken apart
+        const long long len = lane < nr ? s_rp[w][lane + 1] - s_rp[w][lane] : 0;
+        longr = !BATCH && lr.list && len > kLongRow;
+        const long long cinc = group_incl_scan<64>(longr ? 0 : len, lane);
+        s_cp[w][lane + 1] = cinc;
+        if (lane == 0) s_cp[w][0] = 0;
+        if (longr) {
+            const int idx = atomicAdd(&info->long_n, 1);
+            if (idx < lr.list_cap) {               // (the host sizes the lists for every long row)
+                const int nch = (int)((len + kLongChunk - 1) / kLongChunk);
+                const int b = atomicAdd(&info->long_chunks, nch);
+                lr.list[idx] = (int)(r0 + lane);
+                lr.base[idx] = b;
+                lr.acc[idx] = LongAcc{0ull, 0x7fffffff, 0, 0x7fffffff, -1};
+                for (int c = 0; c < nch; ++c)
+                    if (b + c < lr.chunk_cap) lr.chunk_row[b + c] = idx;
+            }
+        }
+        lds_fence();
         // RU entries per lane have their loads in flight together; a step
-        // whose active lanes all belong to one row (a long row) is reduced
-        // across the wave first, so its accumulators take one atomic each
-        // instead of 64 on one address
+        // whose active lanes all belong to one row is reduced across the wave
+        // first, so its accumulators take one atomic each instead of 64 on
+        // one address
         constexpr int RU = 4;
-        const long long e0 = s_rp[w][0], e1 = s_rp[w][nr];
-        for (long long pb = e0; pb < e1; pb += 64 * RU) {      // wave-uniform
+        const long long ew = s_cp[w][nr];
+        for (long long pb = 0; pb < ew; pb += 64 * RU) {       // wave-uniform
             int rw[RU];
             long long b0[RU], b1[RU];
             int c0[RU], c1[RU];
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
-                const long long p = pb + u * 64 + lane;
+                const long long pc = pb + u * 64 + lane;
                 rw[u] = -1;
                 b0[u] = b1[u] = 0;
-                if (p < e1) {
-                    // last row r with s_rp[r] <= p (skips empty rows)
-                    int lo = 0, hi = nr;       // s_rp[lo] <= p < s_rp[hi]
+                if (pc < ew) {
+                    // last row r with s_cp[r] <= pc (skips empty and long rows)
+                    int lo = 0, hi = nr;       // s_cp[lo] <= pc < s_cp[hi]
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
-                        if (s_rp[w][mid] <= p) lo = mid; else hi = mid;
+                        if (s_cp[w][mid] <= pc) lo = mid; else hi = mid;
                     }
                     rw[u] = lo;
+                    const long long p = s_rp[w][lo] + (pc - s_cp[w][lo]);
                     b0[u] = (long long)acol[p] + (BATCH ? s_bo[w][lo] : 0);   // the B row, for now
                 }
             }
@@ -394,7 +438,7 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     }
     __syncthreads();
     const long long row = r0 + lane;
-    const bool valid = lane < nr;
+    const bool valid = lane < nr && !longr;        // (a long row's outputs come later)
     int bin = -1;
     if (valid) {
         const long long s = (long long)s_prod[w][lane];
@@ -406,19 +450,8 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
         bin = bin_of(bins, u);
         if constexpr (FEAT) {
             const long long len = s_rp[w][lane + 1] - s_rp[w][lane];
-            const int mn = len > 0 ? s_mn[w][lane] : 0, mx = s_mx[w][lane];
-            const int lo = s_lo[w][lane], hi = s_hi[w][lane];
-            const double n = (double)(ncols > 0 ? ncols : 1);
-            const float mean = len > 0 ? (float)((double)s / (double)len) : 0.f;
-            float* f = feat + row * 8;
-            f[0] = log2f(1.f + (float)len) * kFeatLogScale;
-            f[1] = log2f(1.f + (float)s) * kFeatLogScale;
-            f[2] = log2f(1.f + (float)mn) * kFeatLogScale;
-            f[3] = log2f(1.f + mean) * kFeatLogScale;
-            f[4] = log2f(1.f + (float)mx) * kFeatLogScale;
-            f[5] = log2f(1.f + (float)ncols) * kFeatLogScale;
-            f[6] = fminf(1.f, (float)((double)s / n));
-            f[7] = (float)((double)(hi < 0 ? 0 : hi - lo) / n);
+            const int mx = s_mx[w][lane];
+            write_features(feat + row * 8, len, s, s_mn[w][lane], mx, s_lo[w][lane], s_hi[w][lane], ncols);
             if (lo_out) lo_out[row] = mx;
         }
     }
@@ -426,6 +459,113 @@ k_row_stats(int m, long long ncols, const int64_t* __restrict__ arp, const int32
     __syncthreads();
     if (bins.nb > 0 && threadIdx.x < kNB && hist[threadIdx.x])
         atomicAdd(&info->sym_part[blockIdx.x % kParts][threadIdx.x], hist[threadIdx.x]);
+}
+
+// Chunks of the long rows: one workgroup per chunk of kLongChunk entries
+// (eight per thread, their loads in flight together), reduced in the
+// workgroup, then one global atomic per statistic into the row's LongAcc.
+template <bool FEAT>
+__global__ void __launch_bounds__(256)
+k_row_stats_long(const DevInfo* __restrict__ info, const int64_t* __restrict__ arp,
+                 const int32_t* __restrict__ acol, const int64_t* __restrict__ brp,
+                 const int32_t* __restrict__ bcol, LongRows lr) {
+    __shared__ unsigned long long r_s[4];
+    __shared__ int r_mn[4], r_mx[4], r_lo[4], r_hi[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nch = min(__hip_atomic_load(&info->long_chunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        lr.chunk_cap);
+    constexpr int PT = kLongChunk / 256;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int idx = lr.chunk_row[c];
+        const int row = lr.list[idx];
+        const long long a0 = arp[row] + (long long)(c - lr.base[idx]) * kLongChunk;
+        const long long a1 = min(arp[row + 1], a0 + kLongChunk);
+        long long k[PT], b0[PT], b1[PT];
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const long long p = a0 + j * 256 + threadIdx.x;
+            k[j] = p < a1 ? (long long)acol[p] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            b0[j] = b1[j] = 0;
+            if (k[j] >= 0) {
+                b0[j] = brp[k[j]];
+                b1[j] = brp[k[j] + 1];
+            }
+        }
+        unsigned long long sl = 0;
+        int mn = 0x7fffffff, mx = 0, lo = 0x7fffffff, hi = -1;
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            if (k[j] < 0) continue;
+            const long long l = b1[j] - b0[j];
+            sl += (unsigned long long)l;
+            if constexpr (FEAT) {
+                mn = min(mn, (int)l);
+                mx = max(mx, (int)l);
+                if (l > 0) {
+                    lo = min(lo, bcol[b0[j]]);
+                    hi = max(hi, bcol[b1[j] - 1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            sl += __shfl_xor(sl, d);
+            if constexpr (FEAT) {
+                mn = min(mn, __shfl_xor(mn, d));
+                mx = max(mx, __shfl_xor(mx, d));
+                lo = min(lo, __shfl_xor(lo, d));
+                hi = max(hi, __shfl_xor(hi, d));
+            }
+        }
+        if (lane == 0) { r_s[w] = sl; r_mn[w] = mn; r_mx[w] = mx; r_lo[w] = lo; r_hi[w] = hi; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int v = 1; v < 4; ++v) {
+                sl += r_s[v];
+                mn = min(mn, r_mn[v]); mx = max(mx, r_mx[v]);
+                lo = min(lo, r_lo[v]); hi = max(hi, r_hi[v]);
+            }
+            LongAcc* a = &lr.acc[idx];
+            atomicAdd(&a->prod, sl);
+            if constexpr (FEAT) {
+                atomicMin(&a->mn, mn);
+                atomicMax(&a->mx, mx);
+                if (hi >= 0) {
+                    atomicMin(&a->lo, lo);
+                    atomicMax(&a->hi, hi);
+                }
+            }
+        }
+        __syncthreads();                          // r_* are reused by the next chunk
+    }
+}
+
+// Outputs of the long rows (as k_row_stats writes them for the others); the
+// bin counts go to the partition of the row's 256-row block, as the scatter
+// expects.
+template <bool FEAT>
+__global__ void __launch_bounds__(256)
+k_row_stats_long_fin(DevInfo* info, long long ncols, const int64_t* __restrict__ arp, LongRows lr,
+                     int32_t* __restrict__ u_out, int64_t* __restrict__ prod_out, int32_t* __restrict__ row_nnz,
+                     BinTable bins, float* __restrict__ feat, int32_t* __restrict__ lo_out) {
+    const int nl = min(__hip_atomic_load(&info->long_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), lr.list_cap);
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nl; idx += gridDim.x * blockDim.x) {
+        const int row = lr.list[idx];
+        const LongAcc a = lr.acc[idx];
+        const long long s = (long long)a.prod;
+        const long long u = s < ncols ? s : ncols;
+        u_out[row] = (int32_t)u;
+        if (prod_out) prod_out[row] = s;
+        if (u == 0 && row_nnz) row_nnz[row] = 0;          // every B row it selects is empty
+        if (bins.nb > 0) atomicAdd(&info->sym_part[(row / 256) % kParts][bin_of(bins, u)], 1);
+        if constexpr (FEAT) {
+            write_features(feat + (long long)row * 8, arp[row + 1] - arp[row], s, a.mn, a.mx, a.lo, a.hi, ncols);
+            if (lo_out) lo_out[row] = a.mx;
+        }
+    }
 }
 
 // ===========================================================================

@@ -210,7 +210,8 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
     for (DevBuf* b : {&h->info, &h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod,
                       &h->bsum, &h->gsl, &h->win_islot, &h->win_row, &h->win_cnt, &h->win_bslot,
-                      &h->win_wpos, &h->win_fb, &h->win_rbm, &h->win_bms})
+                      &h->win_wpos, &h->win_fb, &h->win_rbm, &h->win_bms,
+                      &h->lr_list, &h->lr_base, &h->lr_chunk, &h->lr_acc})
         b->release();
     release_extra(h);
     h->prof.release();

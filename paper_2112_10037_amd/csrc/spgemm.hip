@@ -617,15 +617,46 @@ msp_status run_row_stats(msp_handle* h, const msp_csr* A, const msp_csr* B, cons
     if (s != MSP_OK) return s;
     if (m == 0) return MSP_OK;
     const int grid = (m + 255) / 256;
+    // lists of the rows with more than kLongRow A entries (every such row
+    // fits: at most nnz / (kLongRow + 1) rows, nnz / kLongChunk + rows chunks)
+    LongRows lr;
+    if (A->nnz > kLongRow) {
+        const long long nl = A->nnz / (kLongRow + 1) + 1;
+        const long long nc = A->nnz / kLongChunk + nl + 1;
+        if (nl > INT32_MAX || nc > INT32_MAX) return fail(MSP_ERR_INDEX_OVERFLOW, "too many long rows");
+        if ((s = h->lr_list.ensure((size_t)nl * 4)) != MSP_OK || (s = h->lr_base.ensure((size_t)nl * 4)) != MSP_OK ||
+            (s = h->lr_chunk.ensure((size_t)nc * 4)) != MSP_OK ||
+            (s = h->lr_acc.ensure((size_t)nl * sizeof(LongAcc))) != MSP_OK)
+            return s;
+        lr = LongRows{h->lr_list.as<int>(), h->lr_base.as<int>(), h->lr_chunk.as<int>(), h->lr_acc.as<LongAcc>(),
+                      (int)nl, (int)nc};
+    }
+    DevInfo* info = h->info.as<DevInfo>();
     if (feat)
         k_row_stats<true><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                       h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
-                                                      plan.table, h->info.as<DevInfo>(), feat, lo_out, RowMap{});
+                                                      plan.table, info, feat, lo_out, RowMap{}, lr);
     else
         k_row_stats<false><<<grid, 256, 0, h->stream>>>(m, B->ncols, A->row_ptr, A->col, B->row_ptr, B->col,
                                                        h->u.as<int32_t>(), prod_out, h->rnnz.as<int32_t>(),
-                                                       plan.table, h->info.as<DevInfo>(), nullptr, nullptr, RowMap{});
+                                                       plan.table, info, nullptr, nullptr, RowMap{}, lr);
     msp_status s2 = launch_check("k_row_stats");
+    if (s2 == MSP_OK && lr.list) {
+        // (both kernels read their counts on the device; with no long row they end at once)
+        const int gl = 4 * h->num_cu;
+        if (feat) {
+            k_row_stats_long<true><<<gl, 256, 0, h->stream>>>(info, A->row_ptr, A->col, B->row_ptr, B->col, lr);
+            k_row_stats_long_fin<true><<<4, 256, 0, h->stream>>>(info, B->ncols, A->row_ptr, lr, h->u.as<int32_t>(),
+                                                                 prod_out, h->rnnz.as<int32_t>(), plan.table, feat,
+                                                                 lo_out);
+        } else {
+            k_row_stats_long<false><<<gl, 256, 0, h->stream>>>(info, A->row_ptr, A->col, B->row_ptr, B->col, lr);
+            k_row_stats_long_fin<false><<<4, 256, 0, h->stream>>>(info, B->ncols, A->row_ptr, lr, h->u.as<int32_t>(),
+                                                                  prod_out, h->rnnz.as<int32_t>(), plan.table, nullptr,
+                                                                  nullptr);
+        }
+        s2 = launch_check("k_row_stats_long");
+    }
     if (s2 != MSP_OK || !publish_seq) return s2;
     k_publish<<<1, 64, 0, h->stream>>>(h->info.as<DevInfo>(), 0, plan.table.nb, h->dsum, publish_seq);
     return launch_check("k_publish");

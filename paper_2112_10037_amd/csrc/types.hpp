@@ -39,6 +39,25 @@ constexpr int kSupers = 1024;
 
 constexpr long long kOmarMaxGroup = 4096;   // largest row group of the sharing count
 
+// Row statistics of rows with more than kLongRow A entries are taken apart:
+// chunks of kLongChunk entries go to whole workgroups, which add into the
+// row's LongAcc with global atomics (one wave walking such a row alone would
+// set the kernel's time).
+constexpr int kLongRow = 4096;
+constexpr int kLongChunk = 2048;
+struct LongAcc {
+    unsigned long long prod;              // sum of the B-row lengths
+    int mn, mx;                           // shortest and longest B row
+    int lo, hi;                           // smallest first and largest last column
+};
+struct LongRows {                         // work lists of the long rows (list == nullptr: not taken apart)
+    int* list = nullptr;                  // row of each long row
+    int* base = nullptr;                  // its first chunk
+    int* chunk_row = nullptr;             // long row (index into list) of each chunk
+    LongAcc* acc = nullptr;               // statistics of each long row
+    int list_cap = 0, chunk_cap = 0;
+};
+
 struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
     int err;                              // error bits of the current call
@@ -55,7 +74,9 @@ struct DevInfo {
     long long share_rows;                 // distinct B rows those batches staged
     unsigned long long omar_distinct;     // distinct (row group, column) pairs of A (Eq. 1)
     unsigned long long learned_big_hi;    // learned product: upper bounds of the rows sent to the exact path
-    int pad[10];
+    int long_n;                           // row statistics: rows taken apart as long rows
+    int long_chunks;                      // and their chunks
+    int pad[8];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
