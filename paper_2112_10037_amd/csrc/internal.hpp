@@ -138,6 +138,10 @@ namespace msp {
 // workspace growth or memset then is an internal error instead of a
 // silently recorded graph node.
 extern thread_local bool g_capturing;
+// Set during the allocation-free product: a workspace that was not moved
+// into the scratch array and would grow is then an internal error instead
+// of a hidden hipMalloc.
+extern thread_local bool g_noalloc;
 
 msp_status fail(msp_status s, const char* fmt, ...);
 msp_status hip_fail(hipError_t e, const char* what);

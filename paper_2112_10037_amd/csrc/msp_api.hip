@@ -59,6 +59,7 @@ extern "C" int msp_version(void) { return 1; }
 namespace msp {
 
 thread_local bool g_capturing = false;
+thread_local bool g_noalloc = false;
 
 msp_status DevBuf::ensure(size_t need) {
     if (need <= bytes) return MSP_OK;
@@ -75,6 +76,7 @@ msp_status DevBuf::ensure(size_t need) {
         return MSP_OK;
     }
     if (g_capturing) return fail(MSP_ERR_HIP, "internal: workspace growth during graph capture");
+    if (g_noalloc) return fail(MSP_ERR_HIP, "internal: workspace growth in the allocation-free product");
     if (ptr) {
         hipError_t e = hipFree(ptr);
         ptr = nullptr;

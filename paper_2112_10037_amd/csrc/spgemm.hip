@@ -1202,7 +1202,7 @@ extern "C" msp_status msp_spgemm_noalloc(msp_handle* h, const msp_csr* A, const 
     ar.size = MSP_NOALLOC_SCRATCH_BYTES;
     DevBuf* bufs[] = {&h->u, &h->rnnz, &h->perm, &h->tiles, &h->sbm, &h->prod, &h->bsum, &h->gsl,
                       &h->win_islot, &h->win_row, &h->win_cnt, &h->win_bslot, &h->win_wpos, &h->win_fb,
-                      &h->win_rbm, &h->win_bms};
+                      &h->win_rbm, &h->win_bms, &h->lr_list, &h->lr_base, &h->lr_chunk, &h->lr_acc};
     constexpr int nb = sizeof(bufs) / sizeof(bufs[0]);
     DevBuf saved[nb];
     for (int i = 0; i < nb; ++i) {
@@ -1212,9 +1212,11 @@ extern "C" msp_status msp_spgemm_noalloc(msp_handle* h, const msp_csr* A, const 
     }
     const bool prof_on = h->prof.on;
     h->prof.on = false;
+    g_noalloc = true;
     CPlace place{C->col, C->val, capacity};
     s = spgemm_core(
         h, A, B, C, opts, [](size_t) -> void* { return nullptr; }, [](void*) {}, &place);
+    g_noalloc = false;
     h->prof.on = prof_on;
     for (int i = 0; i < nb; ++i) *bufs[i] = saved[i];
     C->col = place.col;                 // the caller's buffers, whatever happened

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_2112_10037_amd import binding, gen
 
-from gpu_util import TOL, check_full, check_rows, run, to_dev
+from gpu_util import TOL, check_full, check_rows, long_rows_case, run, to_dev
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -496,38 +496,12 @@ def test_table4_standins(h, index):
     print(f"{name}: max |c-o|/bound = {err:.3e}")
 
 
-def _long_rows_case(dtype=np.float64):
-    """1,000 rows of A over 30,000 columns: most with 0..8 entries, rows 5
-    and 77 with 20,000, row 640 with 6,000, and row 300 with 5,000 entries
-    that select only empty B rows (B rows 25,000 on are empty)."""
-    rng = np.random.default_rng(71)
-    m, k, n = 1000, 30_000, 2000
-    rows = []
-    for i in range(m):
-        if i in (5, 77):
-            c = rng.choice(k, 20_000, replace=False)
-        elif i == 640:
-            c = rng.choice(k, 6_000, replace=False)
-        elif i == 300:
-            c = 25_000 + rng.choice(5_000, 5_000, replace=False)
-        else:
-            c = rng.choice(k, int(rng.integers(0, 9)), replace=False)
-        rows.append(np.sort(c))
-    rp = np.zeros(m + 1, np.int64)
-    rp[1:] = np.cumsum([len(r) for r in rows])
-    A = gen.CSR(m, k, rp, np.concatenate(rows).astype(np.int32), rng.uniform(-1, 1, int(rp[-1])).astype(dtype))
-    kb = rng.integers(0, 6, k)
-    kb[25_000:] = 0
-    B = gen.erdos_renyi(k, n, kb, seed=72, dtype=dtype)
-    return A, B
-
-
 def test_long_rows_statistics_and_products(h):
     """Rows with more than 4,096 A entries are taken apart by the statistics
     pass (chunks over whole workgroups); products, features, the plain
     product through that pass (no merge bin) and the one-pass product must
     all match the oracle."""
-    A, B = _long_rows_case()
+    A, B = long_rows_case()
     dA, dB = to_dev(A), to_dev(B)
     prod, feat = h.row_features(dA, dB)
     st = oracle.row_stats(A, B)

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2112_10037_amd import binding, gen
 
-from gpu_util import TOL, to_dev
+from gpu_util import TOL, long_rows_case, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,29 @@ def test_noalloc_matches_plain_twice():
         _check_against_plain(h, small, B)
     finally:
         h.close()
+
+
+def test_noalloc_first_call_on_fresh_handle():
+    """The allocation-free product as a fresh handle's first call, on rows
+    with more than 4,096 A entries (the statistics pass's long-row lists)
+    and on a skewed matrix: every workspace it touches must come from the
+    scratch array, since the library refuses any other workspace growth
+    during this call as an internal error.  Then the plain product, and the
+    allocation-free one again on a smaller input."""
+    for A, B in (long_rows_case(), (gen.rmat(12, 16 << 12, seed=57),) * 2):
+        h = binding.Handle(0)
+        try:
+            o = oracle.spgemm(A, B)
+            st, out, rp, col, val = _noalloc(h, A, B, int(o[0][-1]))
+            assert binding.STATUS[st] == "MSP_OK", h._lib.msp_last_error()
+            n = int(out.nnz)
+            oracle.compare(rp.cpu().numpy(), col[:n].cpu().numpy(), val[:n].cpu().numpy(), o,
+                           TOL[np.dtype(A.val.dtype)])
+            _check_against_plain(h, A, B)
+            small = gen.erdos_renyi(300, A.ncols, 3, seed=58, dtype=A.val.dtype)
+            _check_against_plain(h, small, B)
+        finally:
+            h.close()
 
 
 def test_noalloc_refuses_cleanly():
