@@ -196,6 +196,39 @@ __device__ __forceinline__ unsigned xcd_block() {
     return (b & 7u) * (g >> 3) + (b >> 3);
 }
 
+// Row slots of a persistent workgroup kernel.  With a queue q (two counters
+// in the device info block: slots handed out, workgroups done), a workgroup
+// takes the next free slot each time it finishes a row, so that rows of very
+// different cost (a skewed matrix's hub rows) spread over the compute units;
+// without one (q null) workgroup b takes slots b, b + grid, ...  Every
+// thread calls these (they synchronize the workgroup), and block_slots_done
+// follows the loop.
+__device__ __forceinline__ long long block_first(unsigned* q, long long* s_slot) {
+    if (!q) return blockIdx.x;
+    if (threadIdx.x == 0) *s_slot = atomicAdd(q, 1u);
+    __syncthreads();
+    return *s_slot;
+}
+
+__device__ __forceinline__ long long block_next(unsigned* q, long long slot, long long* s_slot) {
+    if (!q) return slot + gridDim.x;
+    __syncthreads();                            // every thread has read the previous slot
+    if (threadIdx.x == 0) *s_slot = atomicAdd(q, 1u);
+    __syncthreads();
+    return *s_slot;
+}
+
+// The last workgroup out resets the queue: every other workgroup has taken
+// its last slot by then, and the next launch on the stream finds zeros.
+__device__ __forceinline__ void block_slots_done(unsigned* q) {
+    if (!q || threadIdx.x != 0) return;
+    __threadfence();
+    if (atomicAdd(q + 1, 1u) == gridDim.x - 1) {
+        atomicExch(q, 0u);
+        atomicExch(q + 1, 0u);
+    }
+}
+
 // ===========================================================================
 // Fill a small int buffer (graph-safe replacement for memset)
 // ===========================================================================
@@ -751,10 +784,12 @@ __global__ void __launch_bounds__(BS)
 k_sym_block(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp, WinRec rec) {
+            int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp, WinRec rec,
+            unsigned* q) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
+    __shared__ long long s_slot;
     __shared__ int32_t keys[T];
     __shared__ int s_wc[BATCH ? 1 : kWinMaxNw];
     __shared__ int s_rslot;
@@ -763,7 +798,7 @@ k_sym_block(Work wk,
     __shared__ BlockScanSmem<BS> sm;
     const int tid = threadIdx.x;
     int err = 0;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+    for (long long slot = block_first(q, &s_slot); slot < nrows_bin; slot = block_next(q, slot, &s_slot)) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long bo = row_boff<BATCH>(mp, row);
         for (int s = tid; s < T; s += BS) keys[s] = kEmpty;
@@ -806,6 +841,7 @@ k_sym_block(Work wk,
         }
         __syncthreads();
     }
+    block_slots_done(q);
     if (err) atomicOr(&info->err, kErrProbe);
 }
 
@@ -816,10 +852,12 @@ __global__ void __launch_bounds__(BS)
 k_sym_bitmap(Work wk, long long ncols,
              const int64_t* __restrict__ arp, const int32_t* __restrict__ acol,
              const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
-             int32_t* __restrict__ row_nnz, uint32_t* gslab, DevInfo* info, RowMap mp, WinRec rec) {
+             int32_t* __restrict__ row_nnz, uint32_t* gslab, DevInfo* info, RowMap mp, WinRec rec,
+             unsigned* q) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
+    __shared__ long long s_slot;
     extern __shared__ uint32_t dyn_smem[];
     __shared__ int s_wc[BATCH ? 1 : kWinMaxNw];
     __shared__ int s_rslot, s_bmslot;
@@ -829,7 +867,7 @@ k_sym_bitmap(Work wk, long long ncols,
     const int tid = threadIdx.x;
     const long long words = (ncols + 31) >> 5;
     uint32_t* bm = LDSBM ? dyn_smem : gslab + (long long)blockIdx.x * words;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+    for (long long slot = block_first(q, &s_slot); slot < nrows_bin; slot = block_next(q, slot, &s_slot)) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long bo = row_boff<BATCH>(mp, row);
         for (long long w = tid; w < words; w += BS) bm[w] = 0u;
@@ -913,6 +951,7 @@ k_sym_bitmap(Work wk, long long ncols,
         }
         __syncthreads();
     }
+    block_slots_done(q);
     (void)info;
 }
 
@@ -2408,10 +2447,12 @@ k_num_block(Work wk,
             const int64_t* __restrict__ arp, const int32_t* __restrict__ acol, const VT* __restrict__ aval,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp) {
+            int32_t* __restrict__ cnt_out, DevInfo* info, RowMap mp,
+            unsigned* q) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
+    __shared__ long long s_slot;
     constexpr int PER = T / BS;    // slots per thread in the compaction
     static_assert(PER >= 1, "T must be >= BS");
     __shared__ __align__(16) int32_t keys[T];
@@ -2423,7 +2464,7 @@ k_num_block(Work wk,
     __shared__ int s_fail;
     const int tid = threadIdx.x;
     int err = 0;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+    for (long long slot = block_first(q, &s_slot); slot < nrows_bin; slot = block_next(q, slot, &s_slot)) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long bo = row_boff<BATCH>(mp, row);
         for (int s = tid; s < T; s += BS) { keys[s] = kEmpty; vals[s] = 0.0; }
@@ -2535,6 +2576,7 @@ k_num_block(Work wk,
         }
         __syncthreads();
     }
+    block_slots_done(q);
     if (err) atomicOr(&info->err, kErrProbe);
 }
 
@@ -2581,10 +2623,12 @@ k_num_slice(Work wk, long long ncols, long long span,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, const VT* __restrict__ bval,
             const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
             uint32_t* __restrict__ gbm, long long lds_bytes, int32_t* __restrict__ cnt_out, DevInfo* info,
-            RowMap mp) {
+            RowMap mp,
+            unsigned* q) {
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
+    __shared__ long long s_slot;
     constexpr int RU = kProductUnroll;
     extern __shared__ __align__(16) uint32_t dyn_slice[];   // bitmap; then a slice's segment and accumulator
     uint32_t* const dyn_smem = dyn_slice;
@@ -2599,7 +2643,7 @@ k_num_slice(Work wk, long long ncols, long long span,
     const long long budget = lds_bytes - kSliceBlockCost - 16;   // > kSliceBlockCost (host); 16: alignment pad
     const long long span_words = (span + 31) >> 5;
     uint32_t* gb = gbm + (long long)blockIdx.x * span_words;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+    for (long long slot = block_first(q, &s_slot); slot < nrows_bin; slot = block_next(q, slot, &s_slot)) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long bo = row_boff<BATCH>(mp, row);
         const long long a0 = arp[row], a1 = arp[row + 1];
@@ -2822,6 +2866,7 @@ k_num_slice(Work wk, long long ncols, long long span,
         }
         __syncthreads();
     }
+    block_slots_done(q);
 }
 
 // ===========================================================================
@@ -2900,11 +2945,13 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
           const VT* __restrict__ aval, const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
           const VT* __restrict__ bval, const int32_t* __restrict__ bslot, const int32_t* __restrict__ wpos,
           WinRec rec, const int64_t* __restrict__ crp, int32_t* __restrict__ ccol, VT* __restrict__ cval,
-          long long budget, int32_t* __restrict__ fb_list, DevInfo* info) {
+          long long budget, int32_t* __restrict__ fb_list, DevInfo* info,
+          unsigned* q) {
     static_assert(BS >= kWinMaxNw, "one window count per thread");
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
+    __shared__ long long s_slot;
     constexpr int RU = kWinRU;
     // FP64 values double the pipeline's registers: the second stage is kept for FP32 only
     constexpr bool PIPE = kWinPipe && sizeof(VT) == 4;
@@ -2920,7 +2967,7 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nrec = min(__hip_atomic_load(rec.nrec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), rec.cap);
     bool bad = false;
-    for (long long slot = blockIdx.x; slot < nrows_bin; slot += gridDim.x) {
+    for (long long slot = block_first(q, &s_slot); slot < nrows_bin; slot = block_next(q, slot, &s_slot)) {
         const int row = perm ? perm[slot] : (int)slot;
         const long long rp = crp[row], rlen = crp[row + 1] - rp;
         if (tid == 0) {
@@ -3185,6 +3232,7 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
         }
         __syncthreads();                                // s_rec, s_rk and the LDS are reused by the next row
     }
+    block_slots_done(q);
     if (bad && tid == 0) atomicOr(&info->err, kErrCount);
 }
 

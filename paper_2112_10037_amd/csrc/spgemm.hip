@@ -287,6 +287,9 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
+    // row queues of the one-row-per-workgroup kernels (the batched graph's
+    // kernels keep their static slots)
+    auto queue = [&](int k) -> unsigned* { return BATCH ? nullptr : &info->queue[k][0]; };
     // window records for the numeric global bin (plain products only)
     const WinRec rec = BATCH ? WinRec{} : h->cur_rec;
     if (s.kind == Kind::Merge) {
@@ -322,7 +325,8 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
         const int grid = std::min(rows, 4 * h->num_cu);
 #define X(BS, T)                                                                                       \
     if (s.lanes == BS && s.slots == T) {                                                               \
-        k_sym_block<BS, T, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp, rec); \
+        k_sym_block<BS, T, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp, rec, \
+                                                       queue(kQSymBlock));                               \
         return launch_check("k_sym_block");                                                            \
     }
         MSP_SYM_BLOCK_SHAPES(X)
@@ -340,10 +344,11 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
         }
         if (lds)
             k_sym_bitmap<1024, true, BATCH><<<grid, 1024, words * 4, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol,
-                                                                           rnnz, slab, info, mp, rec);
+                                                                           rnnz, slab, info, mp, rec,
+                                                                           queue(kQSymBitmap));
         else
             k_sym_bitmap<1024, false, BATCH><<<grid, 1024, 0, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol, rnnz,
-                                                                    slab, info, mp, rec);
+                                                                    slab, info, mp, rec, queue(kQSymBitmap));
         return launch_check("k_sym_bitmap");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no symbolic kernel for bin shape (%d, %d)", s.lanes, s.slots);
@@ -377,7 +382,7 @@ static msp_status launch_window_bin(msp_handle* h, Work wk, int rows, const Oper
     k_num_win<kWinBS, VT><<<grid, kWinBS, (size_t)lds, st>>>(
         wk, nw, op.arp, op.acol, (const VT*)op.aval, op.brp, op.bcol, (const VT*)op.bval,
         h->win_bslot.as<int32_t>(), h->win_wpos.as<int32_t>(), rec, crp, ccol, cval, (long long)lds,
-        h->win_fb.as<int32_t>(), info);
+        h->win_fb.as<int32_t>(), info, &info->queue[kQNumWin][0]);
     r = launch_check("k_num_win");
     h->prof.sub_end(MSP_PHASE_GLOBAL_BIN, ev, st);
     return r;
@@ -391,6 +396,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
     hipStream_t st = h->stream;
     const VT* av = (const VT*)op.aval;
     const VT* bv = (const VT*)op.bval;
+    auto queue = [&](int k) -> unsigned* { return BATCH ? nullptr : &info->queue[k][0]; };
     if (s.kind == Kind::Merge) {
         const bool small = op.bnnz < INT32_MAX;     // 32-bit positions into B
 #define MSP_MERGE(KK, IT, SH)                                                                            \
@@ -436,7 +442,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
 #define X(BS, T)                                                                                             \
     if (s.lanes == BS && s.slots == T) {                                                                     \
         k_num_block<BS, T, VT, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp,   \
-                                                           ccol, cval, cnt_out, info, mp);                  \
+                                                           ccol, cval, cnt_out, info, mp, queue(kQNumBlock)); \
         return launch_check("k_num_block");                                                                  \
     }
         MSP_NUM_BLOCK_SHAPES(X)
@@ -470,11 +476,11 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
                 if (n <= span_max)
                     k_num_slice<kSliceBS, VT, BATCH, false><<<grid, kSliceBS, (size_t)lds, st>>>(
                         wk, n, span, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval,
-                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp);
+                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp, queue(kQNumSlice));
                 else
                     k_num_slice<kSliceBS, VT, BATCH, true><<<grid, kSliceBS, (size_t)lds, st>>>(
                         wk, n, span, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval,
-                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp);
+                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp, queue(kQNumSlice));
                 return launch_check("k_num_slice");
             }
         }

@@ -58,6 +58,11 @@ struct LongRows {                         // work lists of the long rows (list =
     int list_cap = 0, chunk_cap = 0;
 };
 
+// Row queues of the persistent one-row-per-workgroup kernels of the plain
+// product (one per kernel family; launches of a family follow each other on
+// the handle's stream).
+enum { kQSymBlock = 0, kQSymBitmap, kQNumBlock, kQNumWin, kQNumSlice, kQueues };
+
 struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
     int err;                              // error bits of the current call
@@ -76,7 +81,8 @@ struct DevInfo {
     unsigned long long learned_big_hi;    // learned product: upper bounds of the rows sent to the exact path
     int long_n;                           // row statistics: rows taken apart as long rows
     int long_chunks;                      // and their chunks
-    int pad[8];
+    unsigned queue[kQueues][2];           // row queues of the persistent workgroup kernels:
+                                          // {slots handed out, workgroups done}, zero between launches
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
