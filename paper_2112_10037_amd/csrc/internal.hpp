@@ -101,6 +101,11 @@ struct Profiler {
 struct msp_handle {
     int device = 0;
     hipStream_t stream = nullptr;
+    // side streams for the bins of a phase (default priority), and the
+    // events that fork them from `stream` and join them back
+    hipStream_t side[msp::kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[msp::kSideStreams] = {};
     msp_alloc_fn alloc = nullptr;
     msp_free_fn free_fn = nullptr;
     void* alloc_ctx = nullptr;

@@ -139,6 +139,28 @@ static void default_free(void*, void* p, void*) {
     if (p) (void)hipFree(p);
 }
 
+// Side streams and fork/join events of a handle (null members are skipped).
+static void release_streams(msp_handle* h) {
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (h->side[i]) (void)hipStreamDestroy(h->side[i]);
+        if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+        h->side[i] = nullptr;
+        h->join_ev[i] = nullptr;
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    h->fork_ev = nullptr;
+}
+
+static hipError_t create_streams(msp_handle* h) {
+    hipError_t e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
+        if ((e = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking)) == hipSuccess)
+            e = hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) release_streams(h);
+    return e;
+}
+
 extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
     if (!out) return fail(MSP_ERR_INVALID_ARG, "msp_create: null handle pointer");
     *out = nullptr;
@@ -194,7 +216,8 @@ extern "C" msp_status msp_create(msp_handle** out, int device, void* stream) {
     }
     *h->hpending = 0;
     memset(h->hsum, 0, sizeof(HostSummary));
-    if ((s = configure_kernels(h)) != MSP_OK) {
+    if ((s = configure_kernels(h)) != MSP_OK || (e = create_streams(h)) != hipSuccess) {
+        if (s == MSP_OK) s = hip_fail(e, "side streams");
         (void)hipHostFree(h->hsum);
         (void)hipHostFree(h->hpending);
         (void)hipHostFree(h->hinfo);
@@ -217,6 +240,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
         b->release();
     release_extra(h);
     h->prof.release();
+    release_streams(h);
     if (h->hinfo) (void)hipHostFree(h->hinfo);
     if (h->hpending) (void)hipHostFree(h->hpending);
     if (h->hsum) (void)hipHostFree(h->hsum);

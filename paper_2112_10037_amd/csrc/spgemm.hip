@@ -287,9 +287,7 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
     if (rows <= 0) return MSP_OK;
     DevInfo* info = h->info.as<DevInfo>();
     hipStream_t st = h->stream;
-    // row queues of the one-row-per-workgroup kernels (the batched graph's
-    // kernels keep their static slots)
-    auto queue = [&](int k) -> unsigned* { return BATCH ? nullptr : &info->queue[k][0]; };
+    unsigned* const rq = BATCH ? nullptr : wk.rowq;   // (the batched graph's kernels keep static slots)
     // window records for the numeric global bin (plain products only)
     const WinRec rec = BATCH ? WinRec{} : h->cur_rec;
     if (s.kind == Kind::Merge) {
@@ -326,7 +324,7 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
 #define X(BS, T)                                                                                       \
     if (s.lanes == BS && s.slots == T) {                                                               \
         k_sym_block<BS, T, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, op.brp, op.bcol, rnnz, info, mp, rec, \
-                                                       queue(kQSymBlock));                               \
+                                                       rq);                                              \
         return launch_check("k_sym_block");                                                            \
     }
         MSP_SYM_BLOCK_SHAPES(X)
@@ -345,10 +343,10 @@ static msp_status launch_symbolic_t(msp_handle* h, const BinSpec& s, Work wk, in
         if (lds)
             k_sym_bitmap<1024, true, BATCH><<<grid, 1024, words * 4, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol,
                                                                            rnnz, slab, info, mp, rec,
-                                                                           queue(kQSymBitmap));
+                                                                           rq);
         else
             k_sym_bitmap<1024, false, BATCH><<<grid, 1024, 0, st>>>(wk, n, op.arp, op.acol, op.brp, op.bcol, rnnz,
-                                                                    slab, info, mp, rec, queue(kQSymBitmap));
+                                                                    slab, info, mp, rec, rq);
         return launch_check("k_sym_bitmap");
     }
     return fail(MSP_ERR_UNSUPPORTED, "no symbolic kernel for bin shape (%d, %d)", s.lanes, s.slots);
@@ -382,7 +380,7 @@ static msp_status launch_window_bin(msp_handle* h, Work wk, int rows, const Oper
     k_num_win<kWinBS, VT><<<grid, kWinBS, (size_t)lds, st>>>(
         wk, nw, op.arp, op.acol, (const VT*)op.aval, op.brp, op.bcol, (const VT*)op.bval,
         h->win_bslot.as<int32_t>(), h->win_wpos.as<int32_t>(), rec, crp, ccol, cval, (long long)lds,
-        h->win_fb.as<int32_t>(), info, &info->queue[kQNumWin][0]);
+        h->win_fb.as<int32_t>(), info, wk.rowq);
     r = launch_check("k_num_win");
     h->prof.sub_end(MSP_PHASE_GLOBAL_BIN, ev, st);
     return r;
@@ -396,7 +394,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
     hipStream_t st = h->stream;
     const VT* av = (const VT*)op.aval;
     const VT* bv = (const VT*)op.bval;
-    auto queue = [&](int k) -> unsigned* { return BATCH ? nullptr : &info->queue[k][0]; };
+    unsigned* rq = BATCH ? nullptr : wk.rowq;         // (the batched graph's kernels keep static slots)
     if (s.kind == Kind::Merge) {
         const bool small = op.bnnz < INT32_MAX;     // 32-bit positions into B
 #define MSP_MERGE(KK, IT, SH)                                                                            \
@@ -442,7 +440,7 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
 #define X(BS, T)                                                                                             \
     if (s.lanes == BS && s.slots == T) {                                                                     \
         k_num_block<BS, T, VT, BATCH><<<grid, BS, 0, st>>>(wk, op.arp, op.acol, av, op.brp, op.bcol, bv, crp,   \
-                                                           ccol, cval, cnt_out, info, mp, queue(kQNumBlock)); \
+                                                           ccol, cval, cnt_out, info, mp, rq);              \
         return launch_check("k_num_block");                                                                  \
     }
         MSP_NUM_BLOCK_SHAPES(X)
@@ -455,7 +453,9 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
                 if (r != MSP_OK) return r;
                 // the rows without a record: their list and count are in device memory
                 wk = Work{h->win_fb.as<int32_t>(), 0, &info->win_fb[0]};
+                wk.rowq = &info->queue[1][kNB][0];
                 rows = h->num_cu;
+                rq = wk.rowq;
             }
         }
         {
@@ -476,11 +476,11 @@ static msp_status launch_numeric_t(msp_handle* h, const BinSpec& s, Work wk, int
                 if (n <= span_max)
                     k_num_slice<kSliceBS, VT, BATCH, false><<<grid, kSliceBS, (size_t)lds, st>>>(
                         wk, n, span, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval,
-                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp, queue(kQNumSlice));
+                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp, rq);
                 else
                     k_num_slice<kSliceBS, VT, BATCH, true><<<grid, kSliceBS, (size_t)lds, st>>>(
                         wk, n, span, op.arp, op.acol, av, op.brp, op.bcol, bv, crp, ccol, cval,
-                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp, queue(kQNumSlice));
+                        h->gsl.as<uint32_t>(), lds, cnt_out, info, mp, rq);
                 return launch_check("k_num_slice");
             }
         }
@@ -528,15 +528,18 @@ Operands operands_of(const msp_csr* A, const msp_csr* B) {
 
 // plain product: rows listed in perm (or all rows)
 static msp_status launch_symbolic(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
-                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz) {
-    return launch_symbolic_t<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), rnnz, RowMap{});
+                                  const msp_csr* A, const msp_csr* B, int32_t* rnnz, unsigned* rowq) {
+    Work wk{perm, rows, nullptr};
+    wk.rowq = rowq;
+    return launch_symbolic_t<false>(h, s, wk, rows, operands_of(A, B), rnnz, RowMap{});
 }
 
 static msp_status launch_numeric(msp_handle* h, const BinSpec& s, int rows, const int32_t* perm,
                                  const msp_csr* A, const msp_csr* B, const int64_t* crp,
-                                 int32_t* ccol, void* cval, int32_t* cnt_out) {
-    return launch_numeric_bin<false>(h, s, Work{perm, rows, nullptr}, rows, operands_of(A, B), crp, ccol, cval,
-                                     cnt_out, RowMap{});
+                                 int32_t* ccol, void* cval, int32_t* cnt_out, unsigned* rowq) {
+    Work wk{perm, rows, nullptr};
+    wk.rowq = rowq;
+    return launch_numeric_bin<false>(h, s, wk, rows, operands_of(A, B), crp, ccol, cval, cnt_out, RowMap{});
 }
 
 // ---------------------------------------------------------------------------
@@ -696,16 +699,17 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
             all_group = all_group && (plan.spec[b].kind == Kind::Group || plan.spec[b].kind == Kind::Batch);
         }
     if (nonempty == 0) return MSP_OK;
+    DevInfo* info = h->info.as<DevInfo>();
+    auto rowq = [&](int b) { return &info->queue[numeric ? 1 : 0][b][0]; };
     // bin done_bin was already processed: its rows must not be taken again
     const bool done_rows = done_bin > 0 && counts[done_bin] > 0;
     if (!done_rows && (nonempty == 1 || all_group)) {
-        return numeric ? launch_numeric(h, plan.spec[last], m, nullptr, A, B, crp, ccol, cval, cnt_out)
-                       : launch_symbolic(h, plan.spec[last], m, nullptr, A, B, rnnz);
+        return numeric ? launch_numeric(h, plan.spec[last], m, nullptr, A, B, crp, ccol, cval, cnt_out, rowq(last))
+                       : launch_symbolic(h, plan.spec[last], m, nullptr, A, B, rnnz, rowq(last));
     }
     msp_status s = h->perm.ensure((size_t)m * 4);
     if (s != MSP_OK) return s;
     int32_t* perm = h->perm.as<int32_t>();
-    DevInfo* info = h->info.as<DevInfo>();
     int* cursor = &info->cursor[0][0];
     k_zero_words<<<1, 256, 0, h->stream>>>(cursor, kParts * kPartStride);
     if ((s = launch_check("k_zero_words")) != MSP_OK) return s;
@@ -713,16 +717,65 @@ static msp_status run_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, co
         m, key, plan.table, numeric ? &info->num_part[0][0] : &info->sym_part[0][0],
         numeric ? kScanTile : 256, cursor, perm);
     if ((s = launch_check("k_scatter")) != MSP_OK) return s;
+    // The bins are independent.  A bin with fewer rows than it takes to fill
+    // the GPU ("narrow": under 8 a compute unit) runs on a side stream, forked
+    // after the scatter and joined before the stream goes on, so that its
+    // few long-latency rows overlap the other bins' work; wide bins stay on
+    // the handle's stream (with no wide bin, it takes narrow ones too).  A
+    // global bin with a row for every compute unit fills the GPU with its
+    // persistent kernel by itself: it runs alone first.  Largest rows first.
+    int first[kNB];
     int start = counts[0];
     for (int b = 1; b <= nb; ++b) {
-        if (counts[b] > 0 && b != done_bin) {
-            s = numeric ? launch_numeric(h, plan.spec[b], counts[b], perm + start, A, B, crp, ccol, cval, cnt_out)
-                        : launch_symbolic(h, plan.spec[b], counts[b], perm + start, A, B, rnnz);
-            if (s != MSP_OK) return s;
-        }
+        first[b] = start;
         start += counts[b];
     }
-    return MSP_OK;
+    auto launch = [&](int b, unsigned* q) {
+        return numeric ? launch_numeric(h, plan.spec[b], counts[b], perm + first[b], A, B, crp, ccol, cval, cnt_out, q)
+                       : launch_symbolic(h, plan.spec[b], counts[b], perm + first[b], A, B, rnnz, q);
+    };
+    const Kind gk = plan.spec[nb].kind;
+    int alone = -1;
+    if ((gk == Kind::Dense || gk == Kind::Bitmap) && nb != done_bin && counts[nb] >= h->num_cu) {
+        if ((s = launch(nb, rowq(nb))) != MSP_OK) return s;
+        alone = nb;
+    }
+    auto todo = [&](int b) { return counts[b] > 0 && b != done_bin && b != alone; };
+    auto narrow = [&](int b) { return counts[b] < 8 * h->num_cu; };
+    int nnarrow = 0, nwide = 0;
+    for (int b = 1; b <= nb; ++b)
+        if (todo(b)) ++(narrow(b) ? nnarrow : nwide);
+    // workers for the narrow bins: the side streams, and the handle's stream
+    // when no wide bin needs it
+    const int nside = h->fork_ev && nnarrow > 0 && nnarrow + nwide >= 2
+                          ? std::min(kSideStreams, nwide > 0 ? nnarrow : nnarrow - 1) : 0;
+    const hipStream_t main_st = h->stream;
+    hipError_t e = hipSuccess;
+    if (nside > 0) {
+        if ((e = hipEventRecord(h->fork_ev, main_st)) != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
+        for (int i = 0; i < nside; ++i)
+            if ((e = hipStreamWaitEvent(h->side[i], h->fork_ev, 0)) != hipSuccess)
+                return hip_fail(e, "hipStreamWaitEvent(fork)");
+    }
+    const int nworkers = nside + (nwide > 0 ? 0 : 1);
+    int k = 0;
+    for (int b = nb; b >= 1 && s == MSP_OK; --b) {
+        if (!todo(b)) continue;
+        int w = -1;                                  // -1: the handle's stream
+        if (nside > 0 && narrow(b)) {
+            w = k++ % nworkers;
+            if (nwide == 0) --w;                     // worker 0 is the handle's stream
+        }
+        h->stream = w < 0 ? main_st : h->side[w];
+        s = launch(b, rowq(b));
+    }
+    h->stream = main_st;
+    // join whatever was forked, also after a failed launch
+    for (int i = 0; i < nside && e == hipSuccess; ++i)
+        if ((e = hipEventRecord(h->join_ev[i], h->side[i])) == hipSuccess)
+            e = hipStreamWaitEvent(main_st, h->join_ev[i], 0);
+    if (s != MSP_OK) return s;
+    return e == hipSuccess ? MSP_OK : hip_fail(e, "joining the side streams");
 }
 
 msp_status run_symbolic_bins(msp_handle* h, const msp_csr* A, const msp_csr* B, const BinPlan& plan,

@@ -31,6 +31,7 @@ constexpr float kFeatLogScale = 1.0f / 16.0f;
 // thousands of workgroups do not serialise on one address.
 constexpr int kParts = 32;
 constexpr int kNB = kMaxBins + 1;
+constexpr int kSideStreams = 3;    // streams beside the handle's that run a phase's bins concurrently
 constexpr int kPartStride = 32;    // ints per partition row (128 bytes)
 // On long inputs the fused symbolic pass also adds each workgroup's
 // row-count total into one of at most kSupers super-tile sums, so that a
@@ -58,11 +59,6 @@ struct LongRows {                         // work lists of the long rows (list =
     int list_cap = 0, chunk_cap = 0;
 };
 
-// Row queues of the persistent one-row-per-workgroup kernels of the plain
-// product (one per kernel family; launches of a family follow each other on
-// the handle's stream).
-enum { kQSymBlock = 0, kQSymBitmap, kQNumBlock, kQNumWin, kQNumSlice, kQueues };
-
 struct DevInfo {
     long long nnz;                        // nnz(C) after the scan
     int err;                              // error bits of the current call
@@ -81,8 +77,11 @@ struct DevInfo {
     unsigned long long learned_big_hi;    // learned product: upper bounds of the rows sent to the exact path
     int long_n;                           // row statistics: rows taken apart as long rows
     int long_chunks;                      // and their chunks
-    unsigned queue[kQueues][2];           // row queues of the persistent workgroup kernels:
-                                          // {slots handed out, workgroups done}, zero between launches
+    // row queues of the persistent one-row-per-workgroup kernels, per phase
+    // (symbolic, numeric) and bin, plus [1][kNB] for the global bin's rows
+    // without a window record: {slots handed out, workgroups done}, zero
+    // between launches
+    unsigned queue[2][kNB + 1][2];
     int sym_part[kParts][kPartStride];    // rows per symbolic bin, per partition
     int num_part[kParts][kPartStride];    // rows per numeric bin, per partition
     int cursor[kParts][kPartStride];      // scatter cursors
@@ -155,6 +154,7 @@ struct Work {
     const int* dev;
     int* ticket;        // shared work queue of the launch (zero at launch), or null
     int tk;             // rows per ticket
+    unsigned* rowq = nullptr;   // row queue of a one-row-per-workgroup kernel (see block_first)
 };
 
 __device__ __forceinline__ void work_rows(const Work& w, int* n, const int32_t** perm) {
