@@ -2318,6 +2318,59 @@ k_scan_lookback(int m, const int32_t* __restrict__ cnt, unsigned long long* tile
 // Numeric pass with in-row column sort
 // ===========================================================================
 
+// Column order of a row's n (<= 64 R) distinct outputs held by one wave:
+// the (column, slot) pairs kt[0..n) are sorted ascending by a bitonic
+// network over 64 R elements (element e = r 64 + lane, pads last), lane
+// shuffles for partners in other lanes and register swaps for partners in
+// the lane's other registers; element e then goes to position e of the row
+// with its slot's value (coalesced stores).
+template <int R, typename VT>
+__device__ __forceinline__ void wave_sort_out(const int32_t* kt, const double* vt, int n, int32_t* oc, VT* ov,
+                                              int lane) {
+    constexpr int N = 64 * R;
+    unsigned long long x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        x[r] = e < n ? ((unsigned long long)(unsigned)kt[e] << 32) | (unsigned)e : ~0ull;
+    }
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int rr = r ^ (j >> 6);
+                    if (rr > r) {
+                        const bool up = ((r * 64 + lane) & k) == 0;
+                        const unsigned long long a = x[r], b = x[rr];
+                        if (up ? a > b : a < b) {
+                            x[r] = b;
+                            x[rr] = a;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const unsigned long long o = __shfl_xor(x[r], j);
+                    const bool up = ((r * 64 + lane) & k) == 0, low = (lane & j) == 0;
+                    x[r] = (low == up) ? (o < x[r] ? o : x[r]) : (o > x[r] ? o : x[r]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        if (e < n) {
+            oc[e] = (int32_t)(x[r] >> 32);
+            ov[e] = (VT)vt[(unsigned)x[r]];
+        }
+    }
+}
+
 // Numeric, sub-wave lane groups.  T slots of (int32 key, FP64 value); a row
 // with r = row_nnz_i <= T/2 entries.  After accumulation the occupied slots
 // are compacted (group ballot) and each entry's output position is its
@@ -2417,6 +2470,17 @@ k_num_group(Work wk,
         if (gl == 0) atomicOr(&info->err, failed ? kErrProbe : kErrCount);
         lds_fence();
         continue;
+    }
+    if constexpr (G == 64 && T / 2 > 128) {
+        // long rows: a bitonic sort across the wave (the rank count below
+        // costs n / 4 LDS reads and n compares per output, n / 64 outputs a
+        // lane; the sort of T / 2 elements costs less from about 160 on)
+        if (n > 160) {                                  // wave-uniform (a row per wave)
+            lds_fence();
+            wave_sort_out<T / 128>(kt, vt, n, ccol + rp, cval + rp, lane);
+            lds_fence();
+            continue;
+        }
     }
     const int n4 = (n + 3) & ~3;
     if (gl < n4 - n) kt[n + gl] = 0x7fffffff;         // pads sort after every key
