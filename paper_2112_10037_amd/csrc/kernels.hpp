@@ -2992,7 +2992,7 @@ k_bwin_index(long long brows, const int64_t* __restrict__ brp, const int32_t* __
 constexpr int kWinBS = 1024;                   // threads of the windowed kernel (one workgroup per CU)
 constexpr int kWinRU = 4;                      // products per lane and pipeline stage
 constexpr bool kWinPipe = false;               // gathers of the next stage issued before the current LDS work
-constexpr bool kWinOr32 = false;               // bitmap pass: 32-bit atomic ORs instead of 64-bit
+constexpr bool kWinOr32 = true;                // bitmap pass: 32-bit atomic ORs instead of 64-bit
 constexpr bool kWinSwizzle = true;             // accumulator index swizzled within 32-entry groups
 
 // Accumulator slots of a slice of n outputs, and the slot of rank r: with
