@@ -2503,7 +2503,8 @@ k_num_group(Work wk,
 // Numeric, one workgroup per row: LDS hash of T (key, FP64) slots, then the
 // occupied slots are compacted to the front and put in column order: rows of
 // at most kBlockRankMax outputs by counting each key's smaller keys, longer
-// rows by a bitonic sort in LDS and coalesced stores.
+// rows by a bitonic sort of (column, slot) pairs, its short-range stages in
+// the waves' registers, and coalesced stores.
 constexpr int kBlockRankMax = 512;
 template <int BS, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
@@ -2617,26 +2618,79 @@ k_num_block(Work wk,
             __syncthreads();
             continue;
         }
-        // bitonic sort of keys[0..P) ascending, values follow
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = tid; t < P / 2; t += BS) {
-                    const int i = 2 * j * (t / j) + (t % j);
-                    const int l = i + j;
-                    const bool up = (i & k) == 0;
-                    const int32_t ki = keys[i], kl = keys[l];
-                    if ((ki > kl) == up) {
-                        keys[i] = kl; keys[l] = ki;
-                        const double vi = vals[i];
-                        vals[i] = vals[l]; vals[l] = vi;
+        // a long row: bitonic sort of P (column, slot) pairs (pads last).  The
+        // pairs take the place of the keys (P <= T / 2 pairs of 8 bytes); the
+        // values stay where they are and are read by slot at the end.  Stages
+        // whose partners lie within one 128-element block run in a wave's
+        // registers (lane shuffles; lane l holds elements 128 b + l and
+        // 128 b + 64 + l), the others in LDS with a barrier each.
+        {
+            constexpr int MAXI = (T / 2 + BS - 1) / BS;
+            int32_t kr[MAXI];
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                const int e = tid + i * BS;
+                kr[i] = e < n ? keys[e] : 0;
+            }
+            __syncthreads();
+            unsigned long long* pk = reinterpret_cast<unsigned long long*>(keys);
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                const int e = tid + i * BS;
+                if (e < P) pk[e] = e < n ? ((unsigned long long)(unsigned)kr[i] << 32) | (unsigned)e : ~0ull;
+            }
+            __syncthreads();
+            constexpr int NW = BS / 64;
+            const int lane = tid & 63, wv = tid >> 6;
+            // the stages j <= 64 of phases k0 .. k1, in registers
+            auto wave_stages = [&](int k0, int k1) {
+                for (int b = wv; b < P / 128; b += NW) {                // wave-uniform
+                    const int e0 = 128 * b + lane, e1 = e0 + 64;
+                    unsigned long long x0 = pk[e0], x1 = pk[e1];
+                    for (int k = k0; k <= k1; k <<= 1) {
+                        const bool up0 = (e0 & k) == 0, up1 = (e1 & k) == 0;
+                        for (int jj = (k >> 1) < 64 ? (k >> 1) : 64; jj >= 1; jj >>= 1) {
+                            if (jj == 64) {
+                                if ((x0 > x1) == up0) {
+                                    const unsigned long long t = x0;
+                                    x0 = x1;
+                                    x1 = t;
+                                }
+                            } else {
+                                const unsigned long long o0 = __shfl_xor(x0, jj), o1 = __shfl_xor(x1, jj);
+                                const bool low = (lane & jj) == 0;
+                                x0 = (low == up0) ? (o0 < x0 ? o0 : x0) : (o0 > x0 ? o0 : x0);
+                                x1 = (low == up1) ? (o1 < x1 ? o1 : x1) : (o1 > x1 ? o1 : x1);
+                            }
+                        }
                     }
+                    pk[e0] = x0;
+                    pk[e1] = x1;
                 }
                 __syncthreads();
+            };
+            wave_stages(2, 128);
+            for (int k = 256; k <= P; k <<= 1) {
+                for (int j = k >> 1; j >= 128; j >>= 1) {
+                    for (int t = tid; t < P / 2; t += BS) {
+                        const int i = 2 * j * (t / j) + (t % j);
+                        const int l = i + j;
+                        const bool up = (i & k) == 0;
+                        const unsigned long long a = pk[i], c = pk[l];
+                        if ((a > c) == up) {
+                            pk[i] = c;
+                            pk[l] = a;
+                        }
+                    }
+                    __syncthreads();
+                }
+                wave_stages(k, k);
             }
-        }
-        for (int e = tid; e < n; e += BS) {
-            ccol[rp + e] = keys[e];
-            cval[rp + e] = (VT)vals[e];
+            for (int e = tid; e < n; e += BS) {
+                const unsigned long long x = pk[e];
+                ccol[rp + e] = (int32_t)(x >> 32);
+                cval[rp + e] = (VT)vals[(unsigned)x];
+            }
         }
         __syncthreads();
     }

@@ -568,3 +568,20 @@ def test_group_rows_sorted_across_wave(h, dtype):
     outs = np.diff(ref[0])
     assert outs.min() >= 100 and outs.max() <= 256 and (outs > 160).sum() > 1000
     check_full(h, A, B)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_block_rows_sorted(h, dtype):
+    """Rows of about 500 to 4,000 distinct outputs in the workgroup hash bins
+    (default tuning): those over 512 outputs are put in column order by the
+    bitonic sort whose short-range stages run in the waves' registers, the
+    others by the rank count; every row must match the oracle, ragged sizes
+    (not powers of two, not multiples of 128) included."""
+    rng = np.random.default_rng(95)
+    m, k, n = 700, 5000, 400_000
+    A = gen.erdos_renyi(m, k, rng.integers(33, 256, m), seed=96, dtype=dtype)
+    B = gen.erdos_renyi(k, n, 16, seed=97, dtype=dtype)
+    ref = oracle.spgemm(A, B)
+    outs = np.diff(ref[0])
+    assert outs.min() > 500 and outs.max() <= 4096 and (outs > 2048).sum() > 50
+    check_full(h, A, B)
