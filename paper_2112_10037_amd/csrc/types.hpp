@@ -42,9 +42,11 @@ constexpr long long kOmarMaxGroup = 4096;   // largest row group of the sharing 
 
 // Row statistics of rows with more than kLongRow A entries are taken apart:
 // chunks of kLongChunk entries go to whole workgroups, which add into the
-// row's LongAcc with global atomics (one wave walking such a row alone would
-// set the kernel's time).
-constexpr int kLongRow = 4096;
+// row's LongAcc with global atomics.  A wave walks 64 consecutive rows, and
+// a skewed matrix's longest rows sit together (R-MAT's at the lowest
+// indices): with long rows up to 4096 entries left in the walk, one wave of
+// a 2^18-row R-MAT had 62 times the mean walk and set the kernel's time.
+constexpr int kLongRow = 256;
 constexpr int kLongChunk = 2048;
 struct LongAcc {
     unsigned long long prod;              // sum of the B-row lengths

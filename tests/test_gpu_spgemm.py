@@ -497,8 +497,9 @@ def test_table4_standins(h, index):
 
 
 def test_long_rows_statistics_and_products(h):
-    """Rows with more than 4,096 A entries are taken apart by the statistics
-    pass (chunks over whole workgroups); products, features, the plain
+    """Rows with more than 256 A entries are taken apart by the statistics
+    pass (chunks over whole workgroups; rows of 5,000 to 20,000 entries span
+    several chunks); products, features, the plain
     product through that pass (no merge bin) and the one-pass product must
     all match the oracle."""
     A, B = long_rows_case()

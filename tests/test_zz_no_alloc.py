@@ -69,7 +69,7 @@ def test_noalloc_matches_plain_twice():
 
 def test_noalloc_first_call_on_fresh_handle():
     """The allocation-free product as a fresh handle's first call, on rows
-    with more than 4,096 A entries (the statistics pass's long-row lists)
+    with more than 256 A entries (the statistics pass's long-row lists)
     and on a skewed matrix: every workspace it touches must come from the
     scratch array, since the library refuses any other workspace growth
     during this call as an internal error.  Then the plain product, and the
