@@ -34,7 +34,12 @@
  *    it in msp_destroy.  Output arrays obtained through the allocator belong
  *    to the caller.
  *  - Every call is asynchronous on the handle's stream except for the points
- *    named per entry point where the host must read a size back.
+ *    named per entry point where the host must read a size back.  Within a
+ *    call, bins with few rows may run on the handle's own side streams
+ *    (default priority): they are forked from the handle's stream by an
+ *    event and joined back into it before the call queues anything after
+ *    them, so every call's work is still ordered after earlier work on the
+ *    handle's stream and before later work there.
  *  - No entry point throws, aborts or exits.  On error the return value says
  *    what failed and msp_last_error() gives a message (thread-local); output
  *    arrays already obtained from the allocator are released through its
@@ -130,7 +135,8 @@ typedef struct msp_handle msp_handle;
 /* ---- handle -------------------------------------------------------------- */
 
 /* Create a handle on `device` that queues all work on `hip_stream` (a
- * hipStream_t; NULL means the device's null stream).  Selects the device,
+ * hipStream_t; NULL means the device's null stream), forking bins onto three
+ * side streams the handle creates and destroys itself.  Selects the device,
  * checks that it is gfx950 (MSP_ERR_UNSUPPORTED otherwise). */
 msp_status msp_create(msp_handle** h, int device, void* hip_stream);
 msp_status msp_destroy(msp_handle* h);
