@@ -2503,8 +2503,9 @@ k_num_group(Work wk,
 // Numeric, one workgroup per row: LDS hash of T (key, FP64) slots, then the
 // occupied slots are compacted to the front and put in column order: rows of
 // at most kBlockRankMax outputs by counting each key's smaller keys, longer
-// rows by a bitonic sort of (column, slot) pairs, its short-range stages in
-// the waves' registers, and coalesced stores.
+// rows by a radix sort of (column, slot) pairs when their columns span less
+// than 2^20, else by a bitonic sort with its short-range stages in the
+// waves' registers; then coalesced stores.
 constexpr int kBlockRankMax = 512;
 template <int BS, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(BS)
@@ -2522,11 +2523,15 @@ k_num_block(Work wk,
     static_assert(PER >= 1, "T must be >= BS");
     __shared__ __align__(16) int32_t keys[T];
     __shared__ double vals[T];
-    __shared__ long long s_off[BS];
-    __shared__ long long s_bst[BS];
+    // the A entries' product offsets and B positions; the sort's digit
+    // counters take their place afterwards
+    __shared__ __align__(16) long long s_ob[2 * BS];
+    long long* const s_off = s_ob;
+    long long* const s_bst = s_ob + BS;
     __shared__ double s_a[BS];
     __shared__ BlockScanSmem<BS> sm;
     __shared__ int s_fail;
+    __shared__ int s_mm[2][BS / 64];
     const int tid = threadIdx.x;
     int err = 0;
     for (long long slot = block_first(q, &s_slot); slot < nrows_bin; slot = block_next(q, slot, &s_slot)) {
@@ -2617,6 +2622,122 @@ k_num_block(Work wk,
             }
             __syncthreads();
             continue;
+        }
+        // a long row whose columns span less than 2^20: stable LSD radix sort
+        // of (column - smallest column, slot) packed in 32 bits (slots take the
+        // low 12 bits), 8 bits a pass.  Each wave ranks its chunk of elements
+        // (lane order within 64-element steps, steps in order) against its own
+        // digit counters, from the lanes that share its digit (8 ballots); an
+        // exclusive scan of the counters in (digit, wave) order gives every
+        // element its place in the other half of the key area.
+        {
+            constexpr int NW = BS / 64;
+            const int lane = tid & 63, wv = tid >> 6;
+            int mn = 0x7fffffff, mx = -1;
+            for (int e = tid; e < n; e += BS) {
+                const int k = keys[e];
+                mn = k < mn ? k : mn;
+                mx = k > mx ? k : mx;
+            }
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) {
+                mn = min(mn, __shfl_xor(mn, d));
+                mx = max(mx, __shfl_xor(mx, d));
+            }
+            if (lane == 0) {
+                s_mm[0][wv] = mn;
+                s_mm[1][wv] = mx;
+            }
+            __syncthreads();
+            mn = s_mm[0][0];
+            mx = s_mm[1][0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+                mn = min(mn, s_mm[0][w]);
+                mx = max(mx, s_mm[1][w]);
+            }
+            if (mx - mn < (1 << 20)) {                      // uniform
+                constexpr int MAXI = (T / 2 + BS - 1) / BS;  // elements a lane
+                constexpr int CH = MAXI * 64;                // elements a wave
+                static_assert(T / 2 <= 4096, "slots take 12 bits");
+                static_assert(NW * 256 == 4 * BS, "each thread scans four digit counters");
+                unsigned* const buf = reinterpret_cast<unsigned*>(keys);     // two halves of T / 2 words
+                int* const hist = reinterpret_cast<int*>(s_ob);              // [NW][256]
+                unsigned x[MAXI];
+#pragma unroll
+                for (int i = 0; i < MAXI; ++i) {
+                    const int e = wv * CH + i * 64 + lane;
+                    x[i] = e < n ? ((unsigned)(keys[e] - mn) << 12) | (unsigned)e : 0u;
+                }
+                const int bits = 32 - __builtin_clz((unsigned)(mx - mn) | 1u);
+                int half = 1;                                // half of the key area written next
+                for (int sh = 12; sh < 12 + bits; sh += 8) {
+                    __syncthreads();                         // the last pass's reads are done
+                    for (int i = tid; i < NW * 256; i += BS) hist[i] = 0;
+                    __syncthreads();
+                    int pos[MAXI];
+#pragma unroll
+                    for (int i = 0; i < MAXI; ++i) {
+                        const int e = wv * CH + i * 64 + lane;
+                        const bool ok = e < n;
+                        const int d = (int)((x[i] >> sh) & 255u);
+                        uint64_t peers = __ballot(ok);
+#pragma unroll
+                        for (int b = 0; b < 8; ++b) {
+                            const bool bit = (d >> b) & 1;
+                            const uint64_t m = __ballot(bit);
+                            peers &= bit ? m : ~m;
+                        }
+                        const int below = __builtin_popcountll(peers & ((1ull << lane) - 1ull));
+                        int base = 0;
+                        if (ok) base = hist[wv * 256 + d];
+                        if (ok && below == 0) hist[wv * 256 + d] = base + __builtin_popcountll(peers);
+                        pos[i] = base + below;
+                    }
+                    __syncthreads();
+                    {
+                        int v[4], sum = 0;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int f = tid * 4 + k;
+                            v[k] = hist[(f % NW) * 256 + f / NW];
+                            sum += v[k];
+                        }
+                        long long tot;
+                        int run = (int)(block_incl_scan<BS>(sum, sm, &tot) - sum);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int f = tid * 4 + k;
+                            hist[(f % NW) * 256 + f / NW] = run;
+                            run += v[k];
+                        }
+                    }
+                    __syncthreads();
+                    unsigned* const dst = buf + half * (T / 2);
+#pragma unroll
+                    for (int i = 0; i < MAXI; ++i) {
+                        const int e = wv * CH + i * 64 + lane;
+                        if (e < n) dst[hist[wv * 256 + (int)((x[i] >> sh) & 255u)] + pos[i]] = x[i];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < MAXI; ++i) {
+                        const int e = wv * CH + i * 64 + lane;
+                        x[i] = e < n ? dst[e] : 0u;
+                    }
+                    half ^= 1;
+                }
+#pragma unroll
+                for (int i = 0; i < MAXI; ++i) {
+                    const int e = wv * CH + i * 64 + lane;
+                    if (e < n) {
+                        ccol[rp + e] = (int32_t)((x[i] >> 12) + (unsigned)mn);
+                        cval[rp + e] = (VT)vals[x[i] & 4095u];
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
         }
         // a long row: bitonic sort of P (column, slot) pairs (pads last).  The
         // pairs take the place of the keys (P <= T / 2 pairs of 8 bytes); the

@@ -572,17 +572,21 @@ def test_group_rows_sorted_across_wave(h, dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_block_rows_sorted(h, dtype):
+@pytest.mark.parametrize("n", [400_000, 2_000_000])
+def test_block_rows_sorted(h, dtype, n):
     """Rows of about 500 to 4,000 distinct outputs in the workgroup hash bins
-    (default tuning): those over 512 outputs are put in column order by the
-    bitonic sort whose short-range stages run in the waves' registers, the
-    others by the rank count; every row must match the oracle, ragged sizes
-    (not powers of two, not multiples of 128) included."""
+    (default tuning).  Those over 512 outputs are put in column order by the
+    radix sort when a row's columns span less than 2^20 (400,000 columns),
+    else by the bitonic sort whose short-range stages run in the waves'
+    registers (2,000,000 columns); every row must match the oracle, ragged
+    sizes (not powers of two, not multiples of 128) included."""
     rng = np.random.default_rng(95)
-    m, k, n = 700, 5000, 400_000
+    m, k = 700, 5000
     A = gen.erdos_renyi(m, k, rng.integers(33, 256, m), seed=96, dtype=dtype)
     B = gen.erdos_renyi(k, n, 16, seed=97, dtype=dtype)
     ref = oracle.spgemm(A, B)
     outs = np.diff(ref[0])
     assert outs.min() > 500 and outs.max() <= 4096 and (outs > 2048).sum() > 50
+    span = np.array([ref[1][ref[0][i + 1] - 1] - ref[1][ref[0][i]] for i in range(m)])
+    assert (span < (1 << 20)).all() if n < (1 << 20) else (span >= (1 << 20)).mean() > 0.9
     check_full(h, A, B)
