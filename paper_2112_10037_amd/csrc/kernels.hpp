@@ -3451,14 +3451,18 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
                 __syncthreads();
                 if (bad) break;
                 products(std::integral_constant<int, 1>{});
-                // columns in rank order, then the slice out with coalesced stores
-                for (int i = tid; i < nwd; i += BS) {
-                    unsigned long long bits = bm[i];
-                    int rk = (int)wr[i];
+                // columns in rank order (a thread per 32-bit half of a bitmap
+                // word: a dense word's bits take two lanes), then the slice out
+                // with coalesced stores
+                for (int i = tid; i < 2 * nwd; i += BS) {
+                    const unsigned long long word = bm[i >> 1];
+                    const int o = (i & 1) * 32;
+                    unsigned bits = (unsigned)(word >> o);
+                    int rk = (int)wr[i >> 1] + (o ? __builtin_popcount((unsigned)word) : 0);
                     while (bits) {
-                        const int b = __builtin_ctzll(bits);
-                        bits &= bits - 1ull;
-                        colbuf[rk++] = (int32_t)(c_lo + (long long)i * 64 + b);
+                        const int b = __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        colbuf[rk++] = (int32_t)(c_lo + (long long)i * 32 + b);
                     }
                 }
                 __syncthreads();
