@@ -3112,35 +3112,46 @@ k_num_slice(Work wk, long long ncols, long long span,
 // Global bin in column windows (rows the symbolic pass recorded)
 // ===========================================================================
 
-// Window index of B: one wave per B row.  A row with at least min_len
-// entries takes a slot and stores, for every boundary w = 0..nw, the
-// position (from the row's start) of its first entry with column >= w kWin;
-// rows without a slot get bslot = -1.  An entry with column j whose
-// predecessor has column j' is the first at or past the boundaries w with
-// j' < w kWin <= j; the boundaries past the last entry get the length.
+// Window index of B: a wave per 64 consecutive B rows.  A row with at least
+// min_len entries takes a slot (while slots last) and stores, for every
+// boundary w = 0..nw, the position (from the row's start) of its first entry
+// with column >= w kWin; rows without a slot get bslot = -1.  An entry with
+// column j whose predecessor has column j' is the first at or past the
+// boundaries w with j' < w kWin <= j; the boundaries past the last entry get
+// the length.
 static __global__ void __launch_bounds__(256)
 k_bwin_index(long long brows, const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol, int nw,
              int min_len, long long max_slots, int32_t* __restrict__ bslot, int32_t* __restrict__ wpos,
              DevInfo* info) {
     const int lane = threadIdx.x & 63;
     const long long nwave = (long long)gridDim.x * (blockDim.x >> 6);
-    for (long long k = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < brows; k += nwave) {
-        const long long s = brp[k], e = brp[k + 1];
-        int slot = -1;
-        if (e - s >= min_len) {
-            if (lane == 0) slot = atomicAdd(&info->win_nbs, 1);
-            slot = __shfl(slot, 0);
-            if (slot >= max_slots) slot = -1;           // the host sizes max_slots to cover every such row
-        }
-        if (lane == 0) bslot[k] = slot;
-        if (slot < 0) continue;
-        int32_t* wp = wpos + (long long)slot * (nw + 1);
-        for (long long p = s + lane; p < e; p += 64) {
-            const int j = bcol[p];
-            const int w_lo = p > s ? (bcol[p - 1] >> kWinLog) + 1 : 0;
-            for (int w = w_lo; w <= (j >> kWinLog); ++w) wp[w] = (int32_t)(p - s);
-            if (p == e - 1)
-                for (int w = (j >> kWinLog) + 1; w <= nw; ++w) wp[w] = (int32_t)(e - s);
+    // a wave takes 64 consecutive B rows: one atomic gives slots to all of
+    // its long enough rows, then the wave fills each one's positions
+    for (long long k0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; k0 < brows;
+         k0 += nwave * 64) {
+        const long long k = k0 + lane;
+        const bool take = k < brows && brp[k + 1] - brp[k] >= min_len;
+        const uint64_t tk = __ballot(take);
+        int base = 0;
+        if (lane == 0 && tk) base = atomicAdd(&info->win_nbs, __builtin_popcountll(tk));
+        base = __shfl(base, 0);
+        int slot = take ? base + __builtin_popcountll(tk & ((1ull << lane) - 1ull)) : -1;
+        if (slot >= max_slots) slot = -1;               // rows past the slots keep their binary searches
+        if (k < brows) bslot[k] = slot;
+        uint64_t todo = __ballot(slot >= 0);
+        while (todo) {                                  // wave-uniform
+            const int r = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const long long kr = k0 + r;
+            const long long s = brp[kr], e = brp[kr + 1];
+            int32_t* wp = wpos + (long long)__shfl(slot, r) * (nw + 1);
+            for (long long p = s + lane; p < e; p += 64) {
+                const int j = bcol[p];
+                const int w_lo = p > s ? (bcol[p - 1] >> kWinLog) + 1 : 0;
+                for (int w = w_lo; w <= (j >> kWinLog); ++w) wp[w] = (int32_t)(p - s);
+                if (p == e - 1)
+                    for (int w = (j >> kWinLog) + 1; w <= nw; ++w) wp[w] = (int32_t)(e - s);
+            }
         }
     }
 }

@@ -362,15 +362,20 @@ static msp_status launch_window_bin(msp_handle* h, Work wk, int rows, const Oper
     hipStream_t st = h->stream;
     const WinRec& rec = h->cur_rec;
     const int nw = rec.nw;
-    // every B row of at least kWinMinLen entries gets a slot
-    const long long max_slots = std::max(1LL, std::min(op.brows, op.bnnz / kWinMinLen));
+    // B rows of at least min_len entries get a slot, up to 1/64 of the
+    // device's memory (the allocation-free product, whose scratch is small,
+    // indexes only rows of 64 entries or more); rows without one find their
+    // windows by binary search
+    const int min_len = h->win_wpos.arena ? 64 : kWinMinLen;
+    const long long cap = std::max(1LL, (long long)(h->total_mem / 64) / ((long long)(nw + 1) * 4));
+    const long long max_slots = std::max(1LL, std::min({op.brows, op.bnnz / min_len, cap}));
     msp_status r;
     if ((r = h->win_bslot.ensure((size_t)std::max(op.brows, 1LL) * 4)) != MSP_OK) return r;
     if ((r = h->win_wpos.ensure((size_t)max_slots * (size_t)(nw + 1) * 4)) != MSP_OK) return r;
     if ((r = h->win_fb.ensure((size_t)std::max(rows, 1) * 4)) != MSP_OK) return r;
     if (op.brows > 0) {
-        const long long blocks = std::min<long long>((op.brows + 3) / 4, 16LL * h->num_cu);
-        k_bwin_index<<<(int)blocks, 256, 0, st>>>(op.brows, op.brp, op.bcol, nw, kWinMinLen, max_slots,
+        const long long blocks = std::min<long long>((op.brows + 255) / 256, 16LL * h->num_cu);
+        k_bwin_index<<<(int)blocks, 256, 0, st>>>(op.brows, op.brp, op.bcol, nw, min_len, max_slots,
                                                   h->win_bslot.as<int32_t>(), h->win_wpos.as<int32_t>(), info);
         if ((r = launch_check("k_bwin_index")) != MSP_OK) return r;
     }

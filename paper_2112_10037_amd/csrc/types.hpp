@@ -120,7 +120,7 @@ constexpr int kWinWords = kWin / 64;             // 64-bit bitmap words per wind
 constexpr int kWinFixed = kWinWords * (8 + 4);   // LDS bytes per window: bitmap and word ranks
 constexpr int kWinOut = 8 + 4;                   // LDS bytes per output: FP64 sum and column
 constexpr int kWinMaxNw = 512;                   // most windows per row (ncols <= 2^21)
-constexpr int kWinMinLen = 64;                   // shortest B row given a window index
+constexpr int kWinMinLen = 16;                   // shortest B row given a window index
 
 struct WinRec {
     int32_t* islot;      // per row of A: index of its record (stale values are caught by `row`)
