@@ -3293,8 +3293,9 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
                 const long long c_lo = (long long)w0 << kWinLog, c_hi = (long long)w1 << kWinLog;
                 const int nwd = (w1 - w0) * kWinWords;
                 unsigned long long* bm = dyn_win;
-                uint32_t* wr = reinterpret_cast<uint32_t*>(bm + nwd);
-                double* acc = reinterpret_cast<double*>(wr + nwd);            // nwd is even: 8-byte aligned
+                // word ranks within the slice (below 2^16: a slice holds at most budget / kWinOut outputs)
+                uint16_t* wr = reinterpret_cast<uint16_t*>(bm + nwd);
+                double* acc = reinterpret_cast<double*>(wr + nwd);            // nwd is a multiple of 64: 8-byte aligned
                 int32_t* colbuf = reinterpret_cast<int32_t*>(acc + win_acc_len(nout));
                 __syncthreads();                        // the previous slice is done with LDS
                 if (sbm) {
@@ -3453,7 +3454,7 @@ k_num_win(Work wk, int nw, const int64_t* __restrict__ arp, const int32_t* __res
                     long long tw;
                     long long run = block_incl_scan<BS>(loc, sm, &tw) - loc;
                     for (int i = i0; i < i1; ++i) {
-                        wr[i] = (uint32_t)run;
+                        wr[i] = (uint16_t)run;
                         run += __builtin_popcountll(bm[i]);
                     }
                     if (tw != nout) bad = true;         // uniform

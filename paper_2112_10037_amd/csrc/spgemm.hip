@@ -135,7 +135,8 @@ constexpr int kWinPerCU = 1;               // workgroups of k_num_win per comput
 // unit's LDS for each of its workgroups), or 0 when a window of full
 // density would not fit.
 static int win_lds(const msp_handle* h) {
-    const int dyn = h->lds_per_block / kWinPerCU - kWinReserve;
+    // (a slice then holds fewer than 2^16 outputs: its word ranks are 16-bit)
+    const int dyn = std::min(h->lds_per_block / kWinPerCU - kWinReserve, 65535 * kWinOut);
     return dyn >= kWinFixed + kWinOut * kWin + kWinSlack ? dyn : 0;
 }
 

@@ -117,7 +117,7 @@ static_assert(kNB < kPartMergeNA, "partition rows hold the bins and one spare sl
 constexpr int kWinLog = 12;
 constexpr int kWin = 1 << kWinLog;               // columns per window
 constexpr int kWinWords = kWin / 64;             // 64-bit bitmap words per window
-constexpr int kWinFixed = kWinWords * (8 + 4);   // LDS bytes per window: bitmap and word ranks
+constexpr int kWinFixed = kWinWords * (8 + 2);   // LDS bytes per window: bitmap and 16-bit word ranks
 constexpr int kWinOut = 8 + 4;                   // LDS bytes per output: FP64 sum and column
 constexpr int kWinMaxNw = 512;                   // most windows per row (ncols <= 2^21)
 constexpr int kWinMinLen = 16;                   // shortest B row given a window index
