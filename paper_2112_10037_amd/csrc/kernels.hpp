@@ -608,27 +608,43 @@ k_row_stats_long_fin(DevInfo* info, long long ncols, const int64_t* __restrict__
 // before it; inside a bin, partition p's rows follow those of partitions
 // < p, and each workgroup reserves its range from partition p's cursor.
 // part_counts are the per-partition counts of the pass that binned the
-// rows, which counted rows in workgroups of count_rows rows.
+// rows, which counted rows in workgroups of count_rows rows.  The whole
+// counter table (kParts x kPartStride) is read once per workgroup, with
+// coalesced loads, into LDS, where the bins' totals and this partition's
+// prefix are summed.
 static __global__ void __launch_bounds__(256)
 k_scatter(int m, const int32_t* __restrict__ key, BinTable bins, const int* __restrict__ part_counts,
           int count_rows, int* cursor, int32_t* __restrict__ perm) {
+    static_assert(kNB <= kPartStride && kPartStride <= 256, "a thread per bin");
+    __shared__ int tab[kParts * kPartStride];
+    __shared__ int tot[kPartStride];
+    __shared__ int pre[kPartStride];
     __shared__ int cnt[kNB];
     __shared__ int base[kNB];
     if (threadIdx.x < kNB) cnt[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < kParts * kPartStride; i += 256) tab[i] = part_counts[i];
     __syncthreads();
     const long long row = (long long)blockIdx.x * 256 + threadIdx.x;
     const int b = row < m ? bin_of(bins, key[row]) : -1;
     const int r = wave_hist_add(cnt, b);
-    __syncthreads();
     const int part = (int)(((long long)blockIdx.x * 256 / count_rows) % kParts);
+    if (threadIdx.x <= bins.nb) {
+        // bin t: its rows in every partition, and in the partitions before this one
+        const int t = threadIdx.x;
+        int all = 0, before = 0;
+        for (int p = 0; p < kParts; ++p) {
+            const int c = tab[p * kPartStride + t];
+            all += c;
+            before += p < part ? c : 0;
+        }
+        tot[t] = all;
+        pre[t] = before;
+    }
+    __syncthreads();
     if (threadIdx.x <= bins.nb && cnt[threadIdx.x]) {
         const int me = threadIdx.x;
-        int start = 0;
-        for (int p = 0; p < kParts; ++p) {
-            const int* pc = part_counts + p * kPartStride;
-            for (int i = 0; i < me; ++i) start += pc[i];
-            if (p < part) start += pc[me];
-        }
+        int start = pre[me];
+        for (int i = 0; i < me; ++i) start += tot[i];
         base[me] = start + atomicAdd(&cursor[part * kPartStride + me], cnt[me]);
     }
     __syncthreads();
@@ -725,6 +741,7 @@ k_sym_group(Work wk, int m,
             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
             int32_t* __restrict__ row_nnz, DevInfo* info, RowMap mp) {
     constexpr int NG = GroupCfg<G>::NG;
+    static_assert(T % G == 0, "the table clears in T / G whole steps of the group");
     int nrows_bin;
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
@@ -744,7 +761,7 @@ k_sym_group(Work wk, int m,
     const int row = perm ? perm[slot] : (int)slot;
     const long long bo = row_boff<BATCH>(mp, row);
 #pragma unroll
-    for (int s = gl; s < T; s += G) kt[s] = kEmpty;
+    for (int i = 0; i < T / G; ++i) kt[gl + i * G] = kEmpty;
     lds_fence();
     const long long a0 = arp[row], a1 = arp[row + 1];
     int cnt = 0;
@@ -902,7 +919,7 @@ k_sym_bitmap(Work wk, long long ncols,
                     j[u] = -1;
                     if (q < total) {
                         if (t < 0) t = owner_search(s_off, nact, q);
-                        else while ((long long)s_off[t] <= q) ++t;
+                else while ((long long)s_off[t] <= q) ++t;
                         j[u] = bcol[s_bst[t] + q];
                     }
                 }
@@ -2374,8 +2391,10 @@ __device__ __forceinline__ void wave_sort_out(const int32_t* kt, const double* v
 // Numeric, sub-wave lane groups.  T slots of (int32 key, FP64 value); a row
 // with r = row_nnz_i <= T/2 entries.  After accumulation the occupied slots
 // are compacted (group ballot) and each entry's output position is its
-// rank among the row's keys (keys are distinct), counted with 16-byte LDS
-// reads.  Per-group LDS rows are padded so groups start on different banks.
+// rank among the row's keys (keys are distinct): for a whole-wave row whose
+// columns span less than 32 T, from a bitmap of the span, else counted with
+// 16-byte LDS reads (or, past 160 entries, by a sort across the wave).
+// Per-group LDS rows are padded so groups start on different banks.
 template <int G, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_num_group(Work wk,
@@ -2387,6 +2406,7 @@ k_num_group(Work wk,
     const int32_t* perm;
     work_rows(wk, &nrows_bin, &perm);
     constexpr int NG = GroupCfg<G>::NG;
+    static_assert(T % G == 0, "the table clears in T / G whole steps of the group");
     // (rows of 16-byte multiples: the rank count reads four keys at a time;
     // the occupied slots are compacted to the front of the table in place)
     __shared__ __align__(16) int32_t keys[NG][T + 4];
@@ -2409,7 +2429,7 @@ k_num_group(Work wk,
     const long long bo = row_boff<BATCH>(mp, row);
     int re = 0;                                  // this row's table overflowed
 #pragma unroll
-    for (int s = gl; s < T; s += G) { kt[s] = kEmpty; vt[s] = 0.0; }
+    for (int i = 0; i < T / G; ++i) { kt[gl + i * G] = kEmpty; vt[gl + i * G] = 0.0; }
     lds_fence();
     const long long a0 = arp[row], a1 = arp[row + 1];
     for (long long c0 = a0; c0 < a1; c0 += G) {
@@ -2470,6 +2490,54 @@ k_num_group(Work wk,
         if (gl == 0) atomicOr(&info->err, failed ? kErrProbe : kErrCount);
         lds_fence();
         continue;
+    }
+    if constexpr (G == 64) {
+        // rows whose columns span less than 32 T: column order from a
+        // bitmap of the span (the free upper half of the value table, T / 2
+        // words) and a rank per word (the free upper half of the key
+        // table), O(n / 64 + T / 128) steps a lane instead of a sort
+        int kmn = 0x7fffffff, kmx = -1;
+        for (int e = lane; e < n; e += 64) {
+            kmn = min(kmn, kt[e]);
+            kmx = max(kmx, kt[e]);
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            kmn = min(kmn, __shfl_xor(kmn, d));
+            kmx = max(kmx, __shfl_xor(kmx, d));
+        }
+        if (n > 0 && (long long)kmx - kmn < 32LL * T) {       // wave-uniform
+            unsigned long long* bm = reinterpret_cast<unsigned long long*>(vt + T / 2);
+            int* wr = kt + T / 2;
+            const int nwd = ((kmx - kmn) >> 6) + 1;            // <= T / 2
+            for (int i = lane; i < nwd; i += 64) bm[i] = 0ull;
+            lds_fence();
+            for (int e = lane; e < n; e += 64) {
+                const int d = kt[e] - kmn;
+                atomicOr(&bm[d >> 6], 1ull << (d & 63));
+            }
+            lds_fence();
+            // lane l ranks the E consecutive words from l E
+            const int E = (nwd + 63) >> 6;
+            const int i0 = lane * E, i1 = min(i0 + E, nwd);
+            int loc = 0;
+            for (int i = i0; i < i1; ++i) loc += __builtin_popcountll(bm[i]);
+            int run = (int)group_incl_scan<64>(loc, lane) - loc;
+            for (int i = i0; i < i1; ++i) {
+                wr[i] = run;
+                run += __builtin_popcountll(bm[i]);
+            }
+            lds_fence();
+            for (int e = lane; e < n; e += 64) {
+                const int32_t k = kt[e];
+                const int d = k - kmn;
+                const int rank = wr[d >> 6] + __builtin_popcountll(bm[d >> 6] & ((1ull << (d & 63)) - 1ull));
+                ccol[rp + rank] = k;
+                cval[rp + rank] = (VT)vt[e];
+            }
+            lds_fence();
+            continue;
+        }
     }
     if constexpr (G == 64 && T / 2 > 128) {
         // long rows: a bitonic sort across the wave (the rank count below
@@ -2936,7 +3004,7 @@ k_num_slice(Work wk, long long ncols, long long span,
                         j[u] = -1;
                         if (q < total) {
                             if (t < 0) t = owner_search(s_off, nact, q);
-                            else while (s_off[t] <= q) ++t;
+                else while ((long long)s_off[t] <= q) ++t;
                             j[u] = (int32_t)(bcol[s_bst[t] + q] - C0);
                         }
                     }
@@ -3048,7 +3116,7 @@ k_num_slice(Work wk, long long ncols, long long span,
                             pv[u] = 0.0;
                             if (q < total) {
                                 if (t < 0) t = owner_search(s_off, nact, q);
-                                else while (s_off[t] <= q) ++t;
+                else while ((long long)s_off[t] <= q) ++t;
                                 const long long bi = s_bst[t] + q;
                                 j[u] = (int32_t)(bcol[bi] - c_lo);
                                 pv[u] = s_a[t] * to_f64(bval[bi]);

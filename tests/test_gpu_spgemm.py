@@ -557,10 +557,11 @@ def test_narrow_bins_concurrent(dtype):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_group_rows_sorted_across_wave(h, dtype):
-    """Rows of 100 to 256 distinct outputs in the 64-lane hash bin: those
-    over 160 outputs are put in column order by the wave's bitonic sort,
-    the others by the rank count; both must match the oracle, ragged tails
-    (outputs not a multiple of 64) included."""
+    """Rows of 100 to 256 distinct outputs in the 64-lane hash bins, whose
+    columns span more than 32 T columns (T the table size): those over 160
+    outputs are put in column order by the wave's bitonic sort, the others
+    by the rank count; both must match the oracle, ragged tails (outputs
+    not a multiple of 64) included."""
     rng = np.random.default_rng(91)
     m, k, n = 3000, 4000, 60_000
     A = gen.erdos_renyi(m, k, rng.integers(7, 17, m), seed=92, dtype=dtype)
@@ -569,6 +570,55 @@ def test_group_rows_sorted_across_wave(h, dtype):
     outs = np.diff(ref[0])
     assert outs.min() >= 100 and outs.max() <= 256 and (outs > 160).sum() > 1000
     check_full(h, A, B)
+
+
+def _span_rows(dtype, width, n_out, spans, seed):
+    """B with one row per span s in spans: columns 100 and 100 + s - 1 and
+    n_out - 2 distinct columns between them; A selects each B row alone,
+    then pairs of them (a row's span is then the wider one's)."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for s in spans:
+        mid = rng.choice(np.arange(101, 100 + s - 1), size=n_out - 2, replace=False)
+        cols.append(np.sort(np.concatenate([[100, 100 + s - 1], mid])))
+    nb = len(spans)
+    brp = np.zeros(nb + 1, dtype=np.int64)
+    brp[1:] = np.cumsum([len(c) for c in cols])
+    B = gen.CSR(nb, width, brp, np.concatenate(cols).astype(np.int32),
+                rng.uniform(-1, 1, int(brp[-1])).astype(dtype))
+    arows = [[i] for i in range(nb)] + [[i, j] for i in range(nb) for j in range(i + 1, nb)]
+    arp = np.zeros(len(arows) + 1, dtype=np.int64)
+    arp[1:] = np.cumsum([len(r) for r in arows])
+    A = gen.CSR(len(arows), nb, arp, np.concatenate(arows).astype(np.int32),
+                rng.uniform(-1, 1, int(arp[-1])).astype(dtype))
+    return A, B
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_group_rows_span_bitmap(h, dtype):
+    """Rows of the 64-lane hash bins (256 and 512 table slots, T) whose
+    columns span less than 32 T columns take their column order from a
+    bitmap of the span; wider rows from the sort or the rank count.  Banded
+    products with half-widths under and past that limit, and rows whose
+    span is one column under, at and one over it, each against the
+    oracle."""
+    for k, w, lim in ((11, 2000, 8192), (11, 2300, 8192), (16, 4000, 16384), (16, 4600, 16384)):
+        A = gen.banded_random(30_000, k, w, seed=97 + w, dtype=dtype)
+        rp, col, _, _ = oracle.spgemm(A, A)
+        outs = np.diff(rp)
+        assert outs.max() <= (128 if k == 11 else 256) and np.median(outs) > (64 if k == 11 else 128)
+        wide = (col[rp[1:] - 1] - col[rp[:-1]] + 1 >= lim).sum()
+        assert (wide == 0) if w in (2000, 4000) else (wide > 5000)
+        check_full(h, A, A)
+    # 100-output rows take the 256-slot table (span limit 8,192 columns),
+    # 200-output rows the 512-slot one (16,384); the rows of pairs of B
+    # rows share column 100 and have up to twice the outputs
+    for n_out, lim in ((100, 8192), (200, 16384)):
+        spans = [lim - 1, lim, lim + 1, lim // 2]
+        A, B = _span_rows(dtype, 40_000, n_out, spans, seed=n_out)
+        outs = np.diff(oracle.spgemm(A, B)[0])
+        assert outs[:len(spans)].min() == n_out
+        check_full(h, A, B)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
