@@ -760,15 +760,73 @@ k_sym_group(Work wk, int m,
     for (long long slot = lo + g; slot < hi; slot += NG) {      // group-uniform
     const int row = perm ? perm[slot] : (int)slot;
     const long long bo = row_boff<BATCH>(mp, row);
+    const long long a0 = arp[row], a1 = arp[row + 1];
+    // a one-chunk row's B-row position and length, loaded once for both paths
+    bool pre = false;
+    long long pre_len = 0, pre_bst = 0;
+    if constexpr (G == 64) {
+        // a whole-wave row of at most 64 A entries whose products' columns
+        // (bounded by the first and last column of each B row) span less
+        // than 32 T: its distinct columns are the bits set in a bitmap of
+        // the span, the key table's T words, with one OR per product
+        if (a1 - a0 <= 64) {                                      // wave-uniform
+            const long long p = a0 + gl;
+            long long len = 0, bst = 0;
+            int fmn = 0x7fffffff, fmx = -1;
+            if (p < a1) {
+                const long long k = acol[p] + bo;
+                bst = brp[k];
+                len = brp[k + 1] - bst;
+                if (len > 0) {
+                    fmn = bcol[bst];
+                    fmx = bcol[bst + len - 1];
+                }
+            }
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) {
+                fmn = min(fmn, __shfl_xor(fmn, d));
+                fmx = max(fmx, __shfl_xor(fmx, d));
+            }
+            if (fmx >= 0 && (long long)fmx - fmn < 32LL * T) {    // wave-uniform
+                uint32_t* bm = reinterpret_cast<uint32_t*>(kt);
+                const int nwd = ((fmx - fmn) >> 5) + 1;           // <= T
+                for (int i = gl; i < nwd; i += 64) bm[i] = 0u;
+                const long long incl = group_incl_scan<64>(len, gl);
+                const long long total = __shfl(incl, 63);
+                s_off[g][gl] = incl;
+                s_bst[g][gl] = bst - (incl - len);
+                lds_fence();
+                const int nact = (int)(a1 - a0);
+                int t = -1;
+                for (long long q = gl; q < total; q += 64) {
+                    if (t < 0) t = owner_search(s_off[g], nact, q);
+                    else while (s_off[g][t] <= q) ++t;
+                    const int d = bcol[s_bst[g][t] + q] - fmn;
+                    // (in the span for canonical B; unsorted rows, which
+                    // the input contract excludes, stay in bounds)
+                    if ((unsigned)d < (unsigned)(nwd << 5)) atomicOr(&bm[d >> 5], 1u << (d & 31));
+                }
+                lds_fence();
+                int c = 0;
+                for (int i = gl; i < nwd; i += 64) c += __builtin_popcount(bm[i]);
+                c = group_sum<64>(c);
+                if (gl == 0) row_nnz[row] = c;
+                lds_fence();
+                continue;
+            }
+            pre = true;
+            pre_len = len;
+            pre_bst = bst;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < T / G; ++i) kt[gl + i * G] = kEmpty;
     lds_fence();
-    const long long a0 = arp[row], a1 = arp[row + 1];
     int cnt = 0;
     for (long long c0 = a0; c0 < a1; c0 += G) {
         const long long p = c0 + gl;
-        long long len = 0, bst = 0;
-        if (p < a1) {
+        long long len = pre_len, bst = pre_bst;
+        if (!pre && p < a1) {
             const long long k = acol[p] + bo;
             bst = brp[k];
             len = brp[k + 1] - bst;

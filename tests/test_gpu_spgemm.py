@@ -598,9 +598,11 @@ def _span_rows(dtype, width, n_out, spans, seed):
 def test_group_rows_span_bitmap(h, dtype):
     """Rows of the 64-lane hash bins (256 and 512 table slots, T) whose
     columns span less than 32 T columns take their column order from a
-    bitmap of the span; wider rows from the sort or the rank count.  Banded
-    products with half-widths under and past that limit, and rows whose
-    span is one column under, at and one over it, each against the
+    bitmap of the span; wider rows from the sort or the rank count.  The
+    symbolic 64-lane bins count such rows (at most 64 A entries, span from
+    the B rows' first and last columns under 32 T) with a bitmap too.
+    Banded products with half-widths under and past that limit, and rows
+    whose span is one column under, at and one over it, each against the
     oracle."""
     for k, w, lim in ((11, 2000, 8192), (11, 2300, 8192), (16, 4000, 16384), (16, 4600, 16384)):
         A = gen.banded_random(30_000, k, w, seed=97 + w, dtype=dtype)
