@@ -2452,7 +2452,10 @@ __device__ __forceinline__ void wave_sort_out(const int32_t* kt, const double* v
 // rank among the row's keys (keys are distinct): for a whole-wave row whose
 // columns span less than 32 T, from a bitmap of the span, else counted with
 // 16-byte LDS reads (or, past 160 entries, by a sort across the wave).
-// Per-group LDS rows are padded so groups start on different banks.
+// Other whole-wave rows of at least 64 entries are ordered through 64
+// buckets of equal column width when no bucket holds more than kBucketMax
+// keys.  Per-group LDS rows are padded so groups start on different banks.
+constexpr int kBucketMax = 24;
 template <int G, int T, typename VT, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_num_group(Work wk,
@@ -2595,6 +2598,50 @@ k_num_group(Work wk,
             }
             lds_fence();
             continue;
+        }
+        // (the counters and slots below need T >= 256)
+        if (T >= 256 && n >= 64) {                            // wave-uniform
+            // wider rows: the keys counted into 64 buckets of equal column
+            // width, placed bucket by bucket, and each ranked by comparison
+            // within its bucket; taken while no bucket holds more than
+            // kBucketMax keys (else the sort or the rank count below)
+            int* cnt = reinterpret_cast<int*>(vt + T / 2);    // the free upper half
+            int* cur = cnt + 64;
+            int* sidx = cur + 64;                             // n <= T / 2 entries
+            int32_t* skey = kt + T / 2;                       // n <= T / 2 entries
+            const float scale = 64.0f / (float)((long long)kmx - kmn + 1);
+            auto bucket = [&](int32_t k) { return min(63, (int)((float)(k - kmn) * scale)); };
+            cnt[lane] = 0;
+            lds_fence();
+            for (int e = lane; e < n; e += 64) atomicAdd(&cnt[bucket(kt[e])], 1);
+            lds_fence();
+            const int c = cnt[lane];
+            int cmax = c;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) cmax = max(cmax, __shfl_xor(cmax, d));
+            if (cmax <= kBucketMax) {                         // wave-uniform
+                cur[lane] = (int)group_incl_scan<64>(c, lane) - c;
+                lds_fence();
+                for (int e = lane; e < n; e += 64) {
+                    const int32_t k = kt[e];
+                    const int slot = atomicAdd(&cur[bucket(k)], 1);
+                    skey[slot] = k;
+                    sidx[slot] = e;
+                }
+                lds_fence();
+                // cur[b] is now the end of bucket b
+                for (int sl = lane; sl < n; sl += 64) {
+                    const int32_t k = skey[sl];
+                    const int b = bucket(k);
+                    const int b1 = cur[b], b0 = b1 - cnt[b];
+                    int rank = b0;
+                    for (int j = b0; j < b1; ++j) rank += skey[j] < k;
+                    ccol[rp + rank] = k;
+                    cval[rp + rank] = (VT)vt[sidx[sl]];
+                }
+                lds_fence();
+                continue;
+            }
         }
     }
     if constexpr (G == 64 && T / 2 > 128) {

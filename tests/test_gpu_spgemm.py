@@ -624,6 +624,32 @@ def test_group_rows_span_bitmap(h, dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_group_rows_buckets(h, dtype):
+    """Whole-wave rows of at least 64 outputs whose columns span 64,000
+    (past the span bitmap) are ordered through 64 buckets of 1,000 columns
+    while no bucket holds more than 24 keys, else by the rank count (87-88
+    outputs) or the wave's sort (211-212 outputs).  Each B row: c0 keys in
+    the first bucket, `per` keys mid-way in each of buckets 1-62 and one in
+    the last; A selects each B row alone.  c0 = 24 and 25 on both sizes,
+    against the oracle."""
+    rng = np.random.default_rng(99)
+    cols = []
+    for per in (1, 3):
+        for c0 in (24, 25):
+            mid = [1000 * b + 500 + 7 * i for b in range(1, 63) for i in range(per)]
+            cols.append(100 + np.array(list(range(c0)) + mid + [63_999]))
+    brp = np.zeros(len(cols) + 1, dtype=np.int64)
+    brp[1:] = np.cumsum([len(c) for c in cols])
+    B = gen.CSR(len(cols), 64_200, brp, np.concatenate(cols).astype(np.int32),
+                rng.uniform(-1, 1, int(brp[-1])).astype(dtype))
+    A = gen.CSR(len(cols), len(cols), np.arange(len(cols) + 1, dtype=np.int64),
+                np.arange(len(cols), dtype=np.int32), rng.uniform(-1, 1, len(cols)).astype(dtype))
+    outs = np.diff(oracle.spgemm(A, B)[0])
+    assert list(outs) == [87, 88, 211, 212]
+    check_full(h, A, B)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n", [400_000, 2_000_000])
 def test_block_rows_sorted(h, dtype, n):
     """Rows of about 500 to 4,000 distinct outputs in the workgroup hash bins
