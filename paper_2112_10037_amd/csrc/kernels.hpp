@@ -2489,10 +2489,18 @@ k_num_group(Work wk,
     const int row = perm ? perm[slot] : (int)slot;
     const long long bo = row_boff<BATCH>(mp, row);
     int re = 0;                                  // this row's table overflowed
-#pragma unroll
-    for (int i = 0; i < T / G; ++i) { kt[gl + i * G] = kEmpty; vt[gl + i * G] = 0.0; }
-    lds_fence();
     const long long a0 = arp[row], a1 = arp[row + 1];
+    const long long rp = crp[row];
+    const int expect = (int)(crp[row + 1] - rp);
+    // a whole-wave row of one chunk with as many products as outputs has no
+    // two products in one column: they go straight to the table's first
+    // slots, without the hash and the compaction
+    bool direct = false;
+    if (a1 <= a0) {
+#pragma unroll
+        for (int i = 0; i < T / G; ++i) { kt[gl + i * G] = kEmpty; vt[gl + i * G] = 0.0; }
+        lds_fence();
+    }
     for (long long c0 = a0; c0 < a1; c0 += G) {
         const long long p = c0 + gl;
         long long len = 0, bst = 0;
@@ -2508,40 +2516,57 @@ k_num_group(Work wk,
         s_off[g][gl] = incl;
         s_bst[g][gl] = bst - (incl - len);
         s_a[g][gl] = a;
+        if (c0 == a0) {                              // group-uniform
+            direct = G == 64 && !cnt_out && a1 - a0 <= G && total == expect && total <= T / 2;
+            if (!direct) {
+#pragma unroll
+                for (int i = 0; i < T / G; ++i) { kt[gl + i * G] = kEmpty; vt[gl + i * G] = 0.0; }
+            }
+        }
         lds_fence();
         const int nact = (int)((a1 - c0) < G ? (a1 - c0) : G);
         int t = -1;                                  // owner of q: one search, then it only moves forward
-        for (long long q = gl; q < total; q += G) {
-            if (t < 0) t = owner_search(s_off[g], nact, q);
-            else while (s_off[g][t] <= q) ++t;
-            const long long bi = s_bst[g][t] + q;
-            const int32_t j = bcol[bi];
-            const double prod = s_a[g][t] * to_f64(bval[bi]);
-            const int h = hash_slot_of<T>(kt, j, &re);
-            if (h >= 0) atomicAdd(&vt[h], prod);
+        if (direct) {
+            for (long long q = gl; q < total; q += G) {
+                if (t < 0) t = owner_search(s_off[g], nact, q);
+                else while (s_off[g][t] <= q) ++t;
+                const long long bi = s_bst[g][t] + q;
+                kt[q] = bcol[bi];
+                vt[q] = 0.0 + s_a[g][t] * to_f64(bval[bi]);      // (a sum from zero, as in the table: -0 becomes +0)
+            }
+        } else {
+            for (long long q = gl; q < total; q += G) {
+                if (t < 0) t = owner_search(s_off[g], nact, q);
+                else while (s_off[g][t] <= q) ++t;
+                const long long bi = s_bst[g][t] + q;
+                const int32_t j = bcol[bi];
+                const double prod = s_a[g][t] * to_f64(bval[bi]);
+                const int h = hash_slot_of<T>(kt, j, &re);
+                if (h >= 0) atomicAdd(&vt[h], prod);
+            }
         }
         lds_fence();
     }
     // compact the occupied slots to the front, in place: a slot moves to a
     // position no later than its own, and the group reads its G slots before
     // any of them is written
-    int n = 0;
+    int n = direct ? expect : 0;
+    if (!direct) {
 #pragma unroll
-    for (int s0 = 0; s0 < T; s0 += G) {
-        const int s = s0 + gl;
-        const int32_t k = kt[s];
-        const double v = vt[s];
-        const bool occ = k != kEmpty;
-        const uint64_t mask = group_ballot<G>(occ, lane);
-        if (occ) {
-            const int pos = n + __builtin_popcountll(mask & ((1ull << gl) - 1));
-            kt[pos] = k;
-            vt[pos] = v;
+        for (int s0 = 0; s0 < T; s0 += G) {
+            const int s = s0 + gl;
+            const int32_t k = kt[s];
+            const double v = vt[s];
+            const bool occ = k != kEmpty;
+            const uint64_t mask = group_ballot<G>(occ, lane);
+            if (occ) {
+                const int pos = n + __builtin_popcountll(mask & ((1ull << gl) - 1));
+                kt[pos] = k;
+                vt[pos] = v;
+            }
+            n += __builtin_popcountll(mask);
         }
-        n += __builtin_popcountll(mask);
     }
-    const long long rp = crp[row];
-    const int expect = (int)(crp[row + 1] - rp);
     const bool failed = group_ballot<G>(re != 0, lane) != 0;
     if (cnt_out) {                               // capacity mode
         const bool fits = !failed && n <= expect && n <= T / 2;
